@@ -1,0 +1,207 @@
+/*
+ * mpr.h -- C ABI of the MI355X (gfx950) library for conditional simulation
+ * of gappy gridded data with the modified planar rotator (MPR) Gibbs random
+ * field by hybrid Monte Carlo.
+ *
+ * Paper: M. Zukovic and D. T. Hristopulos, "Gibbs Markov random fields with
+ * continuous values based on the modified planar rotator model"
+ * (arXiv 1710.03038).  Equation numbers are the paper's: (2) data -> angle
+ * map, (3) MPR energy, (4) sample specific energy, (5) equilibrium specific
+ * energy, (6) over-relaxation; Algorithm 1 is the hybrid UPDATE,
+ * Algorithm 2 the simulation driver.
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an mpr_status; nothing aborts, exits or throws
+ *    across the ABI.  On failure mpr_last_error() describes the problem.
+ *  - Device pointers are HIP device addresses owned by the caller, who
+ *    keeps them alive until mpr_destroy() or until the stream has drained.
+ *    The library never allocates device memory: all of its device state
+ *    lives in the caller's workspace (see mpr_init_field).
+ *  - All device work is ordered on the stream given to mpr_init_field.
+ *    Calls that return host values synchronise that stream.
+ *  - Validation happens before any launch; a call that fails validation
+ *    leaves the context unchanged.
+ *  - One context per stream; concurrent calls on one context are not
+ *    allowed.
+ *  - Angles: sample sites hold phi in [0, 2*pi] (Eq. 2, closed interval),
+ *    gap sites live in [0, 2*pi).  Grids are ny rows of nx sites, row
+ *    major, site (x, y) at index y*nx + x; boundaries are open (Sec. 2.2).
+ */
+#ifndef MPR_H
+#define MPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPR_OK = 0,
+  MPR_E_ARG = 1,        /* an argument value is invalid */
+  MPR_E_SHAPE = 2,      /* a grid shape is invalid */
+  MPR_E_DEGENERATE = 3, /* a grid has one distinct sample value: Eq. (2) undefined */
+  MPR_E_NOPAIRS = 4,    /* a grid has no sample-sample neighbour pair: Eq. (4) undefined */
+  MPR_E_RANGE = 5,      /* e_s outside the e(T) table: T clamped to its end */
+  MPR_E_WORKSPACE = 6,  /* workspace missing, too small or misaligned */
+  MPR_E_HIP = 7,        /* the HIP runtime reported an error */
+  MPR_E_STATE = 8       /* the context is not in a state that allows the call */
+} mpr_status;
+
+typedef enum { MPR_FP32 = 0, MPR_FP64 = 1 } mpr_dtype;
+
+/* mpr_sweep flags */
+#define MPR_ADAPT   1u /* apply the a-rule of Algorithm 2, step 4.2 */
+#define MPR_TRACE_E 2u /* record the specific energy e of Eq. (5) after every sweep */
+
+/* mpr_specific_energy selectors */
+#define MPR_SAMPLE_PAIRS 0 /* Eq. (4), one value per grid */
+#define MPR_STATE        1 /* Eq. (5) of the current state, one value per chain */
+
+typedef struct mpr_ctx mpr_ctx; /* opaque; host-side metadata only */
+
+/* One gappy grid (Sec. 2: the grid G, the samples G_s and the gaps G_p). */
+typedef struct {
+  int32_t nx, ny;        /* nx >= 1, ny >= 1, nx*ny >= 2 */
+  int32_t chains;        /* >= 1 independent Markov chains of this grid */
+  int32_t reserved;      /* must be 0 */
+  const double *z;       /* device, ny*nx values; read only at sample sites (gap values are ignored, NaN allowed) */
+  const uint8_t *known;  /* device, ny*nx; nonzero = sample site (frozen), 0 = gap.
+                            A grid without samples is an unconditional simulation (Sec. 2.4). */
+} mpr_grid;
+
+typedef struct {
+  double q;               /* modification factor of Eq. (3): 0 < q <= 0.5, or exactly 1 (planar rotator, test mode) */
+  double a_targ;          /* target acceptance A_targ of the a-rule (paper: 0.3) */
+  double k_a;             /* rate k_a of the a-rule (paper: 3) */
+  int32_t adapt_every;    /* a-rule period in sweeps, using the window's mean acceptance (paper: 1) */
+  int32_t a_sample_keep;  /* 0: a = 1 while sampling, as in Algorithm 2 step 5.2; 1: keep the adapted a */
+  int32_t dtype;          /* mpr_dtype of the sweeps' arithmetic and the stored angles */
+  int32_t sweeps_per_pass;/* sweeps fused per HBM pass, 1..16; 0 = library choice */
+  int32_t tile_x, tile_y; /* interior tile of one workgroup (even, 8..256); 0 = library choice */
+  uint64_t seed;          /* Philox4x32-10 key: (seed mod 2^32, seed >> 32) */
+} mpr_params;
+
+typedef struct {
+  int32_t records;        /* realisations recorded per chain */
+  int32_t reserved;
+  double *a_eq;           /* host [total chains] or NULL: a at the end of equilibration */
+  double *acc_eq;         /* host [total chains] or NULL: mean acceptance over the equilibration sweeps */
+  double *acc_samp;       /* host [total chains] or NULL: mean acceptance over the sampling sweeps */
+} mpr_fill_report;
+
+/* Fill *p with the paper's defaults (Sec. 2.5): q = 0.5, A_targ = 0.3,
+ * k_a = 3, adapt_every = 1, a_sample_keep = 0, FP32, library-chosen tiles,
+ * seed 0. */
+void mpr_default_params(mpr_params *p);
+
+/*
+ * Set up grids for simulation: Eq. (2) maps each grid's samples onto
+ * [0, 2*pi] with that grid's z_min, z_max; gaps are hot-started with
+ * phi = 2*pi*U (Algorithm 2, steps 1.8 and 2.1); the a of every chain is 1
+ * (step 1.10) and the sweep counter is 0.
+ *
+ * grids[n_grids]: host array of grid descriptors (device data pointers).
+ *   Total chains must not exceed 2^31 - 1.
+ * workspace: device memory, 256-byte aligned, of at least *ws_bytes bytes.
+ *   With workspace == NULL the call only writes the required size to
+ *   *ws_bytes and returns MPR_OK without creating a context.
+ * hip_stream: hipStream_t the context orders its work on (NULL = default).
+ * On success *ctx receives a new context.
+ * Errors: MPR_E_ARG (bad params, non-finite z at a sample site),
+ *   MPR_E_SHAPE, MPR_E_DEGENERATE (all samples of a grid equal; a grid with
+ *   no sample is allowed), MPR_E_WORKSPACE, MPR_E_HIP.
+ * Synchronises the stream (the per-grid z_min / z_max are validated).
+ */
+mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids, const mpr_params *p,
+                          void *workspace, size_t *ws_bytes, void *hip_stream);
+
+/*
+ * Run n_sweeps hybrid sweeps (Algorithm 1: over-relaxation then restricted
+ * Metropolis at every gap site, in checkerboard order) of every chain.
+ * T: host [n_grids], reduced temperatures; +INF (beta = 0) and 0 allowed.
+ * flags: MPR_ADAPT applies the a-rule after every adapt_every sweeps
+ *   (Algorithm 2, step 4.2) with the global sweep index as its counter;
+ *   MPR_TRACE_E evaluates e of Eq. (5) after every sweep.
+ * trace: device [n_sweeps][total chains][2] doubles or NULL; receives the
+ *   acceptance ratio A and (with MPR_TRACE_E, else NaN) e of each sweep.
+ * Asynchronous.  Errors: MPR_E_ARG, MPR_E_STATE, MPR_E_HIP.
+ */
+mpr_status mpr_sweep(mpr_ctx *ctx, int32_t n_sweeps, const double *T, uint32_t flags, double *trace);
+
+/*
+ * Specific energies of the current state.
+ * what == MPR_SAMPLE_PAIRS: e_out[n_grids] receives Eq. (4), the mean of
+ *   -cos(q dphi) over unordered sample-sample nearest-neighbour pairs, and
+ *   npairs_out[n_grids] (nullable) their count N_SP; a grid with N_SP = 0
+ *   gets NaN and the call returns MPR_E_NOPAIRS.
+ * what == MPR_STATE: e_out[total chains] receives Eq. (5), H / N_GP over all
+ *   pairs of each chain's current state; npairs_out[total chains] gets N_GP.
+ * Per-pair terms are summed as 2 sin^2(q dphi / 2) in the context's dtype
+ * within a workgroup and in FP64 across workgroups.
+ * Host outputs; synchronises the stream.
+ */
+mpr_status mpr_specific_energy(mpr_ctx *ctx, int32_t what, double *e_out, int64_t *npairs_out);
+
+/*
+ * Specific energy matching (Sec. 2.3): solve e(T) = e_s for each e_s[i] on
+ * a tabulated equilibrium curve (tab_T[k], tab_e[k]), k < n_tab.  The curve
+ * is the monotone piecewise-cubic Hermite (PCHIP, Fritsch-Carlson) fit of
+ * log(1 + e) against log T; the root is bracketed between table nodes and
+ * refined by bisection to the last bit.  Pure host FP64; no context needed.
+ * tab_T strictly increasing and > 0; tab_e non-decreasing, in (-1, 0);
+ * n_tab >= 2.  An e_s outside [tab_e[0], tab_e[n_tab-1]] is clamped to the
+ * nearer end: T_out = that end's T and item_status[i] (nullable) =
+ * MPR_E_RANGE, and the call returns MPR_E_RANGE.  NaN e_s gives NaN and
+ * MPR_E_ARG for that item.
+ */
+mpr_status mpr_match_T(const double *e_s, int32_t n, const double *tab_T, const double *tab_e, int32_t n_tab,
+                       double *T_out, mpr_status *item_status);
+
+/*
+ * Algorithm 2, steps 4-6, with fixed sweep counts: n_eq equilibration
+ * sweeps with the a-rule, then n_samp sampling sweeps (a = 1 unless
+ * a_sample_keep) of which every stride-th is recorded as a realisation;
+ * the conditional mean and standard deviation over all recorded states of
+ * all chains of a grid are mapped back with the inverse of Eq. (2).
+ * Continues from the context's current state and sweep counter.
+ * T: host [n_grids].  zhat, zstd: device [sum nx*ny] doubles, grids back to
+ * back in order (zstd nullable); sample sites get z and 0.
+ * rep: host, nullable.  Requires n_samp / stride >= 1 and every grid to have
+ * samples (else MPR_E_DEGENERATE).  Synchronises the stream.
+ */
+mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp, int32_t stride, double *zhat,
+                    double *zstd, mpr_fill_report *rep);
+
+/*
+ * Copy the angles of one chain out (mpr_get_phi) or in (mpr_set_phi), as
+ * ny*nx device doubles in natural row-major order.  mpr_set_phi writes gap
+ * sites only (sample sites keep their Eq. (2) values); gap values must lie
+ * in [0, 2*pi).  In FP32 contexts values are rounded to float and kept
+ * below 2*pi.  Asynchronous.  Errors: MPR_E_ARG.
+ */
+mpr_status mpr_get_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, double *phi);
+mpr_status mpr_set_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, const double *phi);
+
+/*
+ * The rest of a chain's state: the global sweep counter (which keys the
+ * random stream and the a-rule) and the a of every chain (host [total
+ * chains]).  With the angles this is a complete checkpoint: a run resumed
+ * from it continues bit for bit.  Synchronise the stream.
+ */
+mpr_status mpr_get_chain_state(mpr_ctx *ctx, int64_t *sweep_index, double *a);
+mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *a);
+
+/* Release a context (NULL-safe).  Does not free the workspace. */
+void mpr_destroy(mpr_ctx *ctx);
+
+/* Last error message of ctx, or of the calling thread when ctx == NULL.
+ * Never NULL; valid until the next call on the same context or thread. */
+const char *mpr_last_error(const mpr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPR_H */

@@ -1,0 +1,102 @@
+"""Equilibrium specific-energy table e(T) of the oracle (Sec. 2.3, Eq. 5).
+
+TEST INFRASTRUCTURE (part of the CPU oracle).  The table is the input of
+specific energy matching: e(T, L) = <H>/N_GP, evaluated by unconditional
+simulation, i.e. the same hybrid sweeps with an empty sample set (Sec. 2.4),
+computed once and stored (Sec. 2.3).  Running this module writes
+``oracle/etable_L32.csv`` using the oracle alone:
+
+    python -m oracle.etable
+
+Procedure (a reading: the paper gives no table domain, resolution, start or
+run lengths for this step): for every T on a log-spaced grid, ``chains``
+unconditional L x L chains start from a uniform field (cold start, which
+reaches the energy plateau fastest at low T), run ``n_eq`` sweeps with the
+a-rule from a(0) = max(1, 0.3/sqrt(T)), then ``n_meas`` sweeps at the
+adapted a, recording e after every sweep.  The table value is the mean over
+all recorded sweeps and chains; the error column is the standard error of
+the per-chain means.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+
+from . import mpr
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "etable_L32.csv")
+
+
+def default_temperatures():
+    return np.logspace(-5.0, math.log10(3.0), 46)
+
+
+def table_point(T, L=32, chains=8, n_eq=300, n_meas=900, q=0.5, seed=7, grid=0):
+    known = np.zeros((L, L), dtype=bool)
+    rng = np.random.Generator(np.random.PCG64(seed + grid))
+    phi = np.broadcast_to(rng.uniform(0, 2 * math.pi, chains)[:, None, None],
+                          (chains, L, L)).copy()
+    a0 = max(1.0, 0.3 / math.sqrt(T))
+    ids = np.arange(chains)
+    phi, a, _, _ = mpr.run_sweeps(phi, known, T, a0, q, seed, 0, n_eq, ids, grid, adapt=True)
+    _, _, _, e = mpr.run_sweeps(phi, known, T, a, q, seed, n_eq, n_meas, ids, grid,
+                                trace_energy=True)
+    per_chain = e.mean(axis=0)
+    return float(per_chain.mean()), float(per_chain.std(ddof=1) / math.sqrt(chains))
+
+
+def _point(args):
+    k, T, kw = args
+    return table_point(T, grid=k, **kw)
+
+
+def build_table(temps=None, processes=8, **kw):
+    temps = default_temperatures() if temps is None else np.asarray(temps)
+    jobs = [(k, float(T), kw) for k, T in enumerate(temps)]
+    if processes > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(processes) as pool:
+            res = pool.map(_point, jobs)
+    else:
+        res = [_point(j) for j in jobs]
+    e = np.array([r[0] for r in res])
+    err = np.array([r[1] for r in res])
+    return temps, e, err
+
+
+def save_table(path, T, e, err, header):
+    with open(path, "w") as f:
+        for line in header:
+            f.write("# " + line + "\n")
+        f.write("T,e,e_stderr\n")
+        for t, v, s in zip(T, e, err):
+            f.write(f"{t:.17g},{v:.17g},{s:.6g}\n")
+
+
+def load_table(path=DEFAULT_PATH):
+    """Return (T, e, e_stderr) arrays of a table file."""
+    rows = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or line.startswith("T,"):
+                continue
+            rows.append([float(v) for v in line.split(",")])
+    a = np.array(rows)
+    return a[:, 0], a[:, 1], a[:, 2]
+
+
+if __name__ == "__main__":
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    procs = int(sys.argv[1]) if len(sys.argv) > 1 else 8
+    kw = dict(L=32, chains=8, n_eq=300, n_meas=900, q=0.5, seed=7)
+    T, e, err = build_table(processes=procs, **kw)
+    order_ok = bool(np.all(np.diff(e) > 0))
+    save_table(DEFAULT_PATH, T, e, err, [
+        "Equilibrium MPR specific energy e(T) = <H>/N_GP, q = 1/2, open boundaries,",
+        "from unconditional CPU-oracle chains (oracle/etable.py): "
+        + ", ".join(f"{k}={v}" for k, v in kw.items()),
+        f"strictly increasing in T: {order_ok}",
+    ])
+    print("wrote", DEFAULT_PATH, "monotone:", order_ok)

@@ -1,0 +1,420 @@
+"""Plain FP64 CPU oracle of the MPR hybrid Monte Carlo gap-filling method.
+
+TEST INFRASTRUCTURE.  This module is the checker for the GPU library: only
+tests, the smoke check and the benchmark's CPU-baseline leg may import it.
+It shares no code with the HIP library and is slow on purpose: every step is
+written out in the order the paper gives it, vectorised over whole
+half-lattices and over independent chains with NumPy, in float64.
+
+Paper: Zukovic & Hristopulos, "Gibbs Markov random fields with continuous
+values based on the modified planar rotator model" (arXiv 1710.03038).
+Equation numbers follow the paper: (2) data -> angle map, (3) MPR energy,
+(4) sample specific energy, (5) equilibrium specific energy, (6) over-
+relaxation; Algorithm 1 is the hybrid UPDATE, Algorithm 2 the simulation
+driver.
+
+Readings of points the paper leaves open (each also used by the library):
+
+* Over-relaxation (Eq. 6) is printed with the q = 1 molecular field.  For
+  q = 1/2 that map does not conserve the energy, although the text says it
+  does.  We reflect q*phi about Psi = atan2(sum sin q*phi_j, sum cos q*phi_j):
+  phi* = (2 Psi - q phi)/q, which conserves Eq. (3) exactly.  Because the
+  energy is not 2*pi-periodic for q < 1, phi* is used only when it lies in
+  [0, 2*pi); otherwise the site keeps phi.  For q = 1 the result is wrapped
+  mod 2*pi.  With |h| = 0 the move is the identity.
+* Restricted Metropolis proposals are wrapped into [0, 2*pi) and the energy
+  change is evaluated at the wrapped angle (Algorithm 1, step 3).
+* A proposal is accepted iff dH <= 0 or r < exp(-dH/T); r, u are
+  (w >> 8) * 2^-24 for Philox words w (Algorithm 1, steps 2, 5, 6).
+* The sweep is a checkerboard: all gap sites with (x + y) even, then all
+  with (x + y) odd (Sec. 5.2).  Open boundaries: in-grid neighbours only.
+* Eq. (4) averages over unordered sample-sample neighbour pairs, the same
+  normalisation as Eq. (5).
+* The a-rule (Algorithm 2, step 4.2) is applied after every
+  ``adapt_every``-th equilibration sweep using the mean acceptance over that
+  window (1 = every sweep, as printed); a is reset to 1 for sampling
+  (Algorithm 2, step 5.2) unless ``a_sample_keep``.
+* The fill records every ``stride``-th sampling sweep; the prediction is the
+  arithmetic mean in angle space mapped back by the inverse of Eq. (2).
+
+Random stream (a definition of this project): key = (seed mod 2^32,
+seed >> 32); counter = (pair, sweep, chain, grid) with
+pair = y * ceil(nx/2) + x//2.  A site with even x uses words (w0 -> u,
+w1 -> r), odd x uses (w2 -> u, w3 -> r).  The hot start uses
+sweep = 0xFFFFFFFF and the u word only.
+"""
+import math
+
+import numpy as np
+
+from .philox import philox4x32, unit_float
+
+TWO_PI = 2.0 * math.pi
+HOT_START_SWEEP = 0xFFFFFFFF
+
+
+class OracleError(ValueError):
+    """Raised for inputs the method cannot process (no samples, no pairs)."""
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def split_seed(seed):
+    seed = int(seed)
+    return seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+
+
+def site_uniforms(seed, ny, nx, sweep, chains, grid):
+    """Uniforms (u, r) of every site for one sweep; arrays (C, ny, nx)."""
+    k0, k1 = split_seed(seed)
+    chains = np.asarray(chains, dtype=np.uint64).reshape(-1, 1, 1)
+    y = np.arange(ny, dtype=np.uint64).reshape(1, ny, 1)
+    x = np.arange(nx, dtype=np.uint64).reshape(1, 1, nx)
+    npair = (nx + 1) // 2
+    pair = y * np.uint64(npair) + x // np.uint64(2)
+    w0, w1, w2, w3 = philox4x32(pair, sweep, chains, grid, k0, k1)
+    even = (x % np.uint64(2)) == 0
+    u = np.where(even, w0, w2)
+    r = np.where(even, w1, w3)
+    return unit_float(u), unit_float(r)
+
+
+# --------------------------------------------------------------------------
+# Data transform, Eq. (2), and its inverse (Algorithm 2, step 5.3)
+# --------------------------------------------------------------------------
+def transform(z, known):
+    """Map sample values linearly onto [0, 2*pi]; gaps are set to 0.
+
+    Returns (phi, z_min, z_max) with z_min, z_max taken over the samples.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    known = np.asarray(known, dtype=bool)
+    if not known.any():
+        raise OracleError("no sample sites")
+    zs = z[known]
+    if not np.all(np.isfinite(zs)):
+        raise OracleError("non-finite sample value")
+    zmin, zmax = zs.min(), zs.max()
+    if zmax == zmin:
+        raise OracleError("z_max == z_min")
+    phi = np.zeros(z.shape, dtype=np.float64)
+    phi[known] = (zs - zmin) / (zmax - zmin) * TWO_PI
+    return phi, float(zmin), float(zmax)
+
+
+def inverse_transform(phi, zmin, zmax):
+    return zmin + (zmax - zmin) * (np.asarray(phi, dtype=np.float64) / TWO_PI)
+
+
+def hot_start(phi_s, known, seed, chains, grid):
+    """Paramagnetic start: every gap gets 2*pi*U (Algorithm 2, step 1.8)."""
+    ny, nx = phi_s.shape
+    chains = np.atleast_1d(np.asarray(chains))
+    u, _ = site_uniforms(seed, ny, nx, HOT_START_SWEEP, chains, grid)
+    phi = np.where(known[None], phi_s[None], TWO_PI * u)
+    return phi
+
+
+# --------------------------------------------------------------------------
+# Energies, Eqs. (3)-(5)
+# --------------------------------------------------------------------------
+def _pairs(a):
+    """The two members of every horizontal and vertical nearest-neighbour pair."""
+    return ((a[..., :, :-1], a[..., :, 1:]), (a[..., :-1, :], a[..., 1:, :]))
+
+
+def energy(phi, q):
+    """Eq. (3) with J = 1: H = -sum over pairs cos(q (phi_i - phi_j))."""
+    tot = 0.0
+    for a, b in _pairs(np.asarray(phi, dtype=np.float64)):
+        tot = tot - np.cos(q * (a - b)).sum(axis=(-2, -1))
+    return tot
+
+
+def n_pairs(ny, nx):
+    """N_GP: nearest-neighbour pairs of an ny x nx grid, open boundaries."""
+    return ny * (nx - 1) + nx * (ny - 1)
+
+
+def state_specific_energy(phi, q):
+    """Eq. (5) for one state: e = H / N_GP.  Returns (e, eps) with eps = 1 + e.
+
+    eps is summed as 2 sin^2(q dphi / 2) (equal to 1 - cos(q dphi)), which
+    keeps its relative precision when the field is nearly uniform.
+    """
+    phi = np.asarray(phi, dtype=np.float64)
+    ny, nx = phi.shape[-2:]
+    s = 0.0
+    for a, b in _pairs(phi):
+        s = s + (2.0 * np.sin(0.5 * q * (a - b)) ** 2).sum(axis=(-2, -1))
+    eps = s / n_pairs(ny, nx)
+    return eps - 1.0, eps
+
+
+def sample_specific_energy(phi, known, q):
+    """Eq. (4): mean of -cos(q dphi) over unordered sample-sample pairs.
+
+    Returns (e_s, eps_s, N_SP).  Raises OracleError when N_SP = 0.
+    """
+    phi = np.asarray(phi, dtype=np.float64)
+    known = np.asarray(known, dtype=bool)
+    s = 0.0
+    n = 0
+    for (a, b), (ka, kb) in zip(_pairs(phi), _pairs(known)):
+        both = ka & kb
+        s += (2.0 * np.sin(0.5 * q * (a[both] - b[both])) ** 2).sum()
+        n += int(both.sum())
+    if n == 0:
+        raise OracleError("no sample-sample pairs")
+    eps = s / n
+    return eps - 1.0, eps, n
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 (hybrid UPDATE), checkerboard order
+# --------------------------------------------------------------------------
+def wrap(x):
+    """Angle into [0, 2*pi): x - 2*pi*floor(x / 2*pi), with the rounding
+    cases folded back (a result of exactly 2*pi becomes 0)."""
+    y = x - TWO_PI * np.floor(x / TWO_PI)
+    y = np.where(y < 0.0, y + TWO_PI, y)
+    return np.where(y >= TWO_PI, 0.0, y)
+
+
+def _neighbours(phi):
+    """Angles of the four neighbours of every site, NaN where off the grid."""
+    ny, nx = phi.shape[-2:]
+    pad = np.full(phi.shape[:-2] + (ny + 2, nx + 2), np.nan)
+    pad[..., 1:-1, 1:-1] = phi
+    return [pad[..., 1:-1, :-2], pad[..., 1:-1, 2:], pad[..., :-2, 1:-1], pad[..., 2:, 1:-1]]
+
+
+def over_relax(phi, nbrs, q):
+    """Energy-conserving reflection of each spin about its local field, Eq. (6)
+    in the q-aware reading.  ``nbrs`` are the neighbour angles (NaN = none)."""
+    hx = sum(np.where(np.isnan(n), 0.0, np.cos(q * np.nan_to_num(n))) for n in nbrs)
+    hy = sum(np.where(np.isnan(n), 0.0, np.sin(q * np.nan_to_num(n))) for n in nbrs)
+    psi = np.arctan2(hy, hx)
+    star = (2.0 * psi - q * phi) / q
+    if q == 1.0:
+        out = wrap(star)
+    else:
+        out = np.where((star >= 0.0) & (star < TWO_PI), star, phi)
+    return np.where(hx * hx + hy * hy <= 1e-24, phi, out)
+
+
+def site_energy(phi, nbrs, q):
+    """Energy of the bonds of one site: -sum_j cos(q (phi - phi_j))."""
+    return -sum(np.where(np.isnan(n), 0.0, np.cos(q * (phi - np.nan_to_num(n)))) for n in nbrs)
+
+
+def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid):
+    """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
+
+    phi: (C, ny, nx) float64 current states (not modified).
+    known: (ny, nx) bool, True at frozen sample sites.
+    beta: (C,) inverse temperatures 1/T (0 and inf allowed).
+    alpha: (C,) proposal widths 2*pi/a.
+    Returns (new phi, accepted count per chain).
+    """
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    C, ny, nx = phi.shape
+    beta = np.broadcast_to(np.asarray(beta, dtype=np.float64), (C,)).reshape(C, 1, 1)
+    alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (C,)).reshape(C, 1, 1)
+    u, r = site_uniforms(seed, ny, nx, sweep, chains, grid)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    accepted = np.zeros(C, dtype=np.int64)
+    for colour in (0, 1):
+        update = (((xx + yy) % 2) == colour) & ~known
+        nbrs = _neighbours(phi)
+        phi1 = over_relax(phi, nbrs, q)                      # step 1
+        phi2 = wrap(phi1 + alpha * (u - 0.5))                # steps 2-3
+        dH = site_energy(phi2, nbrs, q) - site_energy(phi1, nbrs, q)   # step 4
+        with np.errstate(invalid="ignore", over="ignore"):
+            boltz = np.exp(-beta * dH)                       # step 5
+        accept = (dH <= 0.0) | (r < boltz)                   # step 6
+        new = np.where(accept, phi2, phi1)
+        phi = np.where(update[None], new, phi)
+        accepted += (update[None] & accept).sum(axis=(1, 2))
+    return phi, accepted
+
+
+def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid):
+    """Algorithm 1 for one chain as a plain per-site loop (small grids only).
+
+    Same checkerboard order and random stream as ``hybrid_sweep``; written
+    with scalar ``math`` calls so the two can be checked against each other.
+    """
+    phi = [list(map(float, row)) for row in np.asarray(phi, dtype=np.float64)]
+    ny, nx = len(phi), len(phi[0])
+    k0, k1 = split_seed(seed)
+    npair = (nx + 1) // 2
+    accepted = 0
+    for colour in (0, 1):
+        for y in range(ny):
+            for x in range(nx):
+                if (x + y) % 2 != colour or known[y][x]:
+                    continue
+                w = philox4x32(y * npair + x // 2, sweep, chain, grid, k0, k1)
+                wu, wr = (w[0], w[1]) if x % 2 == 0 else (w[2], w[3])
+                u = float(unit_float(wu))
+                r = float(unit_float(wr))
+                nb = [phi[yy][xx] for yy, xx in ((y, x - 1), (y, x + 1), (y - 1, x), (y + 1, x))
+                      if 0 <= yy < ny and 0 <= xx < nx]
+                cur = phi[y][x]
+                hx = sum(math.cos(q * v) for v in nb)
+                hy = sum(math.sin(q * v) for v in nb)
+                if hx * hx + hy * hy <= 1e-24:
+                    p1 = cur
+                else:
+                    star = (2.0 * math.atan2(hy, hx) - q * cur) / q
+                    if q == 1.0:
+                        p1 = float(wrap(np.float64(star)))
+                    else:
+                        p1 = star if 0.0 <= star < TWO_PI else cur
+                p2 = float(wrap(np.float64(p1 + alpha * (u - 0.5))))
+                dH = -sum(math.cos(q * (p2 - v)) - math.cos(q * (p1 - v)) for v in nb)
+                if dH <= 0.0:
+                    ok = True
+                elif beta == math.inf:
+                    ok = False
+                else:
+                    ok = r < math.exp(-beta * dH)
+                phi[y][x] = p2 if ok else p1
+                accepted += int(ok)
+    return np.array(phi), accepted
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2: the a-rule and the fill driver (fixed sweep counts)
+# --------------------------------------------------------------------------
+def adapt_a(a, acceptance, i, a_targ=0.3, k_a=3.0):
+    """Algorithm 2, step 4.2: after sweep i (0-based) with acceptance A,
+    a(i+1) = 1 + (i+1)/k_a if A < A_targ, else a(i+1) = a(i)."""
+    return np.where(np.asarray(acceptance) < a_targ, 1.0 + (i + 1) / k_a, a)
+
+
+def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
+               adapt=False, adapt_every=1, a_targ=0.3, k_a=3.0, trace_energy=False):
+    """Advance C chains of one grid by ``n_sweeps`` hybrid sweeps.
+
+    Returns (phi, a, acceptance per sweep (n, C), specific energy per sweep
+    (n, C) or None).  With ``adapt`` the a-rule is applied every
+    ``adapt_every`` sweeps using the mean acceptance of that window; the
+    rule's counter i is the global sweep index.
+    """
+    C = phi.shape[0]
+    T = np.broadcast_to(np.asarray(T, dtype=np.float64), (C,))
+    with np.errstate(divide="ignore"):
+        beta = np.where(np.isinf(T), 0.0, 1.0 / T)
+    a = np.array(np.broadcast_to(np.asarray(a, dtype=np.float64), (C,)), copy=True)
+    n_gap = int((~np.asarray(known, dtype=bool)).sum())
+    acc_trace = np.zeros((n_sweeps, C))
+    e_trace = np.zeros((n_sweeps, C)) if trace_energy else None
+    window = np.zeros(C)
+    for s in range(n_sweeps):
+        i = first_sweep + s
+        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid)
+        A = acc / n_gap if n_gap > 0 else np.ones(C)
+        acc_trace[s] = A
+        if trace_energy:
+            e_trace[s] = state_specific_energy(phi, q)[0]
+        if adapt:
+            window += A
+            if (i + 1) % adapt_every == 0:
+                a = adapt_a(a, window / adapt_every, i, a_targ, k_a)
+                window[:] = 0.0
+    return phi, a, acc_trace, e_trace
+
+
+def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
+         a_targ=0.3, k_a=3.0, adapt_every=1, a_sample_keep=False):
+    """Algorithm 2 with fixed sweep counts (no Savitzky-Golay stop).
+
+    Hot start, ``n_eq`` equilibration sweeps with the a-rule, then
+    ``n_samp`` sampling sweeps of which every ``stride``-th is recorded, for
+    each of ``chains`` independent chains.  Returns a dict with z_hat (the
+    conditional mean mapped back, samples copied through), z_std, the
+    recorded count and the per-sweep acceptance trace.
+    """
+    known = np.asarray(known, dtype=bool)
+    phi_s, zmin, zmax = transform(z, known)
+    chain_ids = np.arange(chains)
+    phi = hot_start(phi_s, known, seed, chain_ids, grid)
+    a = np.ones(chains)
+    phi, a, acc_eq, _ = run_sweeps(phi, known, T, a, q, seed, 0, n_eq, chain_ids, grid,
+                                   adapt=True, adapt_every=adapt_every, a_targ=a_targ, k_a=k_a)
+    a_eq = a.copy()
+    if not a_sample_keep:
+        a = np.ones(chains)
+    s1 = np.zeros(known.shape)
+    s2 = np.zeros(known.shape)
+    m = 0
+    acc_samp = []
+    for j in range(n_samp):
+        phi, a, acc, _ = run_sweeps(phi, known, T, a, q, seed, n_eq + j, 1, chain_ids, grid)
+        acc_samp.append(acc[0])
+        if (j + 1) % stride == 0:
+            s1 += phi.sum(axis=0)
+            s2 += (phi * phi).sum(axis=0)
+            m += chains
+    if m == 0:
+        raise OracleError("no recorded realisation")
+    mean = s1 / m
+    var = np.maximum(s2 / m - mean * mean, 0.0)
+    z_hat = np.where(known, np.asarray(z, dtype=np.float64), inverse_transform(mean, zmin, zmax))
+    z_std = np.where(known, 0.0, (zmax - zmin) / TWO_PI * np.sqrt(var))
+    return dict(z_hat=z_hat, z_std=z_std, records=m, zmin=zmin, zmax=zmax, a_eq=a_eq,
+                acc_eq=acc_eq, acc_samp=np.array(acc_samp), phi=phi)
+
+
+# --------------------------------------------------------------------------
+# Specific energy matching (Sec. 2.3)
+# --------------------------------------------------------------------------
+RANGE_CLAMPED = 1
+
+
+def match_T(e_s, tab_T, tab_e):
+    """Solve e(T) = e_s on a tabulated equilibrium curve (Sec. 2.3).
+
+    The curve is interpolated monotonically (PCHIP) in (log T, log(1 + e)),
+    and the root is found by Brent's method to 1e-14 relative.  Values
+    outside the table are clamped to its ends and flagged RANGE_CLAMPED.
+    Returns (T_hat array, status array).
+    """
+    from scipy.interpolate import PchipInterpolator
+    from scipy.optimize import brentq
+
+    tab_T = np.asarray(tab_T, dtype=np.float64)
+    tab_e = np.asarray(tab_e, dtype=np.float64)
+    lt = np.log(tab_T)
+    le = np.log1p(tab_e)
+    curve = PchipInterpolator(lt, le)
+    e_s = np.atleast_1d(np.asarray(e_s, dtype=np.float64))
+    T_out = np.empty_like(e_s)
+    status = np.zeros(e_s.shape, dtype=np.int32)
+    for k, e in enumerate(e_s):
+        if e <= tab_e[0]:
+            T_out[k] = tab_T[0]
+            status[k] = RANGE_CLAMPED if e < tab_e[0] else 0
+            continue
+        if e >= tab_e[-1]:
+            T_out[k] = tab_T[-1]
+            status[k] = RANGE_CLAMPED if e > tab_e[-1] else 0
+            continue
+        target = math.log1p(e)
+        j = int(np.searchsorted(tab_e, e, side="right")) - 1
+        if tab_e[j] == e:
+            T_out[k] = tab_T[j]
+            continue
+        root = brentq(lambda x: float(curve(x)) - target, lt[j], lt[j + 1],
+                      xtol=1e-15, rtol=1e-15, maxiter=200)
+        T_out[k] = math.exp(root)
+    return T_out, status
+
+
+def mae(z_true, z_hat, gaps):
+    """Average absolute error over the prediction sites (Sec. 3, AAE)."""
+    gaps = np.asarray(gaps, dtype=bool)
+    return float(np.abs(np.asarray(z_true)[gaps] - np.asarray(z_hat)[gaps]).mean())
