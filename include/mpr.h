@@ -193,6 +193,17 @@ mpr_status mpr_set_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, const double *
 mpr_status mpr_get_chain_state(mpr_ctx *ctx, int64_t *sweep_index, double *a);
 mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *a);
 
+/*
+ * Kernel timing, for measurement.  With enable != 0 every later launch of
+ * the sweep kernel is bracketed by two HIP events on the context's stream;
+ * mpr_get_timing synchronises the stream and returns the summed
+ * milliseconds between those event pairs, the number of launches and the
+ * site-sweeps they processed (lattice sites times sweeps, summed over
+ * chains), then resets the sums.  enable == 0 stops recording.
+ */
+mpr_status mpr_set_timing(mpr_ctx *ctx, int32_t enable);
+mpr_status mpr_get_timing(mpr_ctx *ctx, double *sweep_ms, int64_t *launches, int64_t *site_sweeps);
+
 /* Release a context (NULL-safe).  Does not free the workspace. */
 void mpr_destroy(mpr_ctx *ctx);
 

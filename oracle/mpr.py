@@ -209,13 +209,19 @@ def site_energy(phi, nbrs, q):
     return -sum(np.where(np.isnan(n), 0.0, np.cos(q * (phi - np.nan_to_num(n)))) for n in nbrs)
 
 
-def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid):
+def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None):
     """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
 
     phi: (C, ny, nx) float64 current states (not modified).
     known: (ny, nx) bool, True at frozen sample sites.
     beta: (C,) inverse temperatures 1/T (0 and inf allowed).
     alpha: (C,) proposal widths 2*pi/a.
+    margins: optional dict, filled with per-site distances of this sweep's
+      discrete decisions from their thresholds (for judging rounding flips
+      of another implementation): "accept" = |r - min(1, exp(-dH/T))|,
+      "or_edge" = distance of the reflected angle from 0 and 2*pi, "wrap" =
+      distance of the unwrapped proposal from 0 and 2*pi.  inf at sites not
+      updated.
     Returns (new phi, accepted count per chain).
     """
     phi = np.array(phi, dtype=np.float64, copy=True)
@@ -225,6 +231,9 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid):
     u, r = site_uniforms(seed, ny, nx, sweep, chains, grid)
     yy, xx = np.mgrid[0:ny, 0:nx]
     accepted = np.zeros(C, dtype=np.int64)
+    if margins is not None:
+        for k in ("accept", "or_edge", "wrap"):
+            margins[k] = np.full(phi.shape, np.inf)
     for colour in (0, 1):
         update = (((xx + yy) % 2) == colour) & ~known
         nbrs = _neighbours(phi)
@@ -234,6 +243,16 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid):
         with np.errstate(invalid="ignore", over="ignore"):
             boltz = np.exp(-beta * dH)                       # step 5
         accept = (dH <= 0.0) | (r < boltz)                   # step 6
+        if margins is not None:
+            sel = np.broadcast_to(update[None], phi.shape)
+            ap = np.where(dH <= 0.0, 1.0, np.nan_to_num(boltz))
+            hx = sum(np.where(np.isnan(n), 0.0, np.cos(q * np.nan_to_num(n))) for n in nbrs)
+            hy = sum(np.where(np.isnan(n), 0.0, np.sin(q * np.nan_to_num(n))) for n in nbrs)
+            star = (2.0 * np.arctan2(hy, hx) - q * phi) / q
+            raw = phi1 + alpha * (u - 0.5)
+            margins["accept"] = np.where(sel, np.abs(r - ap), margins["accept"])
+            margins["or_edge"] = np.where(sel, np.minimum(np.abs(star), np.abs(star - TWO_PI)), margins["or_edge"])
+            margins["wrap"] = np.where(sel, np.minimum(np.abs(raw), np.abs(raw - TWO_PI)), margins["wrap"])
         new = np.where(accept, phi2, phi1)
         phi = np.where(update[None], new, phi)
         accepted += (update[None] & accept).sum(axis=(1, 2))

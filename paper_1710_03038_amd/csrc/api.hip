@@ -1,0 +1,785 @@
+// Host side of libmpr: the C ABI declared in include/mpr.h.
+//
+// The library owns no device memory.  mpr_init_field carves every device
+// array it needs out of the caller's workspace; the context holds only
+// host metadata and views into that workspace.  All work is ordered on the
+// caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "mpr.h"
+
+using namespace mpr;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+struct Views {
+  GridDesc *gd = nullptr;
+  const double **zp = nullptr;
+  const uint8_t **kp = nullptr;
+  void *st[2] = {nullptr, nullptr};
+  void *acc_ref = nullptr, *acc_s1 = nullptr, *acc_s2 = nullptr;
+  double *a = nullptr, *alpha = nullptr, *beta = nullptr, *window = nullptr, *accsum = nullptr;
+  uint32_t *counts = nullptr;
+  double *energy = nullptr;
+  double *part = nullptr, *out = nullptr;
+};
+
+struct Plan {
+  std::vector<GridDesc> gd;
+  int total_chains = 0;
+  int64_t n_items = 0, n_cblocks = 0, n_sblocks = 0, state_elems = 0, sites = 0;
+  int tile_x = 0, tile_y = 0;
+  size_t elem = 0;
+  size_t bytes = 0;
+  Views v;  // offsets from the workspace base until bound
+};
+
+}  // namespace
+
+struct mpr_ctx {
+  hipStream_t stream = nullptr;
+  mpr_params p{};
+  int n_grids = 0;
+  Plan plan;
+  Views v;
+  int cur = 0;                 // index of the state buffer holding the current angles
+  int64_t sweep_index = 0;     // global sweep counter (keys the random stream)
+  int nsw_max = 1;
+  size_t lds_limit = 65536;
+  std::vector<double> beta_h;  // staging for per-chain inverse temperatures
+  std::string err;
+  // kernel timing (mpr_set_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop) of pending launches
+  size_t ev_used = 0;
+  double t_ms = 0.0;
+  int64_t t_launches = 0, t_site_sweeps = 0;
+  int64_t sites_all_chains = 0;
+  ~mpr_ctx() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+mpr_status fail(mpr_ctx *c, mpr_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_thread_err = msg;
+  return st;
+}
+
+mpr_status hip_fail(mpr_ctx *c, hipError_t e, const char *where) {
+  return fail(c, MPR_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                  \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);  \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+mpr_status check_params(const mpr_params *p) {
+  if (!p) return fail(nullptr, MPR_E_ARG, "params is NULL");
+  if (!(p->q > 0.0 && p->q <= 0.5) && p->q != 1.0)
+    return fail(nullptr, MPR_E_ARG, "q must lie in (0, 0.5] or equal 1");
+  if (!(p->a_targ >= 0.0 && p->a_targ <= 1.0)) return fail(nullptr, MPR_E_ARG, "a_targ must lie in [0, 1]");
+  if (!(p->k_a > 0.0) || !std::isfinite(p->k_a)) return fail(nullptr, MPR_E_ARG, "k_a must be positive");
+  if (p->adapt_every < 1) return fail(nullptr, MPR_E_ARG, "adapt_every must be >= 1");
+  if (p->a_sample_keep != 0 && p->a_sample_keep != 1) return fail(nullptr, MPR_E_ARG, "a_sample_keep must be 0 or 1");
+  if (p->dtype != MPR_FP32 && p->dtype != MPR_FP64) return fail(nullptr, MPR_E_ARG, "dtype must be MPR_FP32 or MPR_FP64");
+  if (p->sweeps_per_pass < 0 || p->sweeps_per_pass > kMaxPass)
+    return fail(nullptr, MPR_E_ARG, "sweeps_per_pass must lie in [0, 16]");
+  for (int t : {p->tile_x, p->tile_y})
+    if (t != 0 && (t < 8 || t > 256 || (t & 1)))
+      return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 256]");
+  return MPR_OK;
+}
+
+// Lay out the grids and the workspace.  Offsets are relative to the base.
+mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool need_ptrs, Plan &pl) {
+  if (!grids || n < 1) return fail(nullptr, MPR_E_ARG, "need at least one grid");
+  pl = Plan();
+  pl.elem = p->dtype == MPR_FP64 ? 8 : 4;
+  pl.tile_x = p->tile_x ? p->tile_x : (p->dtype == MPR_FP64 ? 32 : 64);
+  pl.tile_y = p->tile_y ? p->tile_y : (p->dtype == MPR_FP64 ? 32 : 64);
+  int64_t chains = 0;
+  for (int g = 0; g < n; ++g) {
+    const mpr_grid &G = grids[g];
+    if (G.nx < 1 || G.ny < 1 || (int64_t)G.nx * G.ny < 2 || G.nx > 65536 || G.ny > 65536)
+      return fail(nullptr, MPR_E_SHAPE, "grid " + std::to_string(g) + ": need 1 <= nx, ny <= 65536 and nx*ny >= 2");
+    if (G.chains < 1) return fail(nullptr, MPR_E_SHAPE, "grid " + std::to_string(g) + ": chains must be >= 1");
+    if (G.reserved != 0) return fail(nullptr, MPR_E_ARG, "grid " + std::to_string(g) + ": reserved must be 0");
+    if (need_ptrs && (!G.z || !G.known))
+      return fail(nullptr, MPR_E_ARG, "grid " + std::to_string(g) + ": z and known must be device pointers");
+    GridDesc d{};
+    d.nx = G.nx;
+    d.ny = G.ny;
+    d.chains = G.chains;
+    d.npair = (G.nx + 1) / 2;
+    d.tiles_x = (G.nx + pl.tile_x - 1) / pl.tile_x;
+    d.tiles_y = (G.ny + pl.tile_y - 1) / pl.tile_y;
+    d.chain_base = (int32_t)chains;
+    d.grid_id = g;
+    const int64_t sites = (int64_t)G.nx * G.ny;
+    const int64_t per_chain_blocks = (sites + kChunk - 1) / kChunk;
+    d.item_begin = pl.n_items;
+    d.cb_begin = pl.n_cblocks;
+    d.sb_begin = pl.n_sblocks;
+    d.state_off = pl.state_elems;
+    d.site_off = pl.sites;
+    d.n_pairs = (int64_t)G.ny * (G.nx - 1) + (int64_t)G.nx * (G.ny - 1);
+    d.zmin = d.zmax = NAN;
+    pl.n_items += (int64_t)G.chains * d.tiles_x * d.tiles_y;
+    pl.n_cblocks += (int64_t)G.chains * per_chain_blocks;
+    pl.n_sblocks += per_chain_blocks;
+    pl.state_elems += (int64_t)G.chains * sites;
+    pl.sites += sites;
+    chains += G.chains;
+    if (chains > 0x7fffffff) return fail(nullptr, MPR_E_SHAPE, "more than 2^31 - 1 chains in total");
+    pl.gd.push_back(d);
+  }
+  if (pl.n_items > 0x7fffffff || pl.n_cblocks > 0x7fffffff)
+    return fail(nullptr, MPR_E_SHAPE, "batch too large for one launch");
+  pl.total_chains = (int)chains;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  Views &v = pl.v;
+  const size_t C = (size_t)pl.total_chains;
+  v.gd = (GridDesc *)take(sizeof(GridDesc) * n);
+  v.zp = (const double **)take(sizeof(void *) * n);
+  v.kp = (const uint8_t **)take(sizeof(void *) * n);
+  v.st[0] = (void *)take(pl.elem * pl.state_elems);
+  v.st[1] = (void *)take(pl.elem * pl.state_elems);
+  v.acc_ref = (void *)take(pl.elem * pl.state_elems);
+  v.acc_s1 = (void *)take(pl.elem * pl.state_elems);
+  v.acc_s2 = (void *)take(pl.elem * pl.state_elems);
+  v.a = (double *)take(8 * C);
+  v.alpha = (double *)take(8 * C);
+  v.beta = (double *)take(8 * C);
+  v.window = (double *)take(8 * C);
+  v.accsum = (double *)take(8 * C);
+  v.counts = (uint32_t *)take(4 * C * kMaxPass);
+  v.energy = (double *)take(8 * C * kMaxPass);
+  v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * 4, pl.n_cblocks * 2));
+  v.out = (double *)take(8 * std::max<size_t>((size_t)n * 4, C * 2));
+  pl.bytes = off;
+  return MPR_OK;
+}
+
+template <typename T> T *rebase(T *off, char *base) { return (T *)(base + (size_t)off); }
+
+void bind(Views &v, const Views &o, void *ws) {
+  char *b = (char *)ws;
+  v.gd = rebase(o.gd, b);
+  v.zp = rebase(o.zp, b);
+  v.kp = rebase(o.kp, b);
+  for (int i = 0; i < 2; ++i) v.st[i] = rebase((char *)o.st[i], b);
+  v.acc_ref = rebase((char *)o.acc_ref, b);
+  v.acc_s1 = rebase((char *)o.acc_s1, b);
+  v.acc_s2 = rebase((char *)o.acc_s2, b);
+  v.a = rebase(o.a, b);
+  v.alpha = rebase(o.alpha, b);
+  v.beta = rebase(o.beta, b);
+  v.window = rebase(o.window, b);
+  v.accsum = rebase(o.accsum, b);
+  v.counts = rebase(o.counts, b);
+  v.energy = rebase(o.energy, b);
+  v.part = rebase(o.part, b);
+  v.out = rebase(o.out, b);
+}
+
+// LDS extent of a pass with nsw sweeps: tile + 2*(2*nsw + 1) halo + a ring,
+// or the whole grid plus its ring when that is smaller.
+void lds_extent(const mpr_ctx *c, int nsw, int &w, int &h, size_t &bytes) {
+  const int H = 2 * nsw + 1;
+  w = 0;
+  h = 0;
+  for (const GridDesc &d : c->plan.gd) {
+    w = std::max(w, std::min(c->plan.tile_x + 2 * H + 2, d.nx + 3));
+    h = std::max(h, std::min(c->plan.tile_y + 2 * H + 2, d.ny + 2));
+  }
+  w = (w + 1) & ~1;
+  bytes = (size_t)w * h * 3 * c->plan.elem;  // angle + (cos, sin), both colours
+}
+
+mpr_status set_beta(mpr_ctx *c, const double *T) {
+  if (!T) return fail(c, MPR_E_ARG, "T is NULL");
+  c->beta_h.assign(c->plan.total_chains, 0.0);
+  for (int g = 0; g < c->n_grids; ++g) {
+    const double t = T[g];
+    if (std::isnan(t) || t < 0.0) return fail(c, MPR_E_ARG, "T must be >= 0 (or +inf) for every grid");
+    const double beta = std::isinf(t) ? 0.0 : (t == 0.0 ? INFINITY : 1.0 / t);
+    const GridDesc &d = c->plan.gd[g];
+    for (int k = 0; k < d.chains; ++k) c->beta_h[d.chain_base + k] = beta;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->v.beta, c->beta_h.data(), 8 * c->beta_h.size(), hipMemcpyHostToDevice, c->stream));
+  return MPR_OK;
+}
+
+// Sum the elapsed time of all recorded event pairs (synchronises).
+mpr_status drain_timing(mpr_ctx *c) {
+  if (c->ev_used == 0) return MPR_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    c->t_ms += ms;
+  }
+  c->ev_used = 0;
+  return MPR_OK;
+}
+
+template <typename P>
+mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace, int64_t trace_row0,
+                    uint32_t record_mask, uint32_t first_mask) {
+  SweepArgs<P> A{};
+  int w, h;
+  size_t lds;
+  lds_extent(c, nsw, w, h, lds);
+  if (lds > c->lds_limit)
+    return fail(c, MPR_E_ARG, "tile and sweeps_per_pass need " + std::to_string(lds) + " bytes of LDS, limit " +
+                                  std::to_string(c->lds_limit));
+  A.grids = c->v.gd;
+  A.n_grids = c->n_grids;
+  A.tile_x = c->plan.tile_x;
+  A.tile_y = c->plan.tile_y;
+  A.nsw = nsw;
+  A.lds_w = w;
+  A.lds_h = h;
+  A.q_is_one = c->p.q == 1.0;
+  A.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
+  A.key1 = (uint32_t)(c->p.seed >> 32);
+  A.sweep0 = (uint32_t)c->sweep_index;
+  A.record_mask = record_mask;
+  A.first_mask = first_mask;
+  A.q = (P)c->p.q;
+  A.src = (const P *)c->v.st[c->cur];
+  A.dst = (P *)c->v.st[c->cur ^ 1];
+  A.beta = c->v.beta;
+  A.alpha = c->v.alpha;
+  A.counts = c->v.counts;
+  A.energy = trace_e ? c->v.energy : nullptr;
+  A.acc_ref = (P *)c->v.acc_ref;
+  A.acc_s1 = (P *)c->v.acc_s1;
+  A.acc_s2 = (P *)c->v.acc_s2;
+  if (c->timing) {
+    if (c->ev_used + 2 > c->ev.size()) {
+      if (c->ev.size() < 8192) {
+        for (int i = 0; i < 256; ++i) {
+          hipEvent_t e;
+          HIP_TRY(c, hipEventCreate(&e));
+          c->ev.push_back(e);
+        }
+      } else {
+        const mpr_status st = drain_timing(c);
+        if (st != MPR_OK) return st;
+      }
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+  }
+  HIP_TRY(c, launch_sweep<P>(A, c->plan.n_items, lds, c->stream));
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+    c->ev_used += 2;
+    c->t_launches += 1;
+    c->t_site_sweeps += (int64_t)nsw * c->sites_all_chains;
+  }
+
+  PassEndArgs E{};
+  E.grids = c->v.gd;
+  E.n_grids = c->n_grids;
+  E.total_chains = c->plan.total_chains;
+  E.nsw = nsw;
+  E.sweep0 = (uint32_t)c->sweep_index;
+  E.adapt = adapt;
+  E.adapt_every = c->p.adapt_every;
+  E.a_targ = c->p.a_targ;
+  E.k_a = c->p.k_a;
+  E.trace_row0 = trace_row0;
+  E.trace = trace;
+  E.counts = c->v.counts;
+  E.energy = trace_e ? c->v.energy : nullptr;
+  E.a = c->v.a;
+  E.alpha = c->v.alpha;
+  E.window = c->v.window;
+  E.accsum = c->v.accsum;
+  HIP_TRY(c, launch_pass_end(E, c->stream));
+  c->cur ^= 1;
+  c->sweep_index += nsw;
+  return MPR_OK;
+}
+
+// n sweeps in passes of at most nsw_max; with the a-rule no pass crosses the
+// end of an adapt_every window, so a is constant within every pass.
+// rec_stride > 0 records every rec_stride-th sweep of this run.
+mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *trace, int rec_stride) {
+  if (c->sweep_index + n >= 0xFFFFFFFFLL) return fail(c, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
+  int64_t done = 0;
+  while (done < n) {
+    int64_t len = std::min<int64_t>(c->nsw_max, n - done);
+    if (adapt) {
+      const int64_t ae = c->p.adapt_every;
+      len = std::min<int64_t>(len, ae - (c->sweep_index % ae));
+    }
+    uint32_t rec = 0, first = 0;
+    if (rec_stride > 0)
+      for (int s = 0; s < len; ++s) {
+        const int64_t j = done + s;
+        if ((j + 1) % rec_stride == 0) {
+          rec |= 1u << s;
+          if (j + 1 == rec_stride) first |= 1u << s;
+        }
+      }
+    const mpr_status st = c->p.dtype == MPR_FP64
+                              ? run_pass<double>(c, (int)len, adapt, trace_e, trace, done, rec, first)
+                              : run_pass<float>(c, (int)len, adapt, trace_e, trace, done, rec, first);
+    if (st != MPR_OK) return st;
+    done += len;
+  }
+  return MPR_OK;
+}
+
+mpr_status reduce_energy(mpr_ctx *c, int what, std::vector<double> &out) {
+  const int units = what ? c->plan.total_chains : c->n_grids;
+  const int64_t blocks = what ? c->plan.n_cblocks : c->plan.n_sblocks;
+  if (c->p.dtype == MPR_FP64) {
+    HIP_TRY(c, launch_energy<double>(c->v.gd, c->n_grids, blocks, what, (const double *)c->v.st[c->cur], c->p.q,
+                                     c->v.part, c->stream));
+  } else {
+    HIP_TRY(c, launch_energy<float>(c->v.gd, c->n_grids, blocks, what, (const float *)c->v.st[c->cur],
+                                    (float)c->p.q, c->v.part, c->stream));
+  }
+  HIP_TRY(c, launch_energy_final(c->v.gd, c->n_grids, what, units, c->v.part, c->v.out, c->stream));
+  out.resize((size_t)units * 2);
+  HIP_TRY(c, hipMemcpyAsync(out.data(), c->v.out, 16 * (size_t)units, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MPR_OK;
+}
+
+// ---------------------------------------------------------------- PCHIP
+// Monotone piecewise-cubic Hermite interpolation (Fritsch & Carlson 1980),
+// interior slopes by the weighted harmonic mean of Fritsch & Butland (1984),
+// end slopes by the shape-preserving one-sided three-point formula
+// (Moler, Numerical Computing with MATLAB, Sec. 3.6).
+struct Pchip {
+  std::vector<double> x, y, d;
+  void build(const std::vector<double> &xs, const std::vector<double> &ys) {
+    x = xs;
+    y = ys;
+    const size_t n = x.size();
+    d.assign(n, 0.0);
+    std::vector<double> h(n - 1), m(n - 1);
+    for (size_t k = 0; k + 1 < n; ++k) {
+      h[k] = x[k + 1] - x[k];
+      m[k] = (y[k + 1] - y[k]) / h[k];
+    }
+    if (n == 2) {
+      d[0] = d[1] = m[0];
+      return;
+    }
+    auto sgn = [](double v) { return (v > 0) - (v < 0); };
+    for (size_t k = 1; k + 1 < n; ++k) {
+      if (sgn(m[k - 1]) != sgn(m[k]) || m[k - 1] == 0.0 || m[k] == 0.0) {
+        d[k] = 0.0;
+      } else {
+        const double w1 = 2.0 * h[k] + h[k - 1], w2 = h[k] + 2.0 * h[k - 1];
+        d[k] = (w1 + w2) / (w1 / m[k - 1] + w2 / m[k]);
+      }
+    }
+    auto edge = [&](double h0, double h1, double m0, double m1) {
+      double e = ((2.0 * h0 + h1) * m0 - h0 * m1) / (h0 + h1);
+      if (sgn(e) != sgn(m0)) e = 0.0;
+      else if (sgn(m0) != sgn(m1) && std::fabs(e) > 3.0 * std::fabs(m0)) e = 3.0 * m0;
+      return e;
+    };
+    d[0] = edge(h[0], h[1], m[0], m[1]);
+    d[n - 1] = edge(h[n - 2], h[n - 3], m[n - 2], m[n - 3]);
+  }
+  double eval(size_t k, double xv) const {
+    const double hk = x[k + 1] - x[k], t = xv - x[k];
+    const double mk = (y[k + 1] - y[k]) / hk;
+    const double c2 = (3.0 * mk - 2.0 * d[k] - d[k + 1]) / hk;
+    const double c3 = (d[k] + d[k + 1] - 2.0 * mk) / (hk * hk);
+    return y[k] + t * (d[k] + t * (c2 + t * c3));
+  }
+};
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+void mpr_default_params(mpr_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->q = 0.5;
+  p->a_targ = 0.3;
+  p->k_a = 3.0;
+  p->adapt_every = 1;
+  p->a_sample_keep = 0;
+  p->dtype = MPR_FP32;
+  p->sweeps_per_pass = 0;
+  p->tile_x = 0;
+  p->tile_y = 0;
+  p->seed = 0;
+}
+
+const char *mpr_last_error(const mpr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_thread_err.c_str(); }
+
+void mpr_destroy(mpr_ctx *ctx) { delete ctx; }
+
+mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids, const mpr_params *p,
+                          void *workspace, size_t *ws_bytes, void *hip_stream) {
+  g_thread_err.clear();
+  if (!ws_bytes) return fail(nullptr, MPR_E_ARG, "ws_bytes is NULL");
+  mpr_status st = check_params(p);
+  if (st != MPR_OK) return st;
+  Plan plan;
+  st = make_plan(grids, n_grids, p, workspace != nullptr, plan);
+  if (st != MPR_OK) return st;
+  if (!workspace) {
+    *ws_bytes = plan.bytes;
+    return MPR_OK;
+  }
+  if (!ctx) return fail(nullptr, MPR_E_ARG, "ctx is NULL");
+  if (*ws_bytes < plan.bytes)
+    return fail(nullptr, MPR_E_WORKSPACE,
+                "workspace of " + std::to_string(*ws_bytes) + " bytes, need " + std::to_string(plan.bytes));
+  if (((uintptr_t)workspace) & 255) return fail(nullptr, MPR_E_WORKSPACE, "workspace must be 256-byte aligned");
+
+  mpr_ctx *c = new mpr_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->p = *p;
+  c->n_grids = n_grids;
+  c->plan = plan;
+  bind(c->v, plan.v, workspace);
+  c->nsw_max = p->sweeps_per_pass ? p->sweeps_per_pass : 1;
+  c->sites_all_chains = plan.state_elems;
+  auto bail = [&](mpr_status s) {
+    g_thread_err = c->err;
+    delete c;
+    return s;
+  };
+  int dev = 0, lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "device query"));
+  c->lds_limit = (size_t)lds;
+  {
+    int w, h;
+    size_t need;
+    lds_extent(c, c->nsw_max, w, h, need);
+    if (need > c->lds_limit)
+      return bail(fail(c, MPR_E_ARG, "tile and sweeps_per_pass need " + std::to_string(need) +
+                                         " bytes of LDS per workgroup, the device allows " + std::to_string(lds)));
+  }
+
+  std::vector<const double *> zp(n_grids);
+  std::vector<const uint8_t *> kp(n_grids);
+  for (int g = 0; g < n_grids; ++g) {
+    zp[g] = grids[g].z;
+    kp[g] = grids[g].known;
+  }
+  std::vector<double> mm((size_t)n_grids * 4);
+#define TRY(call)                                      \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return bail(hip_fail(c, e_, #call)); \
+  } while (0)
+  TRY(hipMemcpyAsync(c->v.gd, c->plan.gd.data(), sizeof(GridDesc) * n_grids, hipMemcpyHostToDevice, c->stream));
+  TRY(hipMemcpyAsync(c->v.zp, zp.data(), sizeof(void *) * n_grids, hipMemcpyHostToDevice, c->stream));
+  TRY(hipMemcpyAsync(c->v.kp, kp.data(), sizeof(void *) * n_grids, hipMemcpyHostToDevice, c->stream));
+  TRY(launch_minmax(c->v.gd, n_grids, c->plan.n_sblocks, c->v.zp, c->v.kp, c->v.part, c->stream));
+  TRY(launch_minmax_final(c->v.gd, n_grids, c->v.part, c->v.out, c->stream));
+  TRY(hipMemcpyAsync(mm.data(), c->v.out, 8 * mm.size(), hipMemcpyDeviceToHost, c->stream));
+  TRY(hipStreamSynchronize(c->stream));
+  for (int g = 0; g < n_grids; ++g) {
+    const double mn = mm[g * 4], mx = mm[g * 4 + 1], cnt = mm[g * 4 + 2], bad = mm[g * 4 + 3];
+    if (bad > 0) return bail(fail(c, MPR_E_ARG, "grid " + std::to_string(g) + ": non-finite z at a sample site"));
+    GridDesc &d = c->plan.gd[g];
+    d.n_gap = (int64_t)d.nx * d.ny - (int64_t)cnt;
+    if (cnt > 0) {
+      if (!(mx > mn)) return bail(fail(c, MPR_E_DEGENERATE, "grid " + std::to_string(g) + ": z_max == z_min"));
+      d.zmin = mn;
+      d.zmax = mx;
+    }
+  }
+  TRY(hipMemcpyAsync(c->v.gd, c->plan.gd.data(), sizeof(GridDesc) * n_grids, hipMemcpyHostToDevice, c->stream));
+  if (p->dtype == MPR_FP64) {
+    TRY(launch_init<double>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (double *)c->v.st[0],
+                            (double *)c->v.st[1], 0.0, (uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32),
+                            c->stream));
+  } else {
+    TRY(launch_init<float>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (float *)c->v.st[0],
+                           (float *)c->v.st[1], 0.0f, (uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32),
+                           c->stream));
+  }
+  const int64_t C = c->plan.total_chains;
+  TRY(launch_fill_f64(c->v.a, C, 1.0, c->stream));
+  TRY(launch_fill_f64(c->v.alpha, C, 6.28318530717958647692, c->stream));
+  TRY(launch_fill_f64(c->v.beta, C, 0.0, c->stream));
+  TRY(launch_fill_f64(c->v.window, C, 0.0, c->stream));
+  TRY(launch_fill_f64(c->v.accsum, C, 0.0, c->stream));
+  TRY(launch_zero_u32(c->v.counts, C * kMaxPass, c->stream));
+  TRY(launch_fill_f64(c->v.energy, C * kMaxPass, 0.0, c->stream));
+  TRY(hipStreamSynchronize(c->stream));
+#undef TRY
+  *ctx = c;
+  return MPR_OK;
+}
+
+mpr_status mpr_sweep(mpr_ctx *ctx, int32_t n_sweeps, const double *T, uint32_t flags, double *trace) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (n_sweeps < 0) return fail(ctx, MPR_E_ARG, "n_sweeps must be >= 0");
+  if (flags & ~(MPR_ADAPT | MPR_TRACE_E)) return fail(ctx, MPR_E_ARG, "unknown flag");
+  mpr_status st = set_beta(ctx, T);
+  if (st != MPR_OK) return st;
+  return run_sweeps(ctx, n_sweeps, (flags & MPR_ADAPT) != 0, (flags & MPR_TRACE_E) != 0, trace, 0);
+}
+
+mpr_status mpr_specific_energy(mpr_ctx *ctx, int32_t what, double *e_out, int64_t *npairs_out) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (what != MPR_SAMPLE_PAIRS && what != MPR_STATE) return fail(ctx, MPR_E_ARG, "unknown selector");
+  if (!e_out) return fail(ctx, MPR_E_ARG, "e_out is NULL");
+  std::vector<double> out;
+  mpr_status st = reduce_energy(ctx, what, out);
+  if (st != MPR_OK) return st;
+  mpr_status ret = MPR_OK;
+  if (what == MPR_SAMPLE_PAIRS) {
+    for (int g = 0; g < ctx->n_grids; ++g) {
+      const double s = out[g * 2], n = out[g * 2 + 1];
+      if (npairs_out) npairs_out[g] = (int64_t)n;
+      if (n > 0) {
+        e_out[g] = s / n - 1.0;
+      } else {
+        e_out[g] = NAN;
+        ret = fail(ctx, MPR_E_NOPAIRS, "grid " + std::to_string(g) + " has no sample-sample neighbour pair");
+      }
+    }
+  } else {
+    for (const GridDesc &d : ctx->plan.gd)
+      for (int k = 0; k < d.chains; ++k) {
+        const int u = d.chain_base + k;
+        e_out[u] = out[u * 2] / (double)d.n_pairs - 1.0;
+        if (npairs_out) npairs_out[u] = d.n_pairs;
+      }
+  }
+  return ret;
+}
+
+mpr_status mpr_match_T(const double *e_s, int32_t n, const double *tab_T, const double *tab_e, int32_t n_tab,
+                       double *T_out, mpr_status *item_status) {
+  g_thread_err.clear();
+  if (n < 0 || (n > 0 && (!e_s || !T_out))) return fail(nullptr, MPR_E_ARG, "bad e_s / T_out");
+  if (n_tab < 2 || !tab_T || !tab_e) return fail(nullptr, MPR_E_ARG, "need a table of at least 2 points");
+  for (int k = 0; k < n_tab; ++k) {
+    if (!(tab_T[k] > 0.0) || !std::isfinite(tab_T[k]) || (k && !(tab_T[k] > tab_T[k - 1])))
+      return fail(nullptr, MPR_E_ARG, "tab_T must be finite, positive and strictly increasing");
+    if (!(tab_e[k] > -1.0) || !std::isfinite(tab_e[k]) || (k && !(tab_e[k] >= tab_e[k - 1])))
+      return fail(nullptr, MPR_E_ARG, "tab_e must be finite, > -1 and non-decreasing");
+  }
+  std::vector<double> lx(n_tab), ly(n_tab);
+  for (int k = 0; k < n_tab; ++k) {
+    lx[k] = std::log(tab_T[k]);
+    ly[k] = std::log1p(tab_e[k]);
+  }
+  Pchip pc;
+  pc.build(lx, ly);
+  mpr_status ret = MPR_OK;
+  for (int i = 0; i < n; ++i) {
+    const double e = e_s[i];
+    mpr_status s = MPR_OK;
+    double T;
+    if (std::isnan(e)) {
+      T = NAN;
+      s = MPR_E_ARG;
+    } else if (e <= tab_e[0]) {
+      T = tab_T[0];
+      if (e < tab_e[0]) s = MPR_E_RANGE;
+    } else if (e >= tab_e[n_tab - 1]) {
+      T = tab_T[n_tab - 1];
+      if (e > tab_e[n_tab - 1]) s = MPR_E_RANGE;
+    } else {
+      // last node with tab_e <= e; the root lies in [x_j, x_{j+1})
+      const int j = (int)(std::upper_bound(tab_e, tab_e + n_tab, e) - tab_e) - 1;
+      if (tab_e[j] == e) {
+        T = tab_T[j];
+      } else {
+        const double target = std::log1p(e);
+        double lo = lx[j], hi = lx[j + 1];
+        for (int it = 0; it < 400; ++it) {
+          const double mid = 0.5 * (lo + hi);
+          if (!(mid > lo && mid < hi)) break;
+          if (pc.eval(j, mid) < target) lo = mid;
+          else hi = mid;
+        }
+        const double flo = std::fabs(pc.eval(j, lo) - target), fhi = std::fabs(pc.eval(j, hi) - target);
+        T = std::exp(flo <= fhi ? lo : hi);
+      }
+    }
+    if (item_status) item_status[i] = s;
+    if (s == MPR_E_ARG) ret = fail(nullptr, MPR_E_ARG, "NaN e_s");
+    else if (s == MPR_E_RANGE && ret == MPR_OK) ret = fail(nullptr, MPR_E_RANGE, "e_s outside the table; T clamped");
+    T_out[i] = T;
+  }
+  return ret;
+}
+
+mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp, int32_t stride, double *zhat,
+                    double *zstd, mpr_fill_report *rep) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (n_eq < 0 || n_samp < 1 || stride < 1 || n_samp / stride < 1)
+    return fail(ctx, MPR_E_ARG, "need n_eq >= 0, n_samp >= 1, 1 <= stride <= n_samp");
+  if (!zhat) return fail(ctx, MPR_E_ARG, "zhat is NULL");
+  for (int g = 0; g < ctx->n_grids; ++g)
+    if (std::isnan(ctx->plan.gd[g].zmin))
+      return fail(ctx, MPR_E_DEGENERATE, "grid " + std::to_string(g) + " has no samples to fill from");
+  mpr_status st = set_beta(ctx, T);
+  if (st != MPR_OK) return st;
+  const int64_t C = ctx->plan.total_chains;
+  std::vector<double> hv;
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.window, C, 0.0, ctx->stream));
+  st = run_sweeps(ctx, n_eq, true, false, nullptr, 0);
+  if (st != MPR_OK) return st;
+  if (rep && (rep->a_eq || rep->acc_eq)) {
+    hv.resize(C);
+    if (rep->a_eq) {
+      HIP_TRY(ctx, hipMemcpyAsync(rep->a_eq, ctx->v.a, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(hv.data(), ctx->v.accsum, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (rep->acc_eq)
+      for (int64_t k = 0; k < C; ++k) rep->acc_eq[k] = n_eq ? hv[k] / n_eq : NAN;
+  }
+  if (!ctx->p.a_sample_keep) {
+    HIP_TRY(ctx, launch_fill_f64(ctx->v.a, C, 1.0, ctx->stream));
+    HIP_TRY(ctx, launch_fill_f64(ctx->v.alpha, C, 6.28318530717958647692, ctx->stream));
+  }
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
+  st = run_sweeps(ctx, n_samp, false, false, nullptr, stride);
+  if (st != MPR_OK) return st;
+  const int32_t records = n_samp / stride;
+  if (ctx->p.dtype == MPR_FP64) {
+    HIP_TRY(ctx, launch_finalize<double>(ctx->v.gd, ctx->n_grids, ctx->plan.n_sblocks, ctx->v.zp,
+                                         (const double *)ctx->v.st[ctx->cur], (const double *)ctx->v.acc_ref,
+                                         (const double *)ctx->v.acc_s1, (const double *)ctx->v.acc_s2, records, zhat,
+                                         zstd, ctx->stream));
+  } else {
+    HIP_TRY(ctx, launch_finalize<float>(ctx->v.gd, ctx->n_grids, ctx->plan.n_sblocks, ctx->v.zp,
+                                        (const float *)ctx->v.st[ctx->cur], (const float *)ctx->v.acc_ref,
+                                        (const float *)ctx->v.acc_s1, (const float *)ctx->v.acc_s2, records, zhat,
+                                        zstd, ctx->stream));
+  }
+  if (rep) {
+    rep->records = records;
+    if (rep->acc_samp) {
+      hv.resize(C);
+      HIP_TRY(ctx, hipMemcpyAsync(hv.data(), ctx->v.accsum, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      for (int64_t k = 0; k < C; ++k) rep->acc_samp[k] = hv[k] / n_samp;
+    }
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPR_OK;
+}
+
+static mpr_status chain_view(mpr_ctx *ctx, int32_t grid, int32_t chain, int64_t &off, int64_t &n) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (grid < 0 || grid >= ctx->n_grids) return fail(ctx, MPR_E_ARG, "grid index out of range");
+  const GridDesc &d = ctx->plan.gd[grid];
+  if (chain < 0 || chain >= d.chains) return fail(ctx, MPR_E_ARG, "chain index out of range");
+  n = (int64_t)d.nx * d.ny;
+  off = d.state_off + (int64_t)chain * n;
+  return MPR_OK;
+}
+
+mpr_status mpr_get_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, double *phi) {
+  int64_t off, n;
+  mpr_status st = chain_view(ctx, grid, chain, off, n);
+  if (st != MPR_OK) return st;
+  if (!phi) return fail(ctx, MPR_E_ARG, "phi is NULL");
+  if (ctx->p.dtype == MPR_FP64) {
+    HIP_TRY(ctx, launch_get_phi<double>((const double *)ctx->v.st[ctx->cur] + off, n, phi, ctx->stream));
+  } else {
+    HIP_TRY(ctx, launch_get_phi<float>((const float *)ctx->v.st[ctx->cur] + off, n, phi, ctx->stream));
+  }
+  return MPR_OK;
+}
+
+mpr_status mpr_set_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, const double *phi) {
+  int64_t off, n;
+  mpr_status st = chain_view(ctx, grid, chain, off, n);
+  if (st != MPR_OK) return st;
+  if (!phi) return fail(ctx, MPR_E_ARG, "phi is NULL");
+  if (ctx->p.dtype == MPR_FP64) {
+    HIP_TRY(ctx, launch_set_phi<double>((double *)ctx->v.st[ctx->cur] + off, (double *)ctx->v.st[ctx->cur ^ 1] + off,
+                                        n, phi, ctx->stream));
+  } else {
+    HIP_TRY(ctx, launch_set_phi<float>((float *)ctx->v.st[ctx->cur] + off, (float *)ctx->v.st[ctx->cur ^ 1] + off, n,
+                                       phi, ctx->stream));
+  }
+  return MPR_OK;
+}
+
+mpr_status mpr_set_timing(mpr_ctx *ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return MPR_OK;
+}
+
+mpr_status mpr_get_timing(mpr_ctx *ctx, double *sweep_ms, int64_t *launches, int64_t *site_sweeps) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  const mpr_status st = drain_timing(ctx);
+  if (st != MPR_OK) return st;
+  if (sweep_ms) *sweep_ms = ctx->t_ms;
+  if (launches) *launches = ctx->t_launches;
+  if (site_sweeps) *site_sweeps = ctx->t_site_sweeps;
+  ctx->t_ms = 0.0;
+  ctx->t_launches = 0;
+  ctx->t_site_sweeps = 0;
+  return MPR_OK;
+}
+
+mpr_status mpr_get_chain_state(mpr_ctx *ctx, int64_t *sweep_index, double *a) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (sweep_index) *sweep_index = ctx->sweep_index;
+  if (a) {
+    HIP_TRY(ctx, hipMemcpyAsync(a, ctx->v.a, 8 * (size_t)ctx->plan.total_chains, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPR_OK;
+}
+
+mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *a) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (sweep_index < 0 || sweep_index >= 0xFFFFFFFFLL) return fail(ctx, MPR_E_ARG, "sweep_index out of range");
+  if (a) {
+    for (int k = 0; k < ctx->plan.total_chains; ++k)
+      if (!(a[k] >= 1.0) || !std::isfinite(a[k])) return fail(ctx, MPR_E_ARG, "every a must be finite and >= 1");
+    std::vector<double> al(ctx->plan.total_chains);
+    for (int k = 0; k < ctx->plan.total_chains; ++k) al[k] = 6.28318530717958647692 / a[k];
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->v.a, a, 8 * al.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->v.alpha, al.data(), 8 * al.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  ctx->sweep_index = sweep_index;
+  return MPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal declarations shared by the kernels and the host side of libmpr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mpr {
+
+constexpr int kThreads = 256;       // threads per workgroup of every kernel (4 wave64)
+constexpr int kMaxPass = 16;        // sweeps fused into one pass, at most
+constexpr int kChunk = 4096;        // sites per workgroup in the streaming kernels
+
+// One grid of a batch, as the device sees it.  Angles of chain c of grid g
+// live at state[state_off + c*ny*nx + y*nx + x]; z and the fill outputs at
+// site_off + y*nx + x.  A sample (frozen) site is stored with its sign bit
+// set: the angle is |v|, and gap angles are >= +0.
+struct GridDesc {
+  int32_t nx, ny, chains, npair;   // npair = ceil(nx/2): Philox pairs per row
+  int32_t tiles_x, tiles_y;        // sweep tiles of one chain
+  int32_t chain_base;              // global index of chain 0
+  int32_t grid_id;                 // index of the grid in the batch
+  int64_t item_begin;              // first sweep work item (grid, chain, tile)
+  int64_t cb_begin;                // first chain-chunk block (init, per-chain energy)
+  int64_t sb_begin;                // first site-chunk block (min/max, sample energy, finalize)
+  int64_t state_off, site_off;
+  int64_t n_gap;                   // gap sites per chain
+  int64_t n_pairs;                 // N_GP of Eq. (5)
+  double zmin, zmax;               // Eq. (2) over the samples; NaN without samples
+};
+
+template <typename P>
+struct SweepArgs {
+  const GridDesc *grids;
+  int32_t n_grids;
+  int32_t tile_x, tile_y;
+  int32_t nsw;                     // sweeps in this pass
+  int32_t lds_w, lds_h;            // LDS extent in sites (lds_w even)
+  int32_t q_is_one;
+  uint32_t key0, key1;
+  uint32_t sweep0;                 // global index of the pass's first sweep
+  uint32_t record_mask, first_mask;
+  P q;
+  const P *src;
+  P *dst;
+  const double *beta, *alpha;      // per chain
+  uint32_t *counts;                // [chains][kMaxPass] accepted updates
+  double *energy;                  // [chains][kMaxPass] or nullptr
+  P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
+};
+
+struct PassEndArgs {
+  const GridDesc *grids;
+  int32_t n_grids, total_chains;
+  int32_t nsw;
+  uint32_t sweep0;
+  int32_t adapt, adapt_every;
+  double a_targ, k_a;
+  int64_t trace_row0;
+  double *trace;                   // [rows][chains][2] or nullptr
+  uint32_t *counts;
+  double *energy;                  // or nullptr
+  double *a, *alpha, *window, *accsum;
+};
+
+// Launchers (kernels.hip).  All return the hipError_t of the launch.
+template <typename P>
+hipError_t launch_sweep(const SweepArgs<P> &a, int64_t n_items, size_t lds_bytes, hipStream_t s);
+hipError_t launch_pass_end(const PassEndArgs &a, hipStream_t s);
+hipError_t launch_minmax(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
+                         const uint8_t *const *known, double *part, hipStream_t s);
+hipError_t launch_minmax_final(const GridDesc *g, int n_grids, const double *part, double *out, hipStream_t s);
+template <typename P>
+hipError_t launch_init(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
+                       const uint8_t *const *known, P *s0, P *s1, P q_unused, uint32_t k0, uint32_t k1,
+                       hipStream_t s);
+template <typename P>
+hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q,
+                         double *part, hipStream_t s);
+hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
+                               double *out, hipStream_t s);
+template <typename P>
+hipError_t launch_finalize(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
+                           const P *state, const P *ref, const P *s1, const P *s2, int32_t records,
+                           double *zhat, double *zstd, hipStream_t s);
+template <typename P>
+hipError_t launch_get_phi(const P *state, int64_t n, double *out, hipStream_t s);
+template <typename P>
+hipError_t launch_set_phi(P *s0, P *s1, int64_t n, const double *in, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+
+}  // namespace mpr

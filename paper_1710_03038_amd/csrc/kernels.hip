@@ -1,0 +1,719 @@
+// gfx950 kernels of the MPR hybrid Monte Carlo path.
+//
+// Method: Zukovic & Hristopulos, arXiv 1710.03038.  Eq. (2) maps data to
+// angles, Eq. (3) is the MPR energy -sum cos(q (phi_i - phi_j)) over
+// nearest-neighbour pairs with open boundaries, Eqs. (4)-(5) the sample and
+// equilibrium specific energies, Eq. (6) the over-relaxation; Algorithm 1
+// is the hybrid update (over-relaxation, then restricted Metropolis) and
+// Algorithm 2 the driver.  The sweep runs the sites of one checkerboard
+// colour at a time (Sec. 5.2).
+//
+// Layout: angles are stored per (grid, chain) in natural row-major order;
+// the sign bit marks a frozen sample site (|v| is its angle).  A sweep
+// workgroup stages its tile plus a halo of 2*nsw + 1 sites in LDS, split by
+// colour so that the sites of one colour and the neighbours they read are
+// contiguous, runs nsw sweeps there, and writes the tile interior to the
+// other buffer of a ping-pong pair.  Sites of the halo are updated
+// redundantly by neighbouring tiles with identical arithmetic and random
+// numbers, so results do not depend on the tiling.
+#include "internal.h"
+
+#include <cmath>
+
+namespace mpr {
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon et al., SC'11): rounds multiply words 0 and 2 by
+// 0xD2511F53 and 0xCD9E8D57 (32x32 -> 64 bit), swap and xor in the key; the
+// key advances by 0x9E3779B9 / 0xBB67AE85 between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// ------------------------------------------------------------ precision
+template <typename P> struct Prec;
+template <> struct Prec<float> {
+  using V2 = float2;
+  static constexpr float two_pi = 6.28318530717958647692f;  // rounds up: 6.2831855f
+  static constexpr float below_two_pi = 6.2831850f;         // largest float < two_pi
+  static constexpr float tiny_h2 = 1e-12f;
+  __device__ static float sin_(float x) { return sinf(x); }
+  __device__ static void sincos_(float x, float *s, float *c) { sincosf(x, s, c); }
+  __device__ static float atan2_(float y, float x) { return atan2f(y, x); }
+  __device__ static float exp_(float x) { return expf(x); }
+  __device__ static float sqrt_(float x) { return sqrtf(x); }
+  __device__ static float floor_(float x) { return floorf(x); }
+};
+template <> struct Prec<double> {
+  using V2 = double2;
+  static constexpr double two_pi = 6.28318530717958647692;
+  static constexpr double below_two_pi = 6.2831853071795853;  // nextafter(2*pi, 0)
+  static constexpr double tiny_h2 = 1e-24;
+  __device__ static double sin_(double x) { return sin(x); }
+  __device__ static void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
+  __device__ static double atan2_(double y, double x) { return atan2(y, x); }
+  __device__ static double exp_(double x) { return exp(x); }
+  __device__ static double sqrt_(double x) { return sqrt(x); }
+  __device__ static double floor_(double x) { return floor(x); }
+};
+
+// A 32-bit word to [0, 1 - 2^-24]: (w >> 8) * 2^-24, exact in either precision.
+template <typename P> __device__ __forceinline__ P unit(uint32_t w) {
+  return (P)(w >> 8) * (P)5.9604644775390625e-08;
+}
+
+// Proposal wrap for |shift| <= pi (Algorithm 1, step 3): into [0, 2*pi),
+// with a rounding result of exactly 2*pi folded to 0.
+template <typename P> __device__ __forceinline__ P wrap_step(P x) {
+  const P tp = Prec<P>::two_pi;
+  x = (x < P(0)) ? x + tp : ((x >= tp) ? x - tp : x);
+  return (x >= tp) ? P(0) : x;
+}
+// General wrap (q = 1 over-relaxation): x - 2*pi*floor(x / 2*pi), folded.
+template <typename P> __device__ __forceinline__ P wrap_any(P x) {
+  const P tp = Prec<P>::two_pi;
+  P y = x - tp * Prec<P>::floor_(x / tp);
+  y = (y < P(0)) ? y + tp : y;
+  return (y >= tp) ? P(0) : y;
+}
+
+// --------------------------------------------------------- block reductions
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Sum over the workgroup; the result is valid in thread 0.  Fixed order.
+template <typename T> __device__ __forceinline__ T block_sum(T v, T *scratch) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) scratch[w] = v;
+  __syncthreads();
+  T r = T(0);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kThreads / 64; ++i) r += scratch[i];
+  return r;
+}
+
+__device__ __forceinline__ int find_by(const GridDesc *g, int n, int64_t key, int64_t GridDesc::*field) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g[mid].*field <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- sweep
+// One workgroup = one (grid, chain, tile) item.  Half-sweep hs of the pass
+// updates the colour-(hs & 1) gap sites within distance D = 2*nsw - hs of
+// the interior; the halo of 2*nsw + 1 sites keeps every neighbour read by
+// those sites exact, and after each full sweep the interior plus one ring
+// is exact, which the energy of interior pairs needs.
+template <typename P>
+__global__ void __launch_bounds__(kThreads) k_sweep(const SweepArgs<P> A) {
+  using V2 = typename Prec<P>::V2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[kThreads / 64];
+  __shared__ uint32_t red_u[kThreads / 64];
+
+  const int64_t item = blockIdx.x;
+  const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin);
+  const GridDesc &G = A.grids[gi];
+  const int64_t local = item - G.item_begin;
+  const int tiles = G.tiles_x * G.tiles_y;
+  const int chain = (int)(local / tiles);
+  const int t = (int)(local - (int64_t)chain * tiles);
+  const int nx = G.nx, ny = G.ny;
+  const int x0 = (t % G.tiles_x) * A.tile_x, y0 = (t / G.tiles_x) * A.tile_y;
+  const int ix1 = min(x0 + A.tile_x, nx), iy1 = min(y0 + A.tile_y, ny);
+  const int H = 2 * A.nsw + 1;
+  const int ox = max(x0 - H - 1, -2);  // even, so LDS pairs are Philox pairs
+  const int oy = max(y0 - H - 1, -1);
+  const int lxs = max(x0 - H, 0), lxe = min(ix1 + H, nx);
+  const int lys = max(y0 - H, 0), lye = min(iy1 + H, ny);
+  const int W = A.lds_w, P2 = W >> 1, plane = A.lds_h * P2;
+
+  V2 *cs = reinterpret_cast<V2 *>(smem);                       // (cos q phi, sin q phi)
+  P *ph = reinterpret_cast<P *>(smem + 2 * plane * sizeof(V2));  // encoded angle
+  const P q = A.q;
+  const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
+  const P *src = A.src + cbase;
+
+  // Stage the tile, its halo and a frozen zero ring around them.
+  for (int idx = threadIdx.x; idx < W * A.lds_h; idx += kThreads) {
+    const int ly = idx / W, lx = idx - ly * W;
+    const int gx = ox + lx, gy = oy + ly;
+    const int o = ((gx + gy) & 1) * plane + ly * P2 + (lx >> 1);
+    P v = -P(0);
+    V2 c = {P(0), P(0)};
+    if (gx >= lxs && gx < lxe && gy >= lys && gy < lye) {
+      v = src[(int64_t)gy * nx + gx];
+      P s_, c_;
+      Prec<P>::sincos_(q * fabs(v), &s_, &c_);
+      c = {c_, s_};
+    }
+    ph[o] = v;
+    cs[o] = c;
+  }
+  __syncthreads();
+
+  const int gchain = G.chain_base + chain;
+  const P beta = (P)A.beta[gchain], alpha = (P)A.alpha[gchain];
+  const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
+  const int iw = ix1 - x0, ih = iy1 - y0;
+
+  for (int s = 0; s < A.nsw; ++s) {
+    const uint32_t sweep = A.sweep0 + (uint32_t)s;
+    uint32_t acc = 0;
+    for (int c = 0; c < 2; ++c) {
+      const int D = 2 * A.nsw - (2 * s + c);
+      const int rx0 = max(x0 - D, 0), rx1 = min(ix1 + D, nx);
+      const int ry0 = max(y0 - D, 0), ry1 = min(iy1 + D, ny);
+      const int ja = (rx0 - ox) >> 1, jb = (rx1 - 1 - ox) >> 1;
+      const int npr = jb - ja + 1, rows = ry1 - ry0;
+      const int total = npr * rows;
+      const float inv = 1.0f / (float)npr;
+      P *pc = ph + c * plane;
+      V2 *cc = cs + c * plane;
+      const V2 *cn = cs + (c ^ 1) * plane;
+      for (int f = threadIdx.x; f < total; f += kThreads) {
+        int r = (int)((float)f * inv);
+        int jo = f - r * npr;
+        if (jo >= npr) { ++r; jo -= npr; }
+        if (jo < 0) { --r; jo += npr; }
+        const int j = ja + jo;
+        const int gy = ry0 + r, ly = gy - oy;
+        const int gx = ox + 2 * j + ((c + gy) & 1);  // the colour-c site of pair j
+        if (gx < rx0 || gx >= rx1) continue;
+        const int o = ly * P2 + j;
+        const P phi = pc[o];
+        if (signbit(phi)) continue;  // frozen sample site
+        const int jl = (gx & 1) ? j : j - 1, jr = (gx & 1) ? j + 1 : j;
+        const V2 nl = cn[ly * P2 + jl], nr = cn[ly * P2 + jr];
+        const V2 nu = cn[o - P2], nd = cn[o + P2];
+        const P hx = nl.x + nr.x + nu.x + nd.x;
+        const P hy = nl.y + nr.y + nu.y + nd.y;
+
+        uint32_t w[4];
+        philox4x32_10((uint32_t)gy * (uint32_t)G.npair + (uint32_t)(gx >> 1), sweep, cid, gid, k0, k1, w);
+        const P u = unit<P>((gx & 1) ? w[2] : w[0]);
+        const P rr = unit<P>((gx & 1) ? w[3] : w[1]);
+
+        // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
+        const P h2 = hx * hx + hy * hy;
+        const P psi = Prec<P>::atan2_(hy, hx);
+        P p1 = phi;
+        if (h2 > Prec<P>::tiny_h2) {
+          const P star = (P(2) * psi - q * phi) / q;
+          if (A.q_is_one) p1 = wrap_any(star);
+          else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+        }
+        // Steps 2-3: restricted Metropolis proposal.
+        const P p2 = wrap_step(p1 + alpha * (u - P(0.5)));
+        // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
+        //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
+        const P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_(q * (p2 + p1) * P(0.5) - psi) *
+                     Prec<P>::sin_(q * (p2 - p1) * P(0.5));
+        // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
+        const bool ok = (dH <= P(0)) || (rr < Prec<P>::exp_(-beta * dH));
+        const P nv = ok ? p2 : p1;
+        pc[o] = nv;
+        P s_, c_;
+        Prec<P>::sincos_(q * nv, &s_, &c_);
+        cc[o] = {c_, s_};
+        if (ok && gx >= x0 && gx < ix1 && gy >= y0 && gy < iy1) ++acc;
+      }
+      __syncthreads();
+    }
+
+    if (A.counts) {
+      const uint32_t tot = block_sum(acc, red_u);
+      if (threadIdx.x == 0 && tot) atomicAdd(&A.counts[(int64_t)gchain * kMaxPass + s], tot);
+    }
+    if (A.energy) {
+      // Eq. (5): pairs (x, y)-(x+1, y) and (x, y)-(x, y+1) owned by interior sites.
+      P e = P(0);
+      for (int f = threadIdx.x; f < iw * ih; f += kThreads) {
+        const int r = f / iw;
+        const int gx = x0 + (f - r * iw), gy = y0 + r;
+        const int lx = gx - ox, ly = gy - oy;
+        const int col = (gx + gy) & 1;
+        const P v = fabs(ph[col * plane + ly * P2 + (lx >> 1)]);
+        if (gx + 1 < nx) {
+          const P d = v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]);
+          const P sn = Prec<P>::sin_(q * d * P(0.5));
+          e += P(2) * sn * sn;
+        }
+        if (gy + 1 < ny) {
+          const P d = v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]);
+          const P sn = Prec<P>::sin_(q * d * P(0.5));
+          e += P(2) * sn * sn;
+        }
+      }
+      const double tot = block_sum((double)e, red_d);
+      if (threadIdx.x == 0) atomicAdd(&A.energy[(int64_t)gchain * kMaxPass + s], tot);
+    }
+    if ((A.record_mask >> s) & 1u) {
+      // Algorithm 2, step 5.3: one realisation; shifted sums about the first.
+      const bool first = (A.first_mask >> s) & 1u;
+      for (int f = threadIdx.x; f < iw * ih; f += kThreads) {
+        const int r = f / iw;
+        const int gx = x0 + (f - r * iw), gy = y0 + r;
+        const int lx = gx - ox, ly = gy - oy;
+        const P v = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
+        if (signbit(v)) continue;
+        const int64_t k = cbase + (int64_t)gy * nx + gx;
+        if (first) {
+          A.acc_ref[k] = v;
+          A.acc_s1[k] = P(0);
+          A.acc_s2[k] = P(0);
+        } else {
+          const P d = v - A.acc_ref[k];
+          A.acc_s1[k] += d;
+          A.acc_s2[k] += d * d;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  P *dst = A.dst + cbase;
+  for (int f = threadIdx.x; f < iw * ih; f += kThreads) {
+    const int r = f / iw;
+    const int gx = x0 + (f - r * iw), gy = y0 + r;
+    const int lx = gx - ox, ly = gy - oy;
+    dst[(int64_t)gy * nx + gx] = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
+  }
+}
+
+template <typename P>
+hipError_t launch_sweep(const SweepArgs<P> &a, int64_t n_items, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_sweep<P>, dim3((unsigned)n_items), dim3(kThreads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, int64_t, size_t, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double> &, int64_t, size_t, hipStream_t);
+
+// -------------------------------------------------------------- pass end
+// One thread per chain: turn the pass's accepted counts into acceptance
+// ratios, write the trace, and apply the a-rule (Algorithm 2, step 4.2):
+// after sweep i, if the mean acceptance of the window ending there is below
+// A_targ, a = 1 + (i + 1)/k_a.  Then alpha = 2*pi/a for the next pass.
+__global__ void k_pass_end(const PassEndArgs A) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= A.total_chains) return;
+  int lo = 0, hi = A.n_grids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.grids[mid].chain_base <= ch) lo = mid;
+    else hi = mid - 1;
+  }
+  const GridDesc &G = A.grids[lo];
+  double a = A.a[ch];
+  for (int s = 0; s < A.nsw; ++s) {
+    const int64_t k = (int64_t)ch * kMaxPass + s;
+    const uint32_t cnt = A.counts[k];
+    A.counts[k] = 0;
+    const double acc = G.n_gap > 0 ? (double)cnt / (double)G.n_gap : 1.0;
+    A.accsum[ch] += acc;
+    double e = __builtin_nan("");
+    if (A.energy) {
+      e = A.energy[k] / (double)G.n_pairs - 1.0;
+      A.energy[k] = 0.0;
+    }
+    if (A.trace) {
+      double *tr = A.trace + ((A.trace_row0 + s) * A.total_chains + ch) * 2;
+      tr[0] = acc;
+      tr[1] = e;
+    }
+    if (A.adapt) {
+      const double win = A.window[ch] + acc;
+      const uint32_t i = A.sweep0 + (uint32_t)s;
+      if ((i + 1) % (uint32_t)A.adapt_every == 0) {
+        if (win / (double)A.adapt_every < A.a_targ) a = 1.0 + (double)(i + 1) / A.k_a;
+        A.window[ch] = 0.0;
+      } else {
+        A.window[ch] = win;
+      }
+    }
+  }
+  A.a[ch] = a;
+  A.alpha[ch] = 6.28318530717958647692 / a;
+}
+
+hipError_t launch_pass_end(const PassEndArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_end, dim3((a.total_chains + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ min / max of samples
+// Eq. (2) needs z_min, z_max over the samples of each grid.  Stage 1: one
+// workgroup per chunk of kChunk sites -> (min, max, #samples, #non-finite).
+__global__ void __launch_bounds__(kThreads)
+    k_minmax(const GridDesc *grids, int n_grids, const double *const *zp, const uint8_t *const *kp, double *part) {
+  __shared__ double smin[kThreads], smax[kThreads], scnt[kThreads], sbad[kThreads];
+  const int64_t b = blockIdx.x;
+  const int gi = find_by(grids, n_grids, b, &GridDesc::sb_begin);
+  const GridDesc &G = grids[gi];
+  const int64_t n = (int64_t)G.nx * G.ny;
+  const int64_t base = (b - G.sb_begin) * kChunk;
+  const double *z = zp[gi];
+  const uint8_t *kn = kp[gi];
+  double mn = INFINITY, mx = -INFINITY, cnt = 0, bad = 0;
+  for (int64_t i = base + threadIdx.x; i < min(base + kChunk, n); i += kThreads) {
+    if (kn[i]) {
+      const double v = z[i];
+      cnt += 1;
+      if (!isfinite(v)) bad += 1;
+      else {
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+      }
+    }
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  scnt[threadIdx.x] = cnt;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      scnt[threadIdx.x] += scnt[threadIdx.x + o];
+      sbad[threadIdx.x] += sbad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[b * 4 + 0] = smin[0];
+    part[b * 4 + 1] = smax[0];
+    part[b * 4 + 2] = scnt[0];
+    part[b * 4 + 3] = sbad[0];
+  }
+}
+
+// Stage 2: one workgroup per grid, partials in fixed order -> out[g*4 + ...].
+__global__ void __launch_bounds__(kThreads)
+    k_minmax_final(const GridDesc *grids, int n_grids, const double *part, double *out) {
+  __shared__ double smin[kThreads], smax[kThreads], scnt[kThreads], sbad[kThreads];
+  const int gi = blockIdx.x;
+  const GridDesc &G = grids[gi];
+  const int64_t nb = (gi + 1 < n_grids ? grids[gi + 1].sb_begin : G.sb_begin + ((int64_t)G.nx * G.ny + kChunk - 1) / kChunk) - G.sb_begin;
+  double mn = INFINITY, mx = -INFINITY, cnt = 0, bad = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kThreads) {
+    const double *p = part + (G.sb_begin + i) * 4;
+    mn = fmin(mn, p[0]);
+    mx = fmax(mx, p[1]);
+    cnt += p[2];
+    bad += p[3];
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  scnt[threadIdx.x] = cnt;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      scnt[threadIdx.x] += scnt[threadIdx.x + o];
+      sbad[threadIdx.x] += sbad[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[gi * 4 + 0] = smin[0];
+    out[gi * 4 + 1] = smax[0];
+    out[gi * 4 + 2] = scnt[0];
+    out[gi * 4 + 3] = sbad[0];
+  }
+}
+
+hipError_t launch_minmax(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
+                         const uint8_t *const *known, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, z, known, part);
+  return hipGetLastError();
+}
+hipError_t launch_minmax_final(const GridDesc *g, int n_grids, const double *part, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax_final, dim3((unsigned)n_grids), dim3(kThreads), 0, s, g, n_grids, part, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ init
+// Eq. (2) at the samples, hot start 2*pi*U at the gaps (Algorithm 2, steps
+// 1.8 and 2.1), written to both state buffers.  One workgroup per chunk of
+// one chain.  The hot start draws the u word of sweep 0xFFFFFFFF.
+template <typename P>
+__global__ void __launch_bounds__(kThreads)
+    k_init(const GridDesc *grids, int n_grids, const double *const *zp, const uint8_t *const *kp, P *s0, P *s1,
+           uint32_t k0, uint32_t k1) {
+  const int64_t b = blockIdx.x;
+  const int gi = find_by(grids, n_grids, b, &GridDesc::cb_begin);
+  const GridDesc &G = grids[gi];
+  const int64_t n = (int64_t)G.nx * G.ny;
+  const int64_t per_chain = (n + kChunk - 1) / kChunk;
+  const int64_t lb = b - G.cb_begin;
+  const int chain = (int)(lb / per_chain);
+  const int64_t base = (lb - (int64_t)chain * per_chain) * kChunk;
+  const double *z = zp[gi];
+  const uint8_t *kn = kp[gi];
+  const double zmin = G.zmin, span = G.zmax - G.zmin;
+  for (int64_t i = base + threadIdx.x; i < min(base + kChunk, n); i += kThreads) {
+    P v;
+    if (kn[i]) {
+      v = -(P)((z[i] - zmin) / span * 6.28318530717958647692);
+    } else {
+      const int y = (int)(i / G.nx), x = (int)(i - (int64_t)y * G.nx);
+      uint32_t w[4];
+      philox4x32_10((uint32_t)y * (uint32_t)G.npair + (uint32_t)(x >> 1), 0xFFFFFFFFu, (uint32_t)chain,
+                    (uint32_t)G.grid_id, k0, k1, w);
+      // Float angles are rounded to the nearest float; keep gaps below 2*pi.
+      v = (P)(6.28318530717958647692 * unit<double>((x & 1) ? w[2] : w[0]));
+      if (v >= Prec<P>::two_pi) v = Prec<P>::below_two_pi;
+    }
+    const int64_t k = G.state_off + (int64_t)chain * n + i;
+    s0[k] = v;
+    s1[k] = v;
+  }
+}
+
+template <typename P>
+hipError_t launch_init(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
+                       const uint8_t *const *known, P *s0, P *s1, P, uint32_t k0, uint32_t k1, hipStream_t s) {
+  hipLaunchKernelGGL(k_init<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, z, known, s0, s1, k0, k1);
+  return hipGetLastError();
+}
+template hipError_t launch_init<float>(const GridDesc *, int, int64_t, const double *const *, const uint8_t *const *,
+                                       float *, float *, float, uint32_t, uint32_t, hipStream_t);
+template hipError_t launch_init<double>(const GridDesc *, int, int64_t, const double *const *,
+                                        const uint8_t *const *, double *, double *, double, uint32_t, uint32_t,
+                                        hipStream_t);
+
+// --------------------------------------------------------------- energies
+// what = 0: Eq. (4) per grid over sample-sample pairs of chain 0;
+// what = 1: Eq. (5) per chain over all pairs.  Each site owns its right and
+// lower pair; terms 2 sin^2(q dphi / 2) are summed per thread in P and per
+// workgroup in FP64 -> part[b*2] = sum, part[b*2+1] = #pairs.
+template <typename P>
+__global__ void __launch_bounds__(kThreads)
+    k_energy(const GridDesc *grids, int n_grids, int what, const P *state, P q, double *part) {
+  __shared__ double red[kThreads / 64];
+  const int64_t b = blockIdx.x;
+  const int gi = find_by(grids, n_grids, b, what ? &GridDesc::cb_begin : &GridDesc::sb_begin);
+  const GridDesc &G = grids[gi];
+  const int nx = G.nx;
+  const int64_t n = (int64_t)nx * G.ny;
+  const int64_t per_chain = (n + kChunk - 1) / kChunk;
+  const int64_t lb = b - (what ? G.cb_begin : G.sb_begin);
+  const int chain = what ? (int)(lb / per_chain) : 0;
+  const int64_t base = (lb - (int64_t)chain * per_chain) * kChunk;
+  const P *st = state + G.state_off + (int64_t)chain * n;
+  P e = P(0);
+  double cnt = 0.0;
+  for (int64_t i = base + threadIdx.x; i < min(base + kChunk, n); i += kThreads) {
+    const int y = (int)(i / nx), x = (int)(i - (int64_t)y * nx);
+    const P v = st[i];
+    if (what == 0 && !signbit(v)) continue;
+    if (x + 1 < nx) {
+      const P w = st[i + 1];
+      if (what == 1 || signbit(w)) {
+        const P sn = Prec<P>::sin_(q * (fabs(v) - fabs(w)) * P(0.5));
+        e += P(2) * sn * sn;
+        cnt += 1.0;
+      }
+    }
+    if (y + 1 < G.ny) {
+      const P w = st[i + nx];
+      if (what == 1 || signbit(w)) {
+        const P sn = Prec<P>::sin_(q * (fabs(v) - fabs(w)) * P(0.5));
+        e += P(2) * sn * sn;
+        cnt += 1.0;
+      }
+    }
+  }
+  const double se = block_sum((double)e, red);
+  const double sc = block_sum(cnt, red);
+  if (threadIdx.x == 0) {
+    part[b * 2] = se;
+    part[b * 2 + 1] = sc;
+  }
+}
+
+// One workgroup per unit (grid or chain): fixed-order sum of its partials.
+__global__ void __launch_bounds__(kThreads)
+    k_energy_final(const GridDesc *grids, int n_grids, int what, const double *part, double *out) {
+  __shared__ double red[kThreads / 64];
+  const int unit = blockIdx.x;
+  int gi = 0, chain = 0;
+  if (what) {
+    int lo = 0, hi = n_grids - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (grids[mid].chain_base <= unit) lo = mid;
+      else hi = mid - 1;
+    }
+    gi = lo;
+    chain = unit - grids[gi].chain_base;
+  } else {
+    gi = unit;
+  }
+  const GridDesc &G = grids[gi];
+  const int64_t per_chain = ((int64_t)G.nx * G.ny + kChunk - 1) / kChunk;
+  const int64_t b0 = (what ? G.cb_begin + chain * per_chain : G.sb_begin);
+  double e = 0.0, c = 0.0;
+  for (int64_t i = threadIdx.x; i < per_chain; i += kThreads) {
+    e += part[(b0 + i) * 2];
+    c += part[(b0 + i) * 2 + 1];
+  }
+  const double se = block_sum(e, red);
+  const double sc = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    out[unit * 2] = se;
+    out[unit * 2 + 1] = sc;
+  }
+}
+
+template <typename P>
+hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q,
+                         double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, what, state, q, part);
+  return hipGetLastError();
+}
+template hipError_t launch_energy<float>(const GridDesc *, int, int64_t, int, const float *, float, double *,
+                                         hipStream_t);
+template hipError_t launch_energy<double>(const GridDesc *, int, int64_t, int, const double *, double, double *,
+                                          hipStream_t);
+hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
+                               double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_final, dim3((unsigned)n_units), dim3(kThreads), 0, s, g, n_grids, what, part, out);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- finalize
+// Per site of each grid: pool the chains' recorded states (mean and
+// variance about each chain's first record), then map back with the
+// inverse of Eq. (2).  Samples: z and 0.
+template <typename P>
+__global__ void __launch_bounds__(kThreads)
+    k_finalize(const GridDesc *grids, int n_grids, const double *const *zp, const P *state, const P *ref, const P *s1,
+               const P *s2, int32_t records, double *zhat, double *zstd) {
+  const int64_t b = blockIdx.x;
+  const int gi = find_by(grids, n_grids, b, &GridDesc::sb_begin);
+  const GridDesc &G = grids[gi];
+  const int64_t n = (int64_t)G.nx * G.ny;
+  const int64_t base = (b - G.sb_begin) * kChunk;
+  const double *z = zp[gi];
+  const double M = (double)records, C = (double)G.chains;
+  for (int64_t i = base + threadIdx.x; i < min(base + kChunk, n); i += kThreads) {
+    const int64_t o = G.site_off + i;
+    if (signbit(state[G.state_off + i])) {
+      zhat[o] = z[i];
+      if (zstd) zstd[o] = 0.0;
+      continue;
+    }
+    double mean = 0.0;
+    for (int c = 0; c < G.chains; ++c) {
+      const int64_t k = G.state_off + (int64_t)c * n + i;
+      mean += (double)ref[k] + (double)s1[k] / M;
+    }
+    mean /= C;
+    double var = 0.0;
+    for (int c = 0; c < G.chains; ++c) {
+      const int64_t k = G.state_off + (int64_t)c * n + i;
+      const double m1 = (double)s1[k] / M;
+      const double mc = (double)ref[k] + m1;
+      const double vc = fmax((double)s2[k] / M - m1 * m1, 0.0);
+      var += vc + (mc - mean) * (mc - mean);
+    }
+    var /= C;
+    const double span = G.zmax - G.zmin;
+    zhat[o] = G.zmin + span * (mean / 6.28318530717958647692);
+    if (zstd) zstd[o] = span / 6.28318530717958647692 * sqrt(var);
+  }
+}
+
+template <typename P>
+hipError_t launch_finalize(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z, const P *state,
+                           const P *ref, const P *s1, const P *s2, int32_t records, double *zhat, double *zstd,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, z, state, ref, s1, s2,
+                     records, zhat, zstd);
+  return hipGetLastError();
+}
+template hipError_t launch_finalize<float>(const GridDesc *, int, int64_t, const double *const *, const float *,
+                                           const float *, const float *, const float *, int32_t, double *, double *,
+                                           hipStream_t);
+template hipError_t launch_finalize<double>(const GridDesc *, int, int64_t, const double *const *, const double *,
+                                            const double *, const double *, const double *, int32_t, double *,
+                                            double *, hipStream_t);
+
+// ------------------------------------------------------------ state copies
+template <typename P> __global__ void k_get_phi(const P *st, int64_t n, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = fabs((double)st[i]);
+}
+template <typename P> __global__ void k_set_phi(P *s0, P *s1, int64_t n, const double *in) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || signbit(s0[i])) return;  // sample sites keep their angle
+  P v = (P)in[i];
+  v = (v > P(0)) ? v : P(0);  // also turns -0 into +0
+  if (v >= Prec<P>::two_pi) v = Prec<P>::below_two_pi;
+  s0[i] = v;
+  s1[i] = v;
+}
+template <typename P> hipError_t launch_get_phi(const P *st, int64_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_get_phi<P>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, st, n, out);
+  return hipGetLastError();
+}
+template <typename P> hipError_t launch_set_phi(P *s0, P *s1, int64_t n, const double *in, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_phi<P>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, s0, s1, n,
+                     in);
+  return hipGetLastError();
+}
+template hipError_t launch_get_phi<float>(const float *, int64_t, double *, hipStream_t);
+template hipError_t launch_get_phi<double>(const double *, int64_t, double *, hipStream_t);
+template hipError_t launch_set_phi<float>(float *, float *, int64_t, const double *, hipStream_t);
+template hipError_t launch_set_phi<double>(double *, double *, int64_t, const double *, hipStream_t);
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace mpr

@@ -1,0 +1,306 @@
+"""Python binding of libmpr (include/mpr.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels (or, for mpr_match_T,
+its native host code).  PyTorch provides device memory and the stream.
+Importing this module loads libmpr.so built in place by
+``python -m paper_1710_03038_amd.build``; it raises if the library is
+missing: there is no fallback.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpr.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mpr.h")
+
+MPR_OK, MPR_E_ARG, MPR_E_SHAPE, MPR_E_DEGENERATE, MPR_E_NOPAIRS, MPR_E_RANGE, \
+    MPR_E_WORKSPACE, MPR_E_HIP, MPR_E_STATE = range(9)
+STATUS_NAMES = ["MPR_OK", "MPR_E_ARG", "MPR_E_SHAPE", "MPR_E_DEGENERATE", "MPR_E_NOPAIRS",
+                "MPR_E_RANGE", "MPR_E_WORKSPACE", "MPR_E_HIP", "MPR_E_STATE"]
+FP32, FP64 = 0, 1
+ADAPT, TRACE_E = 1, 2
+SAMPLE_PAIRS, STATE = 0, 1
+
+
+class MPRError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 9 else status}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("a_targ", ctypes.c_double), ("k_a", ctypes.c_double),
+                ("adapt_every", ctypes.c_int32), ("a_sample_keep", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("sweeps_per_pass", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("chains", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("z", ctypes.c_void_p), ("known", ctypes.c_void_p)]
+
+
+class FillReport(ctypes.Structure):
+    _fields_ = [("records", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("a_eq", ctypes.c_void_p), ("acc_eq", ctypes.c_void_p), ("acc_samp", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmpr.so (ctypes.CDLL).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_03038_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.mpr_default_params.argtypes = [ctypes.POINTER(Params)]
+        L.mpr_default_params.restype = None
+        L.mpr_init_field.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), vp,
+                                     ctypes.POINTER(ctypes.c_size_t), vp]
+        L.mpr_sweep.argtypes = [vp, i32, dp, u32, vp]
+        L.mpr_specific_energy.argtypes = [vp, i32, dp, ctypes.POINTER(i64)]
+        L.mpr_match_T.argtypes = [dp, i32, dp, dp, i32, dp, ctypes.POINTER(i32)]
+        L.mpr_fill.argtypes = [vp, dp, i32, i32, i32, vp, vp, ctypes.POINTER(FillReport)]
+        L.mpr_get_phi.argtypes = [vp, i32, i32, vp]
+        L.mpr_set_phi.argtypes = [vp, i32, i32, vp]
+        L.mpr_get_chain_state.argtypes = [vp, ctypes.POINTER(i64), dp]
+        L.mpr_set_chain_state.argtypes = [vp, i64, dp]
+        L.mpr_set_timing.argtypes = [vp, i32]
+        L.mpr_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.mpr_destroy.argtypes = [vp]
+        L.mpr_destroy.restype = None
+        L.mpr_last_error.argtypes = [vp]
+        L.mpr_last_error.restype = ctypes.c_char_p
+        for name in ("mpr_init_field", "mpr_sweep", "mpr_specific_energy", "mpr_match_T", "mpr_fill",
+                     "mpr_get_phi", "mpr_set_phi", "mpr_get_chain_state", "mpr_set_chain_state",
+                     "mpr_set_timing", "mpr_get_timing"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions(path=HEADER):
+    """Names of the functions declared in include/mpr.h."""
+    with open(path) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:mpr_status|void|const char \*)\s*(mpr_\w+)\s*\(", text, re.M)))
+
+
+def _check(status, ctx=None):
+    if status != MPR_OK:
+        msg = lib().mpr_last_error(ctx).decode()
+        raise MPRError(status, msg)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def default_params(**overrides):
+    p = Params()
+    lib().mpr_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k == "dtype" and isinstance(v, str):
+            v = {"fp32": FP32, "fp64": FP64}[v]
+        setattr(p, k, v)
+    return p
+
+
+def match_T(e_s, tab_T, tab_e, raise_on_range=False):
+    """Specific energy matching on a table (mpr_match_T).  Returns (T, status)."""
+    e_s = np.ascontiguousarray(np.atleast_1d(e_s), dtype=np.float64)
+    tab_T = np.ascontiguousarray(tab_T, dtype=np.float64)
+    tab_e = np.ascontiguousarray(tab_e, dtype=np.float64)
+    T = np.empty_like(e_s)
+    st = np.zeros(e_s.shape, dtype=np.int32)
+    rc = lib().mpr_match_T(_dptr(e_s), len(e_s), _dptr(tab_T), _dptr(tab_e), len(tab_T), _dptr(T),
+                           st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc not in (MPR_OK, MPR_E_RANGE) or (rc == MPR_E_RANGE and raise_on_range):
+        _check(rc)
+    return T, st
+
+
+def workspace_bytes(shapes, params):
+    """Workspace needed for grids given as (ny, nx, chains) tuples."""
+    gs = (Grid * len(shapes))()
+    for g, (ny, nx, ch) in zip(gs, shapes):
+        g.nx, g.ny, g.chains, g.reserved = nx, ny, ch, 0
+    n = ctypes.c_size_t(0)
+    _check(lib().mpr_init_field(None, gs, len(shapes), ctypes.byref(params), None, ctypes.byref(n), None))
+    return n.value
+
+
+class Field:
+    """A batch of gappy grids under simulation: one mpr_ctx and its workspace.
+
+    grids: list of (z, known, chains) with z a CUDA float64 tensor (ny, nx)
+    and known a CUDA uint8 tensor (ny, nx).  The tensors are kept alive
+    with the context.
+    """
+
+    def __init__(self, grids, params=None, stream=None):
+        import torch
+
+        self._torch = torch
+        self.params = params if params is not None else default_params()
+        self._keep = []
+        self.shapes = []
+        gs = (Grid * len(grids))()
+        dev = None
+        for g, (z, known, chains) in zip(gs, grids):
+            if not (z.is_cuda and known.is_cuda):
+                raise ValueError("z and known must be CUDA tensors")
+            z = z.contiguous().to(torch.float64)
+            known = known.contiguous().to(torch.uint8)
+            if z.shape != known.shape or z.dim() != 2:
+                raise ValueError("z and known must be 2-D tensors of one shape")
+            dev = z.device
+            ny, nx = z.shape
+            g.nx, g.ny, g.chains, g.reserved = nx, ny, int(chains), 0
+            g.z, g.known = z.data_ptr(), known.data_ptr()
+            self._keep += [z, known]
+            self.shapes.append((ny, nx, int(chains)))
+        self.device = dev
+        self.n_grids = len(grids)
+        self.total_chains = sum(s[2] for s in self.shapes)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        n = ctypes.c_size_t(0)
+        _check(lib().mpr_init_field(None, gs, len(grids), ctypes.byref(self.params), None, ctypes.byref(n), None))
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        size = ctypes.c_size_t(n.value)
+        ctx = ctypes.c_void_p()
+        _check(lib().mpr_init_field(ctypes.byref(ctx), gs, len(grids), ctypes.byref(self.params),
+                                    ctypes.c_void_p(aligned), ctypes.byref(size),
+                                    ctypes.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            lib().mpr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _T(self, T):
+        T = np.broadcast_to(np.asarray(T, dtype=np.float64), (self.n_grids,))
+        return np.ascontiguousarray(T)
+
+    # -- Algorithm 1
+    def sweep(self, n_sweeps, T, adapt=False, trace_energy=False, trace=False):
+        """Run n hybrid sweeps.  Returns a (n, chains, 2) tensor of (A, e) per
+        sweep when ``trace`` (e is NaN unless ``trace_energy``)."""
+        torch = self._torch
+        T = self._T(T)
+        tr = torch.empty((n_sweeps, self.total_chains, 2), dtype=torch.float64, device=self.device) if trace else None
+        flags = (ADAPT if adapt else 0) | (TRACE_E if trace_energy else 0)
+        _check(lib().mpr_sweep(self.ctx, n_sweeps, _dptr(T), flags,
+                               ctypes.c_void_p(tr.data_ptr() if tr is not None else 0)), self.ctx)
+        return tr
+
+    # -- Eqs. (4), (5)
+    def specific_energy(self, what=SAMPLE_PAIRS, allow_nopairs=False):
+        n = self.n_grids if what == SAMPLE_PAIRS else self.total_chains
+        e = np.empty(n)
+        cnt = np.empty(n, dtype=np.int64)
+        rc = lib().mpr_specific_energy(self.ctx, what, _dptr(e), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        if not (rc == MPR_E_NOPAIRS and allow_nopairs):
+            _check(rc, self.ctx)
+        return e, cnt
+
+    # -- Algorithm 2
+    def fill(self, T, n_eq, n_samp, stride=1, want_std=True):
+        """Returns (zhat list, zstd list or None, report dict)."""
+        torch = self._torch
+        T = self._T(T)
+        total = sum(ny * nx for ny, nx, _ in self.shapes)
+        zhat = torch.empty(total, dtype=torch.float64, device=self.device)
+        zstd = torch.empty(total, dtype=torch.float64, device=self.device) if want_std else None
+        a_eq = np.empty(self.total_chains)
+        acc_eq = np.empty(self.total_chains)
+        acc_samp = np.empty(self.total_chains)
+        rep = FillReport(0, 0, a_eq.ctypes.data, acc_eq.ctypes.data, acc_samp.ctypes.data)
+        _check(lib().mpr_fill(self.ctx, _dptr(T), n_eq, n_samp, stride, ctypes.c_void_p(zhat.data_ptr()),
+                              ctypes.c_void_p(zstd.data_ptr() if zstd is not None else 0), ctypes.byref(rep)), self.ctx)
+        out_h, out_s, off = [], [], 0
+        for ny, nx, _ in self.shapes:
+            out_h.append(zhat[off:off + ny * nx].view(ny, nx))
+            if zstd is not None:
+                out_s.append(zstd[off:off + ny * nx].view(ny, nx))
+            off += ny * nx
+        return out_h, (out_s if zstd is not None else None), dict(
+            records=rep.records, a_eq=a_eq, acc_eq=acc_eq, acc_samp=acc_samp)
+
+    # -- state
+    def get_phi(self, grid=0, chain=0):
+        torch = self._torch
+        ny, nx, _ = self.shapes[grid]
+        out = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        _check(lib().mpr_get_phi(self.ctx, grid, chain, ctypes.c_void_p(out.data_ptr())), self.ctx)
+        return out
+
+    def set_phi(self, phi, grid=0, chain=0):
+        torch = self._torch
+        ny, nx, _ = self.shapes[grid]
+        t = torch.as_tensor(phi, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (ny, nx):
+            raise ValueError("phi shape mismatch")
+        _check(lib().mpr_set_phi(self.ctx, grid, chain, ctypes.c_void_p(t.data_ptr())), self.ctx)
+        self.stream.synchronize()
+
+    def set_timing(self, enable=True):
+        _check(lib().mpr_set_timing(self.ctx, 1 if enable else 0), self.ctx)
+
+    def timing(self):
+        """(milliseconds in sweep kernels, launches, site-sweeps) since the
+        last call; resets the sums."""
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        ss = ctypes.c_int64(0)
+        _check(lib().mpr_get_timing(self.ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(ss)), self.ctx)
+        return ms.value, n.value, ss.value
+
+    def chain_state(self):
+        idx = ctypes.c_int64(0)
+        a = np.empty(self.total_chains)
+        _check(lib().mpr_get_chain_state(self.ctx, ctypes.byref(idx), _dptr(a)), self.ctx)
+        return idx.value, a
+
+    def set_chain_state(self, sweep_index, a=None):
+        ap = None
+        if a is not None:
+            a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.total_chains,)))
+            ap = _dptr(a)
+        _check(lib().mpr_set_chain_state(self.ctx, int(sweep_index), ap), self.ctx)
+
+
+def temperatures_from_table(e_s, table_T, table_e):
+    """T-hat per grid by mpr_match_T; NaN e_s raise."""
+    T, st = match_T(e_s, table_T, table_e)
+    if np.any(np.isnan(T)):
+        raise MPRError(MPR_E_ARG, "e_s is NaN")
+    return T, st
+
+
+TWO_PI = 2.0 * math.pi

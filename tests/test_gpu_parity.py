@@ -1,0 +1,324 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Per-sweep parity is teacher-forced: the oracle's state is loaded into the
+library, one pass is run on both sides with the same Philox stream, and the
+angles are compared site by site (FP64: 1e-5 rad at every site; FP32:
+1e-3 rad except flips explained by a decision within 1e-4 of its threshold).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import mpr as om
+from tests.gpu_util import (TWO_PI, as_fp32_state, beta_of, explained_mismatches, make_field, oracle_init,
+                            random_grid)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 64), (45, 67), (1, 9), (3, 3), (130, 33)]
+
+
+def _grids(seed, chains=2):
+    out = []
+    for k, (ny, nx) in enumerate(SHAPES):
+        z, known = random_grid(ny, nx, 0.4, seed + 10 * k, smooth=True)
+        out.append((z, known, chains))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_init_transform_and_hot_start(dtype):
+    seed = 1234567
+    grids = _grids(5)
+    f = make_field(grids, dtype=dtype, seed=seed)
+    for g, (z, known, chains) in enumerate(grids):
+        for c in range(chains):
+            ref = oracle_init(z, known, seed, c, g, dtype)
+            got = f.get_phi(g, c).cpu().numpy()
+            assert np.array_equal(got, ref), (g, c, np.abs(got - ref).max())
+            gap = ~known.astype(bool)
+            assert np.all(got[gap] < TWO_PI) and np.all(got >= 0)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_specific_energies(dtype):
+    q = 0.5
+    grids = _grids(7)
+    f = make_field(grids, dtype=dtype, seed=3)
+    e, n = f.specific_energy(0)
+    for g, (z, known, _) in enumerate(grids):
+        phi0 = oracle_init(z, known, 3, 0, g, dtype)
+        try:
+            es, eps, ns = om.sample_specific_energy(phi0, known.astype(bool), q)
+        except om.OracleError:
+            assert math.isnan(e[g]) and n[g] == 0
+            continue
+        assert n[g] == ns
+        tol = 1e-12 if dtype == "fp64" else 2e-6
+        assert abs((1 + e[g]) - eps) <= tol * eps + 1e-15, (g, e[g], es)
+    e, n = f.specific_energy(1)
+    k = 0
+    for g, (z, known, chains) in enumerate(grids):
+        for c in range(chains):
+            phi = oracle_init(z, known, 3, c, g, dtype)
+            ref, eps = om.state_specific_energy(phi, q)
+            assert n[k] == om.n_pairs(*phi.shape)
+            tol = 1e-12 if dtype == "fp64" else 2e-6
+            assert abs((1 + e[k]) - eps) <= tol * eps, (g, c)
+            k += 1
+
+
+CASES = [(0.3, 1.0), (0.02, 5.0), (1e-3, 40.0), (math.inf, 1.0), (0.0, 3.0)]
+
+
+def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11):
+    grids = _grids(21)
+    f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw)
+    C = f.total_chains
+    results = []
+    for T, a in CASES:
+        # evolve the oracle a little so that the state is not the hot start
+        states = []
+        for g, (z, known, chains) in enumerate(grids):
+            phi = np.stack([oracle_init(z, known, seed, c, g, "fp64") for c in range(chains)])
+            phi, _, _, _ = om.run_sweeps(phi, known.astype(bool), 0.05, 2.0, 0.5, seed, 0, 2, np.arange(chains), g)
+            if dtype == "fp32":
+                phi = np.stack([as_fp32_state(p, known) for p in phi])
+            states.append(phi)
+            for c in range(chains):
+                f.set_phi(phi[c], g, c)
+        f.set_chain_state(sweep_index, np.full(C, a))
+        tr = f.sweep(nsw, np.full(len(grids), T), trace=True).cpu().numpy()
+        k = 0
+        for g, (z, known, chains) in enumerate(grids):
+            beta = beta_of(T)
+            phi = states[g]
+            margins = {}
+            accs = []
+            for s in range(nsw):
+                phi, acc = om.hybrid_sweep(phi, known.astype(bool), [beta] * chains, [TWO_PI / a] * chains, 0.5,
+                                           seed, sweep_index + s, np.arange(chains), g, margins=margins)
+                accs.append(acc)
+            for c in range(chains):
+                got = f.get_phi(g, c).cpu().numpy()
+                results.append((T, a, g, c, got, phi[c], margins, known,
+                                [tr[s, k, 0] for s in range(nsw)], [x[c] for x in accs]))
+                k += 1
+    return results
+
+
+@pytest.mark.parametrize("tile,nsw", [((32, 32), 1), ((16, 24), 3), ((40, 24), 2)])
+def test_teacher_forced_sweep_fp64(tile, nsw):
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp64", tile, nsw):
+        d = np.abs(got - ref).max()
+        assert d <= 1e-5, (T, a, g, c, d)
+        n_gap = int((~known.astype(bool)).sum())
+        for s in range(nsw):
+            if n_gap:
+                assert A[s] * n_gap == pytest.approx(acc[s], abs=1e-6), (T, a, g, c, s)
+        if T == math.inf:
+            assert all(x == 1.0 for x in A)
+
+
+@pytest.mark.parametrize("tile,nsw", [((64, 64), 1), ((16, 16), 2)])
+def test_teacher_forced_sweep_fp32(tile, nsw):
+    total_gap = total_bad = 0
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp32", tile, nsw):
+        if nsw == 1:
+            n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+            assert len(unexpl) == 0, (T, a, g, c, unexpl[:5], got[tuple(unexpl[0])], ref[tuple(unexpl[0])])
+        else:
+            # after several sweeps flips propagate; compare only the share of close sites
+            n_bad = int(((np.abs(got - ref) > 1e-3) & ~known.astype(bool)).sum())
+        total_bad += n_bad
+        total_gap += int((~known.astype(bool)).sum())
+    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_frozen_sites_bit_identical(dtype):
+    grids = _grids(31)
+    f = make_field(grids, dtype=dtype, seed=9)
+    before = [[f.get_phi(g, c).cpu().numpy() for c in range(gr[2])] for g, gr in enumerate(grids)]
+    f.sweep(25, [0.01, 0.2, 1.0, math.inf, 0.0], adapt=True)
+    for g, (z, known, chains) in enumerate(grids):
+        kn = known.astype(bool)
+        for c in range(chains):
+            after = f.get_phi(g, c).cpu().numpy()
+            assert np.array_equal(after[kn], before[g][c][kn])
+            assert np.all(after[~kn] >= 0) and np.all(after[~kn] < TWO_PI)
+
+
+TILINGS = {"fp32": (((16, 16), 1), ((64, 64), 2), ((8, 24), 2), ((32, 16), 4)),
+           "fp64": (((16, 16), 1), ((32, 32), 2), ((8, 24), 2), ((16, 16), 4))}
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_tiling_and_fusion_do_not_change_results(dtype):
+    grids = _grids(41, chains=3)
+    outs = []
+    for tile, nsw in TILINGS[dtype]:
+        f = make_field(grids, dtype=dtype, seed=5, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw)
+        f.set_chain_state(0, np.full(f.total_chains, 3.0))
+        f.sweep(8, [0.05, 0.1, 0.5, 2.0, 0.01])
+        outs.append([f.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
+def test_adaptation_matches_oracle_fp64():
+    z, known = random_grid(48, 40, 0.5, 3)
+    kn = known.astype(bool)
+    seed = 2024
+    f = make_field([(z, known, 2)], dtype="fp64", seed=seed, tile_x=16, tile_y=16)
+    phi = np.stack([oracle_init(z, known, seed, c, 0, "fp64") for c in range(2)])
+    T = 2e-3
+    a = np.ones(2)
+    for i in range(6):
+        phi, a, acc, _ = om.run_sweeps(phi, kn, T, a, 0.5, seed, i, 1, np.arange(2), 0, adapt=True)
+        tr = f.sweep(1, [T], adapt=True, trace=True).cpu().numpy()
+        idx, a_gpu = f.chain_state()
+        assert idx == i + 1
+        np.testing.assert_allclose(tr[0, :, 0], acc[0], rtol=0, atol=1e-12)
+        np.testing.assert_array_equal(a_gpu, a)
+    got = np.stack([f.get_phi(0, c).cpu().numpy() for c in range(2)])
+    assert np.abs(got - phi).max() < 1e-5
+
+
+def test_energy_trace_matches_state_energy():
+    grids = _grids(51)
+    f = make_field(grids, dtype="fp64", seed=4)
+    tr = f.sweep(3, [0.1] * len(grids), trace=True, trace_energy=True).cpu().numpy()
+    e, _ = f.specific_energy(1)
+    np.testing.assert_allclose(tr[-1, :, 1], e, rtol=1e-12, atol=1e-14)
+
+
+def test_checkpoint_resume_is_bit_exact():
+    grids = _grids(61)
+    p = dict(dtype="fp32", seed=8)
+    f1 = make_field(grids, **p)
+    f1.sweep(6, [0.05] * len(grids), adapt=True)
+    full = [f1.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
+    f2 = make_field(grids, **p)
+    f2.sweep(3, [0.05] * len(grids), adapt=True)
+    idx, a = f2.chain_state()
+    mid = [(g, c, f2.get_phi(g, c)) for g, gr in enumerate(grids) for c in range(gr[2])]
+    f3 = make_field(grids, **p)
+    for g, c, ph in mid:
+        f3.set_phi(ph, g, c)
+    f3.set_chain_state(idx, a)
+    f3.sweep(3, [0.05] * len(grids), adapt=True)
+    res = [f3.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
+    for a_, b_ in zip(full, res):
+        assert np.array_equal(a_, b_)
+
+
+# ---------------------------------------------------------------- exact laws
+def _batched_final_states(known, vals, T, a, sweeps, chains, dtype, seed):
+    z = np.where(known.astype(bool), vals, 0.0)
+    f = make_field([(z, known, chains)], dtype=dtype, seed=seed)
+    f.set_chain_state(0, np.full(chains, a))
+    f.sweep(sweeps, [T])
+    import torch
+    return torch.stack([f.get_phi(0, c) for c in range(chains)]).cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("T,a", [(0.1, 1.0), (0.5, 3.0)])
+def test_exact_3x3_corners_frozen(dtype, T, a):
+    from tests.test_oracle_pins import chi2_pvalue
+    # corner values chosen so that z_min -> 0 and z_max -> 2*pi exactly
+    known = np.zeros((3, 3), np.uint8)
+    vals = np.zeros((3, 3))
+    for (y, x), v in {(0, 0): 0.0, (0, 2): 2.0, (2, 0): 4.0, (2, 2): TWO_PI}.items():
+        known[y, x] = 1
+        vals[y, x] = v
+    corners = {(0, 0): 0.0, (0, 2): 2.0, (2, 0): 4.0, (2, 2): TWO_PI}
+    phi = _batched_final_states(known, vals, T, a, 150, 4096, dtype, 11)
+    pc, pe = exact.corners_frozen_bins(corners, 1.0 / T, 0.5, nbins=8)
+    counts, _ = np.histogram(phi[:, 1, 1], bins=8, range=(0, TWO_PI))
+    assert chi2_pvalue(counts, pc) > 1e-3, (counts, pc * 4096)
+    for (y, x), p in pe.items():
+        counts, _ = np.histogram(phi[:, y, x], bins=8, range=(0, TWO_PI))
+        assert chi2_pvalue(counts, p) > 1e-3, ((y, x), counts, p * 4096)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_exact_3x3_free_energy(dtype):
+    T, C = 0.3, 4096
+    known = np.zeros((3, 3), np.uint8)
+    phi = _batched_final_states(known, np.zeros((3, 3)), T, 1.0, 200, C, dtype, 13)
+    e = om.state_specific_energy(phi, 0.5)[0]
+    ref = exact.free3x3_specific_energy(1.0 / T, 0.5)
+    assert abs(e.mean() - ref) < 4 * e.std() / math.sqrt(C)
+
+
+def test_exact_1d_q1_bessel():
+    from paper_1710_03038_amd import mpr as M
+    T, C, n = 0.5, 2048, 8
+    known = np.zeros((1, n), np.uint8)
+    import torch
+    f = make_field([(np.zeros((1, n)), known, C)], dtype="fp32", seed=17, q=1.0)
+    f.sweep(150, [T])
+    e, _ = f.specific_energy(M.STATE)
+    ref = exact.chain1d_energy_q1(1.0 / T)
+    assert abs(e.mean() - ref) < 4 * e.std() / math.sqrt(C)
+    del torch
+
+
+# ---------------------------------------------------------------- fill
+def test_fill_fp64_statistics_match_oracle():
+    import mprgen
+    from oracle.etable import load_table
+    tT, te, _ = load_table()
+    z = mprgen.gaussian_field(32, 32, 4.0, 5, 50.0, 10.0)
+    known = mprgen.mask_random(32, 32, 0.33, 6)
+    kn = known.astype(bool)
+    maes_g, maes_o = [], []
+    for r in range(8):
+        seed = 900 + r
+        f = make_field([(z, known, 1)], dtype="fp64", seed=seed)
+        e_s, _ = f.specific_energy(0)
+        That, _ = om.match_T(e_s, tT, te)
+        phi_s, _, _ = om.transform(z, kn)
+        eo, _, _ = om.sample_specific_energy(phi_s, kn, 0.5)
+        assert abs(e_s[0] - eo) < 1e-13
+        zh, zs, rep = f.fill(That, 30, 30, 1)
+        zh = zh[0].cpu().numpy()
+        assert rep["records"] == 30
+        assert np.array_equal(zh[kn], z[kn]) and np.all(zs[0].cpu().numpy()[kn] == 0)
+        out = om.fill(z, kn, That[0], 30, 30, 1, seed=seed)
+        maes_g.append(om.mae(z, zh, ~kn))
+        maes_o.append(om.mae(z, out["z_hat"], ~kn))
+    mg, mo = np.mean(maes_g), np.mean(maes_o)
+    sg = np.std(maes_g, ddof=1) / math.sqrt(len(maes_g))
+    so = np.std(maes_o, ddof=1) / math.sqrt(len(maes_o))
+    assert abs(mg - mo) <= 3 * math.hypot(sg, so) + 1e-12, (mg, mo, sg, so)
+
+
+# ---------------------------------------------------------------- errors
+def test_error_paths_on_device():
+    from paper_1710_03038_amd import mpr as M
+    z = np.full((8, 8), 3.0)
+    known = np.ones((8, 8), np.uint8)
+    with pytest.raises(M.MPRError) as ei:
+        make_field([(z, known, 1)])
+    assert ei.value.status == M.MPR_E_DEGENERATE
+    z2, k2 = random_grid(8, 8, 0.3, 1)
+    z2[k2.astype(bool).nonzero()[0][0], k2.astype(bool).nonzero()[1][0]] = math.nan
+    with pytest.raises(M.MPRError) as ei:
+        make_field([(z2, k2, 1)])
+    assert ei.value.status == M.MPR_E_ARG
+    # unconditional grid: allowed, but no Eq. (4) and no fill
+    f = make_field([(np.zeros((8, 8)), np.zeros((8, 8), np.uint8), 1)])
+    e, n = f.specific_energy(0, allow_nopairs=True)
+    assert math.isnan(e[0]) and n[0] == 0
+    with pytest.raises(M.MPRError) as ei:
+        f.fill([0.1], 1, 1, 1)
+    assert ei.value.status == M.MPR_E_DEGENERATE
+    with pytest.raises(M.MPRError) as ei:
+        f.sweep(1, [-1.0])
+    assert ei.value.status == M.MPR_E_ARG
