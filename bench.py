@@ -158,7 +158,7 @@ def main():
         "config": {"workload": args.workload, "grid": [spec["n"], spec["n"]], "gap_fraction": p,
                    "field": spec["field"], "corr_len": spec["corr_len"], "mask": spec["mask"], "chains": chains,
                    "n_eq": spec["n_eq"], "n_samp": spec["n_samp"], "stride": spec["stride"],
-                   "sweeps_per_pass": prm32.sweeps_per_pass or 1, "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
+                   "sweeps_per_pass": prm32.sweeps_per_pass or 8, "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
                    "T_hat": out32[3], "e_s": out32[4]},
         "realisations_per_s": records / dt32,
         "mae_fp32": mae32,

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -30,13 +31,16 @@ struct Views {
   uint32_t *counts = nullptr;
   double *energy = nullptr;
   double *part = nullptr, *out = nullptr;
+  uint16_t *plan = nullptr;
+  uint32_t *plan_cum = nullptr;
 };
 
 struct Plan {
   std::vector<GridDesc> gd;
   int total_chains = 0;
   int64_t n_items = 0, n_cblocks = 0, n_sblocks = 0, state_elems = 0, sites = 0;
-  int tile_x = 0, tile_y = 0;
+  int64_t n_tiles = 0, plan_entries = 0;
+  int tile_x = 0, tile_y = 0, nsw_max = 1, dmax = 2;
   size_t elem = 0;
   size_t bytes = 0;
   Views v;  // offsets from the workspace base until bound
@@ -53,6 +57,7 @@ struct mpr_ctx {
   int cur = 0;                 // index of the state buffer holding the current angles
   int64_t sweep_index = 0;     // global sweep counter (keys the random stream)
   int nsw_max = 1;
+  int threads = 256;           // workgroup size of the sweep kernel
   size_t lds_limit = 65536;
   std::vector<double> beta_h;  // staging for per-chain inverse temperatures
   std::string err;
@@ -100,8 +105,8 @@ mpr_status check_params(const mpr_params *p) {
   if (p->sweeps_per_pass < 0 || p->sweeps_per_pass > kMaxPass)
     return fail(nullptr, MPR_E_ARG, "sweeps_per_pass must lie in [0, 16]");
   for (int t : {p->tile_x, p->tile_y})
-    if (t != 0 && (t < 8 || t > 256 || (t & 1)))
-      return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 256]");
+    if (t != 0 && (t < 8 || t > kMaxTile || (t & 1)))
+      return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 192]");
   return MPR_OK;
 }
 
@@ -112,6 +117,10 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   pl.elem = p->dtype == MPR_FP64 ? 8 : 4;
   pl.tile_x = p->tile_x ? p->tile_x : (p->dtype == MPR_FP64 ? 32 : 64);
   pl.tile_y = p->tile_y ? p->tile_y : (p->dtype == MPR_FP64 ? 32 : 64);
+  // Default: 8 sweeps per pass in FP32 (64 x 64 tiles fit in LDS with the
+  // 17-site halo), 1 in FP64 (the plain reference arm).
+  pl.nsw_max = p->sweeps_per_pass ? p->sweeps_per_pass : (p->dtype == MPR_FP64 ? 1 : 8);
+  pl.dmax = 2 * pl.nsw_max;
   int64_t chains = 0;
   for (int g = 0; g < n; ++g) {
     const mpr_grid &G = grids[g];
@@ -133,6 +142,9 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
     const int64_t sites = (int64_t)G.nx * G.ny;
     const int64_t per_chain_blocks = (sites + kChunk - 1) / kChunk;
     d.item_begin = pl.n_items;
+    d.plan_begin = pl.n_tiles;
+    d.plan_ebase = pl.plan_entries;
+    d.plan_cap = (int64_t)std::min(pl.tile_x + 2 * pl.dmax, G.nx) * std::min(pl.tile_y + 2 * pl.dmax, G.ny);
     d.cb_begin = pl.n_cblocks;
     d.sb_begin = pl.n_sblocks;
     d.state_off = pl.state_elems;
@@ -140,6 +152,8 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
     d.n_pairs = (int64_t)G.ny * (G.nx - 1) + (int64_t)G.nx * (G.ny - 1);
     d.zmin = d.zmax = NAN;
     pl.n_items += (int64_t)G.chains * d.tiles_x * d.tiles_y;
+    pl.n_tiles += (int64_t)d.tiles_x * d.tiles_y;
+    pl.plan_entries += (int64_t)d.tiles_x * d.tiles_y * d.plan_cap;
     pl.n_cblocks += (int64_t)G.chains * per_chain_blocks;
     pl.n_sblocks += per_chain_blocks;
     pl.state_elems += (int64_t)G.chains * sites;
@@ -177,6 +191,8 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.energy = (double *)take(8 * C * kMaxPass);
   v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * 4, pl.n_cblocks * 2));
   v.out = (double *)take(8 * std::max<size_t>((size_t)n * 4, C * 2));
+  v.plan = (uint16_t *)take(2 * (size_t)pl.plan_entries);
+  v.plan_cum = (uint32_t *)take(4 * (size_t)pl.n_tiles * 2 * (pl.dmax + 2));
   pl.bytes = off;
   return MPR_OK;
 }
@@ -201,6 +217,8 @@ void bind(Views &v, const Views &o, void *ws) {
   v.energy = rebase(o.energy, b);
   v.part = rebase(o.part, b);
   v.out = rebase(o.out, b);
+  v.plan = rebase(o.plan, b);
+  v.plan_cum = rebase(o.plan_cum, b);
 }
 
 // LDS extent of a pass with nsw sweeps: tile + 2*(2*nsw + 1) halo + a ring,
@@ -214,7 +232,8 @@ void lds_extent(const mpr_ctx *c, int nsw, int &w, int &h, size_t &bytes) {
     h = std::max(h, std::min(c->plan.tile_y + 2 * H + 2, d.ny + 2));
   }
   w = (w + 1) & ~1;
-  bytes = (size_t)w * h * 3 * c->plan.elem;  // angle + (cos, sin), both colours
+  // angle + (cos, sin) of both colours, and the staged gap-site list
+  bytes = (size_t)w * h * 3 * c->plan.elem + (size_t)w * h * 2;
 }
 
 mpr_status set_beta(mpr_ctx *c, const double *T) {
@@ -256,6 +275,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
                                   std::to_string(c->lds_limit));
   A.grids = c->v.gd;
   A.n_grids = c->n_grids;
+  A.total_chains = c->plan.total_chains;
   A.tile_x = c->plan.tile_x;
   A.tile_y = c->plan.tile_y;
   A.nsw = nsw;
@@ -267,16 +287,29 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.sweep0 = (uint32_t)c->sweep_index;
   A.record_mask = record_mask;
   A.first_mask = first_mask;
+  A.adapt = adapt;
+  A.adapt_every = c->p.adapt_every;
+  A.a_targ = c->p.a_targ;
+  A.k_a = c->p.k_a;
   A.q = (P)c->p.q;
+  A.inv_q = (P)(1.0 / c->p.q);
   A.src = (const P *)c->v.st[c->cur];
   A.dst = (P *)c->v.st[c->cur ^ 1];
   A.beta = c->v.beta;
+  A.a = c->v.a;
   A.alpha = c->v.alpha;
+  A.window = c->v.window;
+  A.accsum = c->v.accsum;
   A.counts = c->v.counts;
   A.energy = trace_e ? c->v.energy : nullptr;
+  A.trace_row0 = trace_row0;
+  A.trace = trace;
   A.acc_ref = (P *)c->v.acc_ref;
   A.acc_s1 = (P *)c->v.acc_s1;
   A.acc_s2 = (P *)c->v.acc_s2;
+  A.plan = c->v.plan;
+  A.plan_cum = c->v.plan_cum;
+  A.plan_dmax = c->plan.dmax;
   if (c->timing) {
     if (c->ev_used + 2 > c->ev.size()) {
       if (c->ev.size() < 8192) {
@@ -292,33 +325,14 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
     }
     HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
   }
-  HIP_TRY(c, launch_sweep<P>(A, c->plan.n_items, lds, c->stream));
+  HIP_TRY(c, launch_sweep<P>(A, c->threads, c->plan.n_items, lds, c->stream));
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
     c->ev_used += 2;
     c->t_launches += 1;
     c->t_site_sweeps += (int64_t)nsw * c->sites_all_chains;
   }
-
-  PassEndArgs E{};
-  E.grids = c->v.gd;
-  E.n_grids = c->n_grids;
-  E.total_chains = c->plan.total_chains;
-  E.nsw = nsw;
-  E.sweep0 = (uint32_t)c->sweep_index;
-  E.adapt = adapt;
-  E.adapt_every = c->p.adapt_every;
-  E.a_targ = c->p.a_targ;
-  E.k_a = c->p.k_a;
-  E.trace_row0 = trace_row0;
-  E.trace = trace;
-  E.counts = c->v.counts;
-  E.energy = trace_e ? c->v.energy : nullptr;
-  E.a = c->v.a;
-  E.alpha = c->v.alpha;
-  E.window = c->v.window;
-  E.accsum = c->v.accsum;
-  HIP_TRY(c, launch_pass_end(E, c->stream));
+  HIP_TRY(c, launch_pass_end<P>(A, c->stream));
   c->cur ^= 1;
   c->sweep_index += nsw;
   return MPR_OK;
@@ -468,7 +482,12 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
   c->n_grids = n_grids;
   c->plan = plan;
   bind(c->v, plan.v, workspace);
-  c->nsw_max = p->sweeps_per_pass ? p->sweeps_per_pass : 1;
+  c->nsw_max = plan.nsw_max;
+  c->threads = p->dtype == MPR_FP64 ? 256 : 512;
+  if (const char *env = std::getenv("MPR_SWEEP_THREADS")) {
+    const int t = std::atoi(env);
+    if (t == 256 || t == 512 || t == 1024) c->threads = t;
+  }
   c->sites_all_chains = plan.state_elems;
   auto bail = [&](mpr_status s) {
     g_thread_err = c->err;
@@ -528,6 +547,13 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
     TRY(launch_init<float>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (float *)c->v.st[0],
                            (float *)c->v.st[1], 0.0f, (uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32),
                            c->stream));
+  }
+  if (p->dtype == MPR_FP64) {
+    TRY(launch_plan<double>(c->v.gd, n_grids, c->plan.n_tiles, (const double *)c->v.st[0], c->plan.tile_x,
+                            c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
+  } else {
+    TRY(launch_plan<float>(c->v.gd, n_grids, c->plan.n_tiles, (const float *)c->v.st[0], c->plan.tile_x,
+                           c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
   }
   const int64_t C = c->plan.total_chains;
   TRY(launch_fill_f64(c->v.a, C, 1.0, c->stream));

@@ -21,6 +21,9 @@ struct GridDesc {
   int32_t chain_base;              // global index of chain 0
   int32_t grid_id;                 // index of the grid in the batch
   int64_t item_begin;              // first sweep work item (grid, chain, tile)
+  int64_t plan_begin;              // first tile of this grid in the gap-site plan
+  int64_t plan_ebase;              // first plan entry of this grid
+  int64_t plan_cap;                // plan entries reserved per tile of this grid
   int64_t cb_begin;                // first chain-chunk block (init, per-chain energy)
   int64_t sb_begin;                // first site-chunk block (min/max, sample energy, finalize)
   int64_t state_off, site_off;
@@ -32,7 +35,7 @@ struct GridDesc {
 template <typename P>
 struct SweepArgs {
   const GridDesc *grids;
-  int32_t n_grids;
+  int32_t n_grids, total_chains;
   int32_t tile_x, tile_y;
   int32_t nsw;                     // sweeps in this pass
   int32_t lds_w, lds_h;            // LDS extent in sites (lds_w even)
@@ -40,33 +43,41 @@ struct SweepArgs {
   uint32_t key0, key1;
   uint32_t sweep0;                 // global index of the pass's first sweep
   uint32_t record_mask, first_mask;
-  P q;
+  int32_t adapt, adapt_every;      // a-rule (Algorithm 2, step 4.2)
+  double a_targ, k_a;
+  P q, inv_q;
   const P *src;
   P *dst;
-  const double *beta, *alpha;      // per chain
+  const double *beta;              // per chain
+  double *a, *alpha, *window, *accsum;  // per chain, updated at the end of each pass
   uint32_t *counts;                // [chains][kMaxPass] accepted updates
   double *energy;                  // [chains][kMaxPass] or nullptr
-  P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
-};
-
-struct PassEndArgs {
-  const GridDesc *grids;
-  int32_t n_grids, total_chains;
-  int32_t nsw;
-  uint32_t sweep0;
-  int32_t adapt, adapt_every;
-  double a_targ, k_a;
   int64_t trace_row0;
   double *trace;                   // [rows][chains][2] or nullptr
-  uint32_t *counts;
-  double *energy;                  // or nullptr
-  double *a, *alpha, *window, *accsum;
+  P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
+  // Gap-site plan (k_plan): per tile, the gap sites within ring distance
+  // plan_dmax of the interior, colour 0 then colour 1, each sorted by ring
+  // (ring = Chebyshev distance from the interior rectangle); entry =
+  // ((y - y0 + 32) << 8) | (x - x0 + 32).  plan_cum[tile][c][r] = number of
+  // colour-c entries with ring < r, r = 0 .. plan_dmax + 1.
+  const uint16_t *plan;
+  const uint32_t *plan_cum;
+  int32_t plan_dmax;
 };
+
+// Entries of the gap-site plan are packed into 16 bits with an offset of 32
+// around the tile origin; this bounds tile + 2 * plan_dmax + 32 <= 256.
+constexpr int kPlanOffset = 32;
+constexpr int kMaxTile = 192;
 
 // Launchers (kernels.hip).  All return the hipError_t of the launch.
 template <typename P>
-hipError_t launch_sweep(const SweepArgs<P> &a, int64_t n_items, size_t lds_bytes, hipStream_t s);
-hipError_t launch_pass_end(const PassEndArgs &a, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds_bytes, hipStream_t s);
+template <typename P>
+hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s);
+template <typename P>
+hipError_t launch_plan(const GridDesc *g, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y,
+                       int dmax, uint16_t *plan, uint32_t *plan_cum, hipStream_t s);
 hipError_t launch_minmax(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
                          const uint8_t *const *known, double *part, hipStream_t s);
 hipError_t launch_minmax_final(const GridDesc *g, int n_grids, const double *part, double *out, hipStream_t s);

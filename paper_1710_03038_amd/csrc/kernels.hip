@@ -20,12 +20,26 @@
 
 #include <cmath>
 
+#include "fastmath.h"
+
 namespace mpr {
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon et al., SC'11): rounds multiply words 0 and 2 by
 // 0xD2511F53 and 0xCD9E8D57 (32x32 -> 64 bit), swap and xor in the key; the
 // key advances by 0x9E3779B9 / 0xBB67AE85 between rounds.
+// The 32x32 -> 64-bit products use one v_mad_u64_u32 each (both halves at
+// once); the compiler would otherwise split them into mul_lo + mul_hi.
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b) {
+#ifdef MPR_PHILOX_SPLIT_MUL
+  return ((uint64_t)__umulhi(a, b) << 32) | (uint64_t)(a * b);
+#else
+  uint64_t r, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "v"(b));
+  return r;
+#endif
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                               uint32_t k1, uint32_t out[4]) {
 #pragma unroll
@@ -34,8 +48,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint64_t p0 = mul_wide(0xD2511F53u, c0), p1 = mul_wide(0xCD9E8D57u, c2);
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
@@ -49,17 +64,19 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 // ------------------------------------------------------------ precision
+// FP32 uses the bounded-argument routines of fastmath.h; FP64 (the plain
+// reference arm) uses the device library's correctly rounded functions.
 template <typename P> struct Prec;
 template <> struct Prec<float> {
   using V2 = float2;
   static constexpr float two_pi = 6.28318530717958647692f;  // rounds up: 6.2831855f
   static constexpr float below_two_pi = 6.2831850f;         // largest float < two_pi
   static constexpr float tiny_h2 = 1e-12f;
-  __device__ static float sin_(float x) { return sinf(x); }
-  __device__ static void sincos_(float x, float *s, float *c) { sincosf(x, s, c); }
-  __device__ static float atan2_(float y, float x) { return atan2f(y, x); }
-  __device__ static float exp_(float x) { return expf(x); }
-  __device__ static float sqrt_(float x) { return sqrtf(x); }
+  __device__ static float sin_(float x) { return fm::sin(x); }
+  __device__ static void sincos_(float x, float *s, float *c) { fm::sincos(x, s, c); }
+  __device__ static float atan2_(float y, float x) { return fm::atan2(y, x); }
+  __device__ static float exp_(float x) { return fm::exp(x); }
+  __device__ static float sqrt_(float x) { return fm::sqrt(x); }
   __device__ static float floor_(float x) { return floorf(x); }
 };
 template <> struct Prec<double> {
@@ -67,12 +84,12 @@ template <> struct Prec<double> {
   static constexpr double two_pi = 6.28318530717958647692;
   static constexpr double below_two_pi = 6.2831853071795853;  // nextafter(2*pi, 0)
   static constexpr double tiny_h2 = 1e-24;
-  __device__ static double sin_(double x) { return sin(x); }
-  __device__ static void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
-  __device__ static double atan2_(double y, double x) { return atan2(y, x); }
-  __device__ static double exp_(double x) { return exp(x); }
-  __device__ static double sqrt_(double x) { return sqrt(x); }
-  __device__ static double floor_(double x) { return floor(x); }
+  __device__ static double sin_(double x) { return ::sin(x); }
+  __device__ static void sincos_(double x, double *s, double *c) { ::sincos(x, s, c); }
+  __device__ static double atan2_(double y, double x) { return ::atan2(y, x); }
+  __device__ static double exp_(double x) { return ::exp(x); }
+  __device__ static double sqrt_(double x) { return ::sqrt(x); }
+  __device__ static double floor_(double x) { return ::floor(x); }
 };
 
 // A 32-bit word to [0, 1 - 2^-24]: (w >> 8) * 2^-24, exact in either precision.
@@ -101,8 +118,9 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-// Sum over the workgroup; the result is valid in thread 0.  Fixed order.
-template <typename T> __device__ __forceinline__ T block_sum(T v, T *scratch) {
+// Sum over the workgroup of NT threads; the result is valid in thread 0.
+// Fixed order, so the result does not depend on scheduling.
+template <int NT, typename T> __device__ __forceinline__ T block_sum(T v, T *scratch) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
@@ -110,7 +128,7 @@ template <typename T> __device__ __forceinline__ T block_sum(T v, T *scratch) {
   __syncthreads();
   T r = T(0);
   if (threadIdx.x == 0)
-    for (int i = 0; i < kThreads / 64; ++i) r += scratch[i];
+    for (int i = 0; i < NT / 64; ++i) r += scratch[i];
   return r;
 }
 
@@ -124,217 +142,32 @@ __device__ __forceinline__ int find_by(const GridDesc *g, int n, int64_t key, in
   return lo;
 }
 
-// ---------------------------------------------------------------- sweep
-// One workgroup = one (grid, chain, tile) item.  Half-sweep hs of the pass
-// updates the colour-(hs & 1) gap sites within distance D = 2*nsw - hs of
-// the interior; the halo of 2*nsw + 1 sites keeps every neighbour read by
-// those sites exact, and after each full sweep the interior plus one ring
-// is exact, which the energy of interior pairs needs.
-template <typename P>
-__global__ void __launch_bounds__(kThreads) k_sweep(const SweepArgs<P> A) {
-  using V2 = typename Prec<P>::V2;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red_d[kThreads / 64];
-  __shared__ uint32_t red_u[kThreads / 64];
-
-  const int64_t item = blockIdx.x;
-  const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin);
-  const GridDesc &G = A.grids[gi];
-  const int64_t local = item - G.item_begin;
-  const int tiles = G.tiles_x * G.tiles_y;
-  const int chain = (int)(local / tiles);
-  const int t = (int)(local - (int64_t)chain * tiles);
-  const int nx = G.nx, ny = G.ny;
-  const int x0 = (t % G.tiles_x) * A.tile_x, y0 = (t / G.tiles_x) * A.tile_y;
-  const int ix1 = min(x0 + A.tile_x, nx), iy1 = min(y0 + A.tile_y, ny);
-  const int H = 2 * A.nsw + 1;
-  const int ox = max(x0 - H - 1, -2);  // even, so LDS pairs are Philox pairs
-  const int oy = max(y0 - H - 1, -1);
-  const int lxs = max(x0 - H, 0), lxe = min(ix1 + H, nx);
-  const int lys = max(y0 - H, 0), lye = min(iy1 + H, ny);
-  const int W = A.lds_w, P2 = W >> 1, plane = A.lds_h * P2;
-
-  V2 *cs = reinterpret_cast<V2 *>(smem);                       // (cos q phi, sin q phi)
-  P *ph = reinterpret_cast<P *>(smem + 2 * plane * sizeof(V2));  // encoded angle
-  const P q = A.q;
-  const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
-  const P *src = A.src + cbase;
-
-  // Stage the tile, its halo and a frozen zero ring around them.
-  for (int idx = threadIdx.x; idx < W * A.lds_h; idx += kThreads) {
-    const int ly = idx / W, lx = idx - ly * W;
-    const int gx = ox + lx, gy = oy + ly;
-    const int o = ((gx + gy) & 1) * plane + ly * P2 + (lx >> 1);
-    P v = -P(0);
-    V2 c = {P(0), P(0)};
-    if (gx >= lxs && gx < lxe && gy >= lys && gy < lye) {
-      v = src[(int64_t)gy * nx + gx];
-      P s_, c_;
-      Prec<P>::sincos_(q * fabs(v), &s_, &c_);
-      c = {c_, s_};
-    }
-    ph[o] = v;
-    cs[o] = c;
-  }
-  __syncthreads();
-
-  const int gchain = G.chain_base + chain;
-  const P beta = (P)A.beta[gchain], alpha = (P)A.alpha[gchain];
-  const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
-  const int iw = ix1 - x0, ih = iy1 - y0;
-
-  for (int s = 0; s < A.nsw; ++s) {
-    const uint32_t sweep = A.sweep0 + (uint32_t)s;
-    uint32_t acc = 0;
-    for (int c = 0; c < 2; ++c) {
-      const int D = 2 * A.nsw - (2 * s + c);
-      const int rx0 = max(x0 - D, 0), rx1 = min(ix1 + D, nx);
-      const int ry0 = max(y0 - D, 0), ry1 = min(iy1 + D, ny);
-      const int ja = (rx0 - ox) >> 1, jb = (rx1 - 1 - ox) >> 1;
-      const int npr = jb - ja + 1, rows = ry1 - ry0;
-      const int total = npr * rows;
-      const float inv = 1.0f / (float)npr;
-      P *pc = ph + c * plane;
-      V2 *cc = cs + c * plane;
-      const V2 *cn = cs + (c ^ 1) * plane;
-      for (int f = threadIdx.x; f < total; f += kThreads) {
-        int r = (int)((float)f * inv);
-        int jo = f - r * npr;
-        if (jo >= npr) { ++r; jo -= npr; }
-        if (jo < 0) { --r; jo += npr; }
-        const int j = ja + jo;
-        const int gy = ry0 + r, ly = gy - oy;
-        const int gx = ox + 2 * j + ((c + gy) & 1);  // the colour-c site of pair j
-        if (gx < rx0 || gx >= rx1) continue;
-        const int o = ly * P2 + j;
-        const P phi = pc[o];
-        if (signbit(phi)) continue;  // frozen sample site
-        const int jl = (gx & 1) ? j : j - 1, jr = (gx & 1) ? j + 1 : j;
-        const V2 nl = cn[ly * P2 + jl], nr = cn[ly * P2 + jr];
-        const V2 nu = cn[o - P2], nd = cn[o + P2];
-        const P hx = nl.x + nr.x + nu.x + nd.x;
-        const P hy = nl.y + nr.y + nu.y + nd.y;
-
-        uint32_t w[4];
-        philox4x32_10((uint32_t)gy * (uint32_t)G.npair + (uint32_t)(gx >> 1), sweep, cid, gid, k0, k1, w);
-        const P u = unit<P>((gx & 1) ? w[2] : w[0]);
-        const P rr = unit<P>((gx & 1) ? w[3] : w[1]);
-
-        // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
-        const P h2 = hx * hx + hy * hy;
-        const P psi = Prec<P>::atan2_(hy, hx);
-        P p1 = phi;
-        if (h2 > Prec<P>::tiny_h2) {
-          const P star = (P(2) * psi - q * phi) / q;
-          if (A.q_is_one) p1 = wrap_any(star);
-          else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
-        }
-        // Steps 2-3: restricted Metropolis proposal.
-        const P p2 = wrap_step(p1 + alpha * (u - P(0.5)));
-        // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
-        //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
-        const P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_(q * (p2 + p1) * P(0.5) - psi) *
-                     Prec<P>::sin_(q * (p2 - p1) * P(0.5));
-        // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
-        const bool ok = (dH <= P(0)) || (rr < Prec<P>::exp_(-beta * dH));
-        const P nv = ok ? p2 : p1;
-        pc[o] = nv;
-        P s_, c_;
-        Prec<P>::sincos_(q * nv, &s_, &c_);
-        cc[o] = {c_, s_};
-        if (ok && gx >= x0 && gx < ix1 && gy >= y0 && gy < iy1) ++acc;
-      }
-      __syncthreads();
-    }
-
-    if (A.counts) {
-      const uint32_t tot = block_sum(acc, red_u);
-      if (threadIdx.x == 0 && tot) atomicAdd(&A.counts[(int64_t)gchain * kMaxPass + s], tot);
-    }
-    if (A.energy) {
-      // Eq. (5): pairs (x, y)-(x+1, y) and (x, y)-(x, y+1) owned by interior sites.
-      P e = P(0);
-      for (int f = threadIdx.x; f < iw * ih; f += kThreads) {
-        const int r = f / iw;
-        const int gx = x0 + (f - r * iw), gy = y0 + r;
-        const int lx = gx - ox, ly = gy - oy;
-        const int col = (gx + gy) & 1;
-        const P v = fabs(ph[col * plane + ly * P2 + (lx >> 1)]);
-        if (gx + 1 < nx) {
-          const P d = v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]);
-          const P sn = Prec<P>::sin_(q * d * P(0.5));
-          e += P(2) * sn * sn;
-        }
-        if (gy + 1 < ny) {
-          const P d = v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]);
-          const P sn = Prec<P>::sin_(q * d * P(0.5));
-          e += P(2) * sn * sn;
-        }
-      }
-      const double tot = block_sum((double)e, red_d);
-      if (threadIdx.x == 0) atomicAdd(&A.energy[(int64_t)gchain * kMaxPass + s], tot);
-    }
-    if ((A.record_mask >> s) & 1u) {
-      // Algorithm 2, step 5.3: one realisation; shifted sums about the first.
-      const bool first = (A.first_mask >> s) & 1u;
-      for (int f = threadIdx.x; f < iw * ih; f += kThreads) {
-        const int r = f / iw;
-        const int gx = x0 + (f - r * iw), gy = y0 + r;
-        const int lx = gx - ox, ly = gy - oy;
-        const P v = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
-        if (signbit(v)) continue;
-        const int64_t k = cbase + (int64_t)gy * nx + gx;
-        if (first) {
-          A.acc_ref[k] = v;
-          A.acc_s1[k] = P(0);
-          A.acc_s2[k] = P(0);
-        } else {
-          const P d = v - A.acc_ref[k];
-          A.acc_s1[k] += d;
-          A.acc_s2[k] += d * d;
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  P *dst = A.dst + cbase;
-  for (int f = threadIdx.x; f < iw * ih; f += kThreads) {
-    const int r = f / iw;
-    const int gx = x0 + (f - r * iw), gy = y0 + r;
-    const int lx = gx - ox, ly = gy - oy;
-    dst[(int64_t)gy * nx + gx] = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
+// Row r and column offset of flat index f over rows of npr entries, without
+// an integer division (f < 2^22, so the float estimate is off by at most one).
+__device__ __forceinline__ void split_index(int f, int npr, float inv, int &r, int &c) {
+  r = (int)((float)f * inv);
+  c = f - r * npr;
+  if (c >= npr) {
+    ++r;
+    c -= npr;
+  } else if (c < 0) {
+    --r;
+    c += npr;
   }
 }
 
+// End of a pass for one chain (run after the pass's sweep kernel):
+// turn the accepted counts into acceptance ratios, write the trace, and
+// apply the a-rule of Algorithm 2, step 4.2: after sweep i, if the mean
+// acceptance of the adapt_every-window ending there is below A_targ, then
+// a = 1 + (i + 1)/k_a.  Then alpha = 2*pi/a for the next pass.
 template <typename P>
-hipError_t launch_sweep(const SweepArgs<P> &a, int64_t n_items, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(k_sweep<P>, dim3((unsigned)n_items), dim3(kThreads), lds_bytes, s, a);
-  return hipGetLastError();
-}
-template hipError_t launch_sweep<float>(const SweepArgs<float> &, int64_t, size_t, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double> &, int64_t, size_t, hipStream_t);
-
-// -------------------------------------------------------------- pass end
-// One thread per chain: turn the pass's accepted counts into acceptance
-// ratios, write the trace, and apply the a-rule (Algorithm 2, step 4.2):
-// after sweep i, if the mean acceptance of the window ending there is below
-// A_targ, a = 1 + (i + 1)/k_a.  Then alpha = 2*pi/a for the next pass.
-__global__ void k_pass_end(const PassEndArgs A) {
-  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ch >= A.total_chains) return;
-  int lo = 0, hi = A.n_grids - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (A.grids[mid].chain_base <= ch) lo = mid;
-    else hi = mid - 1;
-  }
-  const GridDesc &G = A.grids[lo];
+__device__ void chain_pass_end(const SweepArgs<P> &A, const GridDesc &G, int ch) {
   double a = A.a[ch];
   for (int s = 0; s < A.nsw; ++s) {
     const int64_t k = (int64_t)ch * kMaxPass + s;
     const uint32_t cnt = A.counts[k];
-    A.counts[k] = 0;
+    A.counts[k] = 0u;
     const double acc = G.n_gap > 0 ? (double)cnt / (double)G.n_gap : 1.0;
     A.accsum[ch] += acc;
     double e = __builtin_nan("");
@@ -362,10 +195,311 @@ __global__ void k_pass_end(const PassEndArgs A) {
   A.alpha[ch] = 6.28318530717958647692 / a;
 }
 
-hipError_t launch_pass_end(const PassEndArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pass_end, dim3((a.total_chains + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+// ---------------------------------------------------------------- sweep
+// One workgroup = one (grid, chain, tile) item.  Half-sweep hs of the pass
+// updates the colour-(hs & 1) gap sites within distance D = 2*nsw - hs of
+// the interior; the halo of 2*nsw + 1 sites keeps every neighbour read by
+// those sites exact, and after each full sweep the interior plus one ring
+// is exact, which the energy of interior pairs needs.
+template <typename P, int NT>
+__global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
+  using V2 = typename Prec<P>::V2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[NT / 64];
+  __shared__ uint32_t red_u[NT / 64];
+
+  const int64_t item = blockIdx.x;
+  const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin);
+  const GridDesc G = A.grids[gi];  // by value: kept in registers across LDS stores
+  const int64_t local = item - G.item_begin;
+  const int tiles = G.tiles_x * G.tiles_y;
+  const int chain = (int)(local / tiles);
+  const int t = (int)(local - (int64_t)chain * tiles);
+  const int nx = G.nx, ny = G.ny;
+  const int x0 = (t % G.tiles_x) * A.tile_x, y0 = (t / G.tiles_x) * A.tile_y;
+  const int ix1 = min(x0 + A.tile_x, nx), iy1 = min(y0 + A.tile_y, ny);
+  const int H = 2 * A.nsw + 1;
+  const int ox = max(x0 - H - 1, -2);  // even, so LDS pairs are Philox pairs
+  const int oy = max(y0 - H - 1, -1);
+  const int lxs = max(x0 - H, 0), lxe = min(ix1 + H, nx);
+  const int lys = max(y0 - H, 0), lye = min(iy1 + H, ny);
+  const int W = A.lds_w, P2 = W >> 1, plane = A.lds_h * P2;
+
+  V2 *cs = reinterpret_cast<V2 *>(smem);                         // (cos q phi, sin q phi)
+  P *ph = reinterpret_cast<P *>(smem + 2 * plane * sizeof(V2));  // encoded angle
+  const P q = A.q, inv_q = A.inv_q;
+  const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
+  const P *src = A.src + cbase;
+
+  // Stage the tile, its halo and a frozen zero ring around them.
+  {
+    const float invw = 1.0f / (float)W;
+    for (int idx = threadIdx.x; idx < W * A.lds_h; idx += NT) {
+      int ly, lx;
+      split_index(idx, W, invw, ly, lx);
+      const int gx = ox + lx, gy = oy + ly;
+      const int o = ((gx + gy) & 1) * plane + ly * P2 + (lx >> 1);
+      P v = -P(0);
+      V2 c = {P(0), P(0)};
+      if (gx >= lxs && gx < lxe && gy >= lys && gy < lye) {
+        v = src[(int64_t)gy * nx + gx];
+        P s_, c_;
+        Prec<P>::sincos_(q * fabs(v), &s_, &c_);
+        c = {c_, s_};
+      }
+      ph[o] = v;
+      cs[o] = c;
+    }
+  }
+  __syncthreads();
+
+  // Stage this pass's part of the tile's gap-site plan: colour-0 entries
+  // within ring 2*nsw, then colour-1 entries within ring 2*nsw - 1.
+  uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);
+  const int64_t pitem = G.plan_begin + t;
+  const uint32_t *cum = A.plan_cum + pitem * 2 * (A.plan_dmax + 2);
+  const int cstride = A.plan_dmax + 2;
+  const uint32_t n0_all = cum[A.plan_dmax + 1];
+  const uint32_t na = cum[2 * A.nsw + 1], nb = cum[cstride + 2 * A.nsw];
+  {
+    const uint16_t *pl = A.plan + G.plan_ebase + (int64_t)t * G.plan_cap;
+    for (uint32_t f = threadIdx.x; f < na; f += NT) list[f] = pl[f];
+    for (uint32_t f = threadIdx.x; f < nb; f += NT) list[na + f] = pl[n0_all + f];
+  }
+  __syncthreads();
+
+  const int gchain = G.chain_base + chain;
+  const P beta = (P)A.beta[gchain], alpha = (P)A.alpha[gchain];
+  const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
+  const int iw = ix1 - x0, ih = iy1 - y0;
+  const float inv_iw = 1.0f / (float)iw;
+  const uint32_t npair = (uint32_t)G.npair;
+
+  for (int s = 0; s < A.nsw; ++s) {
+    const uint32_t sweep = A.sweep0 + (uint32_t)s;
+    uint32_t acc = 0;
+    for (int c = 0; c < 2; ++c) {
+      const int D = 2 * A.nsw - (2 * s + c);
+      const uint32_t n = cum[c * cstride + D + 1];      // entries within ring D
+      const uint32_t n_inner = cum[c * cstride + 1];    // ring 0: the interior
+      const uint16_t *lc = list + (c ? na : 0);
+      P *pc = ph + c * plane;
+      V2 *cc = cs + c * plane;
+      const V2 *cn = cs + (c ^ 1) * plane;
+      for (uint32_t f = threadIdx.x; f < n; f += NT) {
+        const uint32_t e = lc[f];
+        const int gx = x0 + (int)(e & 255u) - kPlanOffset, gy = y0 + (int)(e >> 8) - kPlanOffset;
+        const int lx = gx - ox, ly = gy - oy;
+        const int j = lx >> 1;
+        const int o = ly * P2 + j;
+        const P phi = pc[o];
+        const int jl = (gx & 1) ? j : j - 1, jr = (gx & 1) ? j + 1 : j;
+        const V2 nl = cn[ly * P2 + jl], nr = cn[ly * P2 + jr];
+        const V2 nu = cn[o - P2], nd = cn[o + P2];
+        const P hx = nl.x + nr.x + nu.x + nd.x;
+        const P hy = nl.y + nr.y + nu.y + nd.y;
+
+        uint32_t w[4];
+        philox4x32_10((uint32_t)gy * npair + (uint32_t)(gx >> 1), sweep, cid, gid, k0, k1, w);
+        const P u = unit<P>((gx & 1) ? w[2] : w[0]);
+        const P rr = unit<P>((gx & 1) ? w[3] : w[1]);
+
+        // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
+        const P h2 = hx * hx + hy * hy;
+        const bool live = h2 > Prec<P>::tiny_h2;
+        const P psi = live ? Prec<P>::atan2_(hy, hx) : P(0);
+        P p1 = phi;
+        if (live) {
+          const P star = (P(2) * psi - q * phi) * inv_q;
+          if (A.q_is_one) p1 = wrap_any(star);
+          else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+        }
+        // Steps 2-3: restricted Metropolis proposal.
+        const P p2 = wrap_step(p1 + alpha * (u - P(0.5)));
+        // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
+        //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
+        P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_(q * (p2 + p1) * P(0.5) - psi) *
+               Prec<P>::sin_(q * (p2 - p1) * P(0.5));
+        dH = live ? dH : P(0);
+        // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
+        const bool ok = (dH <= P(0)) || (rr < Prec<P>::exp_(-beta * dH));
+        const P nv = ok ? p2 : p1;
+        pc[o] = nv;
+        P s_, c_;
+        Prec<P>::sincos_(q * nv, &s_, &c_);
+        cc[o] = {c_, s_};
+        if (ok && f < n_inner) ++acc;
+      }
+      __syncthreads();
+    }
+
+    const uint32_t tot = block_sum<NT>(acc, red_u);
+    if (threadIdx.x == 0 && tot) atomicAdd(&A.counts[(int64_t)gchain * kMaxPass + s], tot);
+    if (A.energy) {
+      // Eq. (5): pairs (x, y)-(x+1, y) and (x, y)-(x, y+1) owned by interior sites.
+      P e = P(0);
+      for (int f = threadIdx.x; f < iw * ih; f += NT) {
+        int r, cx;
+        split_index(f, iw, inv_iw, r, cx);
+        const int gx = x0 + cx, gy = y0 + r;
+        const int lx = gx - ox, ly = gy - oy;
+        const int col = (gx + gy) & 1;
+        const P v = fabs(ph[col * plane + ly * P2 + (lx >> 1)]);
+        if (gx + 1 < nx) {
+          const P d = v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]);
+          const P sn = Prec<P>::sin_(q * d * P(0.5));
+          e += P(2) * sn * sn;
+        }
+        if (gy + 1 < ny) {
+          const P d = v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]);
+          const P sn = Prec<P>::sin_(q * d * P(0.5));
+          e += P(2) * sn * sn;
+        }
+      }
+      const double et = block_sum<NT>((double)e, red_d);
+      if (threadIdx.x == 0) atomicAdd(&A.energy[(int64_t)gchain * kMaxPass + s], et);
+    }
+    if ((A.record_mask >> s) & 1u) {
+      // Algorithm 2, step 5.3: one realisation; shifted sums about the first.
+      const bool first = (A.first_mask >> s) & 1u;
+      for (int f = threadIdx.x; f < iw * ih; f += NT) {
+        int r, cx;
+        split_index(f, iw, inv_iw, r, cx);
+        const int gx = x0 + cx, gy = y0 + r;
+        const int lx = gx - ox, ly = gy - oy;
+        const P v = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
+        if (signbit(v)) continue;
+        const int64_t k = cbase + (int64_t)gy * nx + gx;
+        if (first) {
+          A.acc_ref[k] = v;
+          A.acc_s1[k] = P(0);
+          A.acc_s2[k] = P(0);
+        } else {
+          const P d = v - A.acc_ref[k];
+          A.acc_s1[k] += d;
+          A.acc_s2[k] += d * d;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  P *dst = A.dst + cbase;
+  for (int f = threadIdx.x; f < iw * ih; f += NT) {
+    int r, cx;
+    split_index(f, iw, inv_iw, r, cx);
+    const int gx = x0 + cx, gy = y0 + r;
+    const int lx = gx - ox, ly = gy - oy;
+    dst[(int64_t)gy * nx + gx] = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
+  }
+
+}
+
+// ------------------------------------------------------------------- plan
+// One workgroup per (grid, tile): list the tile's gap sites within ring
+// distance dmax of its interior, colour 0 first, each colour sorted by ring
+// (a counting sort).  The order inside one ring follows the LDS atomics and
+// may vary between runs; the sweep's results do not depend on it.
+template <typename P>
+__global__ void __launch_bounds__(kThreads)
+    k_plan(const GridDesc *grids, int n_grids, const P *state, int tile_x, int tile_y, int dmax, uint16_t *plan,
+           uint32_t *plan_cum) {
+  __shared__ uint32_t cnt[2][2 * kMaxPass + 2];
+  __shared__ uint32_t cur[2][2 * kMaxPass + 2];
+  const int64_t item = blockIdx.x;
+  const int gi = find_by(grids, n_grids, item, &GridDesc::plan_begin);
+  const GridDesc G = grids[gi];
+  const int t = (int)(item - G.plan_begin);
+  const int nx = G.nx, ny = G.ny;
+  const int x0 = (t % G.tiles_x) * tile_x, y0 = (t / G.tiles_x) * tile_y;
+  const int ix1 = min(x0 + tile_x, nx), iy1 = min(y0 + tile_y, ny);
+  const int rx0 = max(x0 - dmax, 0), rx1 = min(ix1 + dmax, nx);
+  const int ry0 = max(y0 - dmax, 0), ry1 = min(iy1 + dmax, ny);
+  const int rw = rx1 - rx0, n = rw * (ry1 - ry0);
+  const float inv = 1.0f / (float)rw;
+  const P *st = state + G.state_off;  // chain 0: the sample sites are those of every chain
+  for (int i = threadIdx.x; i < 2 * (2 * kMaxPass + 2); i += kThreads) (&cnt[0][0])[i] = 0u;
+  __syncthreads();
+  for (int f = threadIdx.x; f < n; f += kThreads) {
+    int r, cx;
+    split_index(f, rw, inv, r, cx);
+    const int gx = rx0 + cx, gy = ry0 + r;
+    if (signbit(st[(int64_t)gy * nx + gx])) continue;
+    const int ring = max(max(max(x0 - gx, gx - (ix1 - 1)), max(y0 - gy, gy - (iy1 - 1))), 0);
+    atomicAdd(&cnt[(gx + gy) & 1][ring], 1u);
+  }
+  __syncthreads();
+  uint32_t *cum = plan_cum + item * 2 * (dmax + 2);
+  if (threadIdx.x == 0) {
+    uint32_t base = 0;
+    for (int c = 0; c < 2; ++c) {
+      uint32_t acc = 0;
+      for (int r = 0; r <= dmax + 1; ++r) {
+        cum[c * (dmax + 2) + r] = acc;
+        cur[c][r] = base + acc;
+        if (r <= dmax) acc += cnt[c][r];
+      }
+      base += acc;
+    }
+  }
+  __syncthreads();
+  uint16_t *out = plan + G.plan_ebase + (int64_t)t * G.plan_cap;
+  for (int f = threadIdx.x; f < n; f += kThreads) {
+    int r, cx;
+    split_index(f, rw, inv, r, cx);
+    const int gx = rx0 + cx, gy = ry0 + r;
+    if (signbit(st[(int64_t)gy * nx + gx])) continue;
+    const int ring = max(max(max(x0 - gx, gx - (ix1 - 1)), max(y0 - gy, gy - (iy1 - 1))), 0);
+    const uint32_t pos = atomicAdd(&cur[(gx + gy) & 1][ring], 1u);
+    out[pos] = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (gx - x0 + kPlanOffset));
+  }
+}
+
+template <typename P>
+hipError_t launch_plan(const GridDesc *g, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y,
+                       int dmax, uint16_t *plan, uint32_t *plan_cum, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan<P>, dim3((unsigned)n_tiles), dim3(kThreads), 0, s, g, n_grids, state, tile_x, tile_y, dmax,
+                     plan, plan_cum);
   return hipGetLastError();
 }
+template hipError_t launch_plan<float>(const GridDesc *, int, int64_t, const float *, int, int, int, uint16_t *,
+                                       uint32_t *, hipStream_t);
+template hipError_t launch_plan<double>(const GridDesc *, int, int64_t, const double *, int, int, int, uint16_t *,
+                                        uint32_t *, hipStream_t);
+
+// One thread per chain, after the sweep kernel of a pass: close the pass.
+template <typename P>
+__global__ void k_pass_end(const SweepArgs<P> A) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= A.total_chains) return;
+  int lo = 0, hi = A.n_grids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.grids[mid].chain_base <= ch) lo = mid;
+    else hi = mid - 1;
+  }
+  chain_pass_end(A, A.grids[lo], ch);
+}
+
+template <typename P>
+hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
+  switch (threads) {
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256>), dim3((unsigned)n_items), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512>), dim3((unsigned)n_items), dim3(512), lds, s, a); break;
+    case 1024: hipLaunchKernelGGL((k_sweep<P, 1024>), dim3((unsigned)n_items), dim3(1024), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename P> hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_end<P>, dim3((a.total_chains + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_pass_end<float>(const SweepArgs<float> &, hipStream_t);
+template hipError_t launch_pass_end<double>(const SweepArgs<double> &, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int64_t, size_t, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int64_t, size_t, hipStream_t);
 
 // ------------------------------------------------------ min / max of samples
 // Eq. (2) needs z_min, z_max over the samples of each grid.  Stage 1: one
@@ -553,8 +687,8 @@ __global__ void __launch_bounds__(kThreads)
       }
     }
   }
-  const double se = block_sum((double)e, red);
-  const double sc = block_sum(cnt, red);
+  const double se = block_sum<kThreads>((double)e, red);
+  const double sc = block_sum<kThreads>(cnt, red);
   if (threadIdx.x == 0) {
     part[b * 2] = se;
     part[b * 2 + 1] = sc;
@@ -587,8 +721,8 @@ __global__ void __launch_bounds__(kThreads)
     e += part[(b0 + i) * 2];
     c += part[(b0 + i) * 2 + 1];
   }
-  const double se = block_sum(e, red);
-  const double sc = block_sum(c, red);
+  const double se = block_sum<kThreads>(e, red);
+  const double sc = block_sum<kThreads>(c, red);
   if (threadIdx.x == 0) {
     out[unit * 2] = se;
     out[unit * 2 + 1] = sc;

@@ -14,7 +14,7 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmpr.so")
+LIB_PATH = os.environ.get("MPR_LIB") or os.path.join(HERE, "libmpr.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mpr.h")
 
 MPR_OK, MPR_E_ARG, MPR_E_SHAPE, MPR_E_DEGENERATE, MPR_E_NOPAIRS, MPR_E_RANGE, \
