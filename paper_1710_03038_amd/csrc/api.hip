@@ -27,7 +27,7 @@ struct Views {
   const uint8_t **kp = nullptr;
   void *st[2] = {nullptr, nullptr};
   void *acc_ref = nullptr, *acc_s1 = nullptr, *acc_s2 = nullptr;
-  double *a = nullptr, *alpha = nullptr, *beta = nullptr, *window = nullptr, *accsum = nullptr;
+  double *a = nullptr, *beta = nullptr, *window = nullptr, *accsum = nullptr;
   uint32_t *counts = nullptr;
   double *energy = nullptr;
   double *part = nullptr, *out = nullptr;
@@ -56,6 +56,8 @@ struct mpr_ctx {
   Views v;
   int cur = 0;                 // index of the state buffer holding the current angles
   int64_t sweep_index = 0;     // global sweep counter (keys the random stream)
+  int64_t pass_no = 0;         // passes run so far: selects the counter and a buffers
+  PassEnd pending{};           // the last pass, until its end has been applied
   int nsw_max = 1;
   int threads = 256;           // workgroup size of the sweep kernel
   size_t lds_limit = 65536;
@@ -182,13 +184,12 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.acc_ref = (void *)take(pl.elem * pl.state_elems);
   v.acc_s1 = (void *)take(pl.elem * pl.state_elems);
   v.acc_s2 = (void *)take(pl.elem * pl.state_elems);
-  v.a = (double *)take(8 * C);
-  v.alpha = (double *)take(8 * C);
+  v.a = (double *)take(8 * 2 * C);                 // by pass parity
   v.beta = (double *)take(8 * C);
-  v.window = (double *)take(8 * C);
+  v.window = (double *)take(8 * 2 * C);            // by pass parity
   v.accsum = (double *)take(8 * C);
-  v.counts = (uint32_t *)take(4 * C * kMaxPass);
-  v.energy = (double *)take(8 * C * kMaxPass);
+  v.counts = (uint32_t *)take(4 * 3 * C * kMaxPass);  // by pass number mod 3
+  v.energy = (double *)take(8 * 3 * C * kMaxPass);
   v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * 4, pl.n_cblocks * 2));
   v.out = (double *)take(8 * std::max<size_t>((size_t)n * 4, C * 2));
   v.plan = (uint16_t *)take(2 * (size_t)pl.plan_entries);
@@ -209,7 +210,6 @@ void bind(Views &v, const Views &o, void *ws) {
   v.acc_s1 = rebase((char *)o.acc_s1, b);
   v.acc_s2 = rebase((char *)o.acc_s2, b);
   v.a = rebase(o.a, b);
-  v.alpha = rebase(o.alpha, b);
   v.beta = rebase(o.beta, b);
   v.window = rebase(o.window, b);
   v.accsum = rebase(o.accsum, b);
@@ -234,6 +234,15 @@ void lds_extent(const mpr_ctx *c, int nsw, int &w, int &h, size_t &bytes) {
   w = (w + 1) & ~1;
   // angle + (cos, sin) of both colours, and the staged gap-site list
   bytes = (size_t)w * h * 3 * c->plan.elem + (size_t)w * h * 2;
+}
+
+double *a_buf(mpr_ctx *c, int64_t pass) { return c->v.a + (pass & 1) * c->plan.total_chains; }
+double *win_buf(mpr_ctx *c, int64_t pass) { return c->v.window + (pass & 1) * c->plan.total_chains; }
+uint32_t *counts_buf(mpr_ctx *c, int64_t pass) {
+  return c->v.counts + (pass % 3) * (int64_t)c->plan.total_chains * kMaxPass;
+}
+double *energy_buf(mpr_ctx *c, int64_t pass) {
+  return c->v.energy + (pass % 3) * (int64_t)c->plan.total_chains * kMaxPass;
 }
 
 mpr_status set_beta(mpr_ctx *c, const double *T) {
@@ -296,14 +305,15 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.src = (const P *)c->v.st[c->cur];
   A.dst = (P *)c->v.st[c->cur ^ 1];
   A.beta = c->v.beta;
-  A.a = c->v.a;
-  A.alpha = c->v.alpha;
-  A.window = c->v.window;
+  const int64_t pn = c->pass_no;
+  A.pe = c->pending;
+  A.a_now = a_buf(c, pn);
+  A.win_now = win_buf(c, pn);
   A.accsum = c->v.accsum;
-  A.counts = c->v.counts;
-  A.energy = trace_e ? c->v.energy : nullptr;
-  A.trace_row0 = trace_row0;
-  A.trace = trace;
+  A.counts = counts_buf(c, pn);
+  A.energy = trace_e ? energy_buf(c, pn) : nullptr;
+  A.counts_clear = counts_buf(c, pn + 1);
+  A.energy_clear = energy_buf(c, pn + 1);
   A.acc_ref = (P *)c->v.acc_ref;
   A.acc_s1 = (P *)c->v.acc_s1;
   A.acc_s2 = (P *)c->v.acc_s2;
@@ -332,10 +342,46 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
     c->t_launches += 1;
     c->t_site_sweeps += (int64_t)nsw * c->sites_all_chains;
   }
-  HIP_TRY(c, launch_pass_end<P>(A, c->stream));
+  PassEnd &E = c->pending;
+  E.valid = 1;
+  E.nsw = nsw;
+  E.adapt = adapt;
+  E.has_energy = trace_e;
+  E.sweep0 = (uint32_t)c->sweep_index;
+  E.trace_row0 = trace_row0;
+  E.trace = trace;
+  E.counts = A.counts;
+  E.energy = A.energy;
+  E.a_in = A.a_now;
+  E.win_in = A.win_now;
   c->cur ^= 1;
   c->sweep_index += nsw;
+  c->pass_no += 1;
   return MPR_OK;
+}
+
+// Apply the end of the last pass (a-rule, trace, acceptance sums) so that
+// a, the window and the sums are current in the buffers of pass pass_no.
+template <typename P> mpr_status close_pending(mpr_ctx *c) {
+  if (!c->pending.valid) return MPR_OK;
+  SweepArgs<P> A{};
+  A.grids = c->v.gd;
+  A.n_grids = c->n_grids;
+  A.total_chains = c->plan.total_chains;
+  A.adapt_every = c->p.adapt_every;
+  A.a_targ = c->p.a_targ;
+  A.k_a = c->p.k_a;
+  A.pe = c->pending;
+  A.a_now = a_buf(c, c->pass_no);
+  A.win_now = win_buf(c, c->pass_no);
+  A.accsum = c->v.accsum;
+  HIP_TRY(c, launch_pass_end<P>(A, c->stream));
+  c->pending.valid = 0;
+  return MPR_OK;
+}
+
+mpr_status close_pending(mpr_ctx *c) {
+  return c->p.dtype == MPR_FP64 ? close_pending<double>(c) : close_pending<float>(c);
 }
 
 // n sweeps in passes of at most nsw_max; with the a-rule no pass crosses the
@@ -365,7 +411,7 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
     if (st != MPR_OK) return st;
     done += len;
   }
-  return MPR_OK;
+  return close_pending(c);
 }
 
 mpr_status reduce_energy(mpr_ctx *c, int what, std::vector<double> &out) {
@@ -483,7 +529,7 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
   c->plan = plan;
   bind(c->v, plan.v, workspace);
   c->nsw_max = plan.nsw_max;
-  c->threads = p->dtype == MPR_FP64 ? 256 : 512;
+  c->threads = p->dtype == MPR_FP64 ? 256 : 1024;
   if (const char *env = std::getenv("MPR_SWEEP_THREADS")) {
     const int t = std::atoi(env);
     if (t == 256 || t == 512 || t == 1024) c->threads = t;
@@ -556,13 +602,12 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
                            c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
   }
   const int64_t C = c->plan.total_chains;
-  TRY(launch_fill_f64(c->v.a, C, 1.0, c->stream));
-  TRY(launch_fill_f64(c->v.alpha, C, 6.28318530717958647692, c->stream));
+  TRY(launch_fill_f64(c->v.a, 2 * C, 1.0, c->stream));
   TRY(launch_fill_f64(c->v.beta, C, 0.0, c->stream));
-  TRY(launch_fill_f64(c->v.window, C, 0.0, c->stream));
+  TRY(launch_fill_f64(c->v.window, 2 * C, 0.0, c->stream));
   TRY(launch_fill_f64(c->v.accsum, C, 0.0, c->stream));
-  TRY(launch_zero_u32(c->v.counts, C * kMaxPass, c->stream));
-  TRY(launch_fill_f64(c->v.energy, C * kMaxPass, 0.0, c->stream));
+  TRY(launch_zero_u32(c->v.counts, 3 * C * kMaxPass, c->stream));
+  TRY(launch_fill_f64(c->v.energy, 3 * C * kMaxPass, 0.0, c->stream));
   TRY(hipStreamSynchronize(c->stream));
 #undef TRY
   *ctx = c;
@@ -680,13 +725,13 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
   const int64_t C = ctx->plan.total_chains;
   std::vector<double> hv;
   HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
-  HIP_TRY(ctx, launch_fill_f64(ctx->v.window, C, 0.0, ctx->stream));
+  HIP_TRY(ctx, launch_fill_f64(win_buf(ctx, ctx->pass_no), C, 0.0, ctx->stream));
   st = run_sweeps(ctx, n_eq, true, false, nullptr, 0);
   if (st != MPR_OK) return st;
   if (rep && (rep->a_eq || rep->acc_eq)) {
     hv.resize(C);
     if (rep->a_eq) {
-      HIP_TRY(ctx, hipMemcpyAsync(rep->a_eq, ctx->v.a, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipMemcpyAsync(rep->a_eq, a_buf(ctx, ctx->pass_no), 8 * C, hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_TRY(ctx, hipMemcpyAsync(hv.data(), ctx->v.accsum, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -694,8 +739,7 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
       for (int64_t k = 0; k < C; ++k) rep->acc_eq[k] = n_eq ? hv[k] / n_eq : NAN;
   }
   if (!ctx->p.a_sample_keep) {
-    HIP_TRY(ctx, launch_fill_f64(ctx->v.a, C, 1.0, ctx->stream));
-    HIP_TRY(ctx, launch_fill_f64(ctx->v.alpha, C, 6.28318530717958647692, ctx->stream));
+    HIP_TRY(ctx, launch_fill_f64(a_buf(ctx, ctx->pass_no), C, 1.0, ctx->stream));
   }
   HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
   st = run_sweeps(ctx, n_samp, false, false, nullptr, stride);
@@ -786,7 +830,8 @@ mpr_status mpr_get_chain_state(mpr_ctx *ctx, int64_t *sweep_index, double *a) {
   if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
   if (sweep_index) *sweep_index = ctx->sweep_index;
   if (a) {
-    HIP_TRY(ctx, hipMemcpyAsync(a, ctx->v.a, 8 * (size_t)ctx->plan.total_chains, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(a, a_buf(ctx, ctx->pass_no), 8 * (size_t)ctx->plan.total_chains,
+                                hipMemcpyDeviceToHost, ctx->stream));
   }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return MPR_OK;
@@ -798,10 +843,8 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
   if (a) {
     for (int k = 0; k < ctx->plan.total_chains; ++k)
       if (!(a[k] >= 1.0) || !std::isfinite(a[k])) return fail(ctx, MPR_E_ARG, "every a must be finite and >= 1");
-    std::vector<double> al(ctx->plan.total_chains);
-    for (int k = 0; k < ctx->plan.total_chains; ++k) al[k] = 6.28318530717958647692 / a[k];
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->v.a, a, 8 * al.size(), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->v.alpha, al.data(), 8 * al.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(a_buf(ctx, ctx->pass_no), a, 8 * (size_t)ctx->plan.total_chains,
+                                hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   }
   ctx->sweep_index = sweep_index;

@@ -32,6 +32,20 @@ struct GridDesc {
   double zmin, zmax;               // Eq. (2) over the samples; NaN without samples
 };
 
+// The end of a pass whose per-chain acceptance and energy sums are complete
+// but not yet applied: turned into acceptance ratios and trace rows, and run
+// through the a-rule, by the next pass's sweep kernel (or k_pass_end).
+struct PassEnd {
+  int32_t valid;                   // 0: nothing pending
+  int32_t nsw, adapt, has_energy;
+  uint32_t sweep0;                 // global index of that pass's first sweep
+  int64_t trace_row0;
+  double *trace;                   // [rows][chains][2] or nullptr
+  const uint32_t *counts;          // that pass's accepted counts [chains][kMaxPass]
+  const double *energy;            // that pass's energy sums, or nullptr
+  const double *a_in, *win_in;     // a and a-rule window before that pass
+};
+
 template <typename P>
 struct SweepArgs {
   const GridDesc *grids;
@@ -49,11 +63,13 @@ struct SweepArgs {
   const P *src;
   P *dst;
   const double *beta;              // per chain
-  double *a, *alpha, *window, *accsum;  // per chain, updated at the end of each pass
-  uint32_t *counts;                // [chains][kMaxPass] accepted updates
-  double *energy;                  // [chains][kMaxPass] or nullptr
-  int64_t trace_row0;
-  double *trace;                   // [rows][chains][2] or nullptr
+  PassEnd pe;                      // previous pass, if its end is pending
+  double *a_now, *win_now;         // a and window this pass runs with (written by tile 0 if pe.valid)
+  double *accsum;                  // per chain, sum of acceptance ratios (written by tile 0)
+  uint32_t *counts;                // this pass: [chains][kMaxPass] accepted updates
+  double *energy;                  // this pass: [chains][kMaxPass] or nullptr
+  uint32_t *counts_clear;          // buffer of the pass after next, cleared by tile 0
+  double *energy_clear;
   P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
   // Gap-site plan (k_plan): per tile, the gap sites within ring distance
   // plan_dmax of the interior, colour 0 then colour 1, each sorted by ring

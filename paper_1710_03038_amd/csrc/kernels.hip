@@ -73,6 +73,7 @@ template <> struct Prec<float> {
   static constexpr float below_two_pi = 6.2831850f;         // largest float < two_pi
   static constexpr float tiny_h2 = 1e-12f;
   __device__ static float sin_(float x) { return fm::sin(x); }
+  __device__ static float sin_dh_(float x) { return fm::sin_hw(x); }
   __device__ static void sincos_(float x, float *s, float *c) { fm::sincos(x, s, c); }
   __device__ static float atan2_(float y, float x) { return fm::atan2(y, x); }
   __device__ static float exp_(float x) { return fm::exp(x); }
@@ -85,6 +86,7 @@ template <> struct Prec<double> {
   static constexpr double below_two_pi = 6.2831853071795853;  // nextafter(2*pi, 0)
   static constexpr double tiny_h2 = 1e-24;
   __device__ static double sin_(double x) { return ::sin(x); }
+  __device__ static double sin_dh_(double x) { return ::sin(x); }
   __device__ static void sincos_(double x, double *s, double *c) { ::sincos(x, s, c); }
   __device__ static double atan2_(double y, double x) { return ::atan2(y, x); }
   __device__ static double exp_(double x) { return ::exp(x); }
@@ -156,43 +158,41 @@ __device__ __forceinline__ void split_index(int f, int npr, float inv, int &r, i
   }
 }
 
-// End of a pass for one chain (run after the pass's sweep kernel):
-// turn the accepted counts into acceptance ratios, write the trace, and
-// apply the a-rule of Algorithm 2, step 4.2: after sweep i, if the mean
-// acceptance of the adapt_every-window ending there is below A_targ, then
-// a = 1 + (i + 1)/k_a.  Then alpha = 2*pi/a for the next pass.
+// End of a pending pass for one chain: turn the accepted counts into
+// acceptance ratios and trace rows, and apply the a-rule of Algorithm 2,
+// step 4.2: after sweep i, if the mean acceptance of the adapt_every-window
+// ending there is below A_targ, then a = 1 + (i + 1)/k_a.  Every caller
+// computes the same a from the same read-only inputs; only the caller with
+// write = true stores a, the window, the trace and the acceptance sums.
 template <typename P>
-__device__ void chain_pass_end(const SweepArgs<P> &A, const GridDesc &G, int ch) {
-  double a = A.a[ch];
-  for (int s = 0; s < A.nsw; ++s) {
+__device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int ch, bool write) {
+  const PassEnd &E = A.pe;
+  double a = E.a_in[ch], win = E.win_in[ch];
+  double accs = 0.0;
+  for (int s = 0; s < E.nsw; ++s) {
     const int64_t k = (int64_t)ch * kMaxPass + s;
-    const uint32_t cnt = A.counts[k];
-    A.counts[k] = 0u;
-    const double acc = G.n_gap > 0 ? (double)cnt / (double)G.n_gap : 1.0;
-    A.accsum[ch] += acc;
-    double e = __builtin_nan("");
-    if (A.energy) {
-      e = A.energy[k] / (double)G.n_pairs - 1.0;
-      A.energy[k] = 0.0;
-    }
-    if (A.trace) {
-      double *tr = A.trace + ((A.trace_row0 + s) * A.total_chains + ch) * 2;
+    const double acc = G.n_gap > 0 ? (double)E.counts[k] / (double)G.n_gap : 1.0;
+    accs += acc;
+    if (write && E.trace) {
+      double *tr = E.trace + ((E.trace_row0 + s) * A.total_chains + ch) * 2;
       tr[0] = acc;
-      tr[1] = e;
+      tr[1] = E.has_energy ? E.energy[k] / (double)G.n_pairs - 1.0 : __builtin_nan("");
     }
-    if (A.adapt) {
-      const double win = A.window[ch] + acc;
-      const uint32_t i = A.sweep0 + (uint32_t)s;
+    if (E.adapt) {
+      win += acc;
+      const uint32_t i = E.sweep0 + (uint32_t)s;
       if ((i + 1) % (uint32_t)A.adapt_every == 0) {
         if (win / (double)A.adapt_every < A.a_targ) a = 1.0 + (double)(i + 1) / A.k_a;
-        A.window[ch] = 0.0;
-      } else {
-        A.window[ch] = win;
+        win = 0.0;
       }
     }
   }
-  A.a[ch] = a;
-  A.alpha[ch] = 6.28318530717958647692 / a;
+  if (write) {
+    A.a_now[ch] = a;
+    A.win_now[ch] = win;
+    A.accsum[ch] += accs;
+  }
+  return a;
 }
 
 // ---------------------------------------------------------------- sweep
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   using V2 = typename Prec<P>::V2;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_d[NT / 64];
-  __shared__ uint32_t red_u[NT / 64];
+  __shared__ uint32_t acc_lds[kMaxPass];
 
   const int64_t item = blockIdx.x;
   const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin);
@@ -253,6 +253,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   }
   __syncthreads();
 
+  if (threadIdx.x < kMaxPass) acc_lds[threadIdx.x] = 0u;
   // Stage this pass's part of the tile's gap-site plan: colour-0 entries
   // within ring 2*nsw, then colour-1 entries within ring 2*nsw - 1.
   uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);
@@ -269,7 +270,13 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   __syncthreads();
 
   const int gchain = G.chain_base + chain;
-  const P beta = (P)A.beta[gchain], alpha = (P)A.alpha[gchain];
+  // Close the previous pass (every tile derives the same a; tile 0 records).
+  const double a_d = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0 && threadIdx.x == 0) : A.a_now[gchain];
+  if (t == 0 && threadIdx.x < kMaxPass) {
+    A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
+    A.energy_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0.0;
+  }
+  const P beta = (P)A.beta[gchain], alpha = (P)(6.28318530717958647692 / a_d);
   const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
   const int iw = ix1 - x0, ih = iy1 - y0;
   const float inv_iw = 1.0f / (float)iw;
@@ -318,8 +325,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         const P p2 = wrap_step(p1 + alpha * (u - P(0.5)));
         // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
         //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
-        P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_(q * (p2 + p1) * P(0.5) - psi) *
-               Prec<P>::sin_(q * (p2 - p1) * P(0.5));
+        P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_dh_(q * (p2 + p1) * P(0.5) - psi) *
+               Prec<P>::sin_dh_(q * (p2 - p1) * P(0.5));
         dH = live ? dH : P(0);
         // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
         const bool ok = (dH <= P(0)) || (rr < Prec<P>::exp_(-beta * dH));
@@ -333,8 +340,11 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       __syncthreads();
     }
 
-    const uint32_t tot = block_sum<NT>(acc, red_u);
-    if (threadIdx.x == 0 && tot) atomicAdd(&A.counts[(int64_t)gchain * kMaxPass + s], tot);
+    {
+      const uint32_t wsum = wave_sum(acc);
+      if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(&acc_lds[s], wsum);
+    }
+    const bool rec = (A.record_mask >> s) & 1u;
     if (A.energy) {
       // Eq. (5): pairs (x, y)-(x+1, y) and (x, y)-(x, y+1) owned by interior sites.
       P e = P(0);
@@ -359,7 +369,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       const double et = block_sum<NT>((double)e, red_d);
       if (threadIdx.x == 0) atomicAdd(&A.energy[(int64_t)gchain * kMaxPass + s], et);
     }
-    if ((A.record_mask >> s) & 1u) {
+    if (rec) {
       // Algorithm 2, step 5.3: one realisation; shifted sums about the first.
       const bool first = (A.first_mask >> s) & 1u;
       for (int f = threadIdx.x; f < iw * ih; f += NT) {
@@ -381,8 +391,11 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         }
       }
     }
-    __syncthreads();
+    if (A.energy || rec) __syncthreads();  // the next sweep overwrites what was read
   }
+  __syncthreads();
+  if (threadIdx.x < A.nsw && acc_lds[threadIdx.x])
+    atomicAdd(&A.counts[(int64_t)gchain * kMaxPass + threadIdx.x], acc_lds[threadIdx.x]);
 
   P *dst = A.dst + cbase;
   for (int f = threadIdx.x; f < iw * ih; f += NT) {
@@ -467,7 +480,7 @@ template hipError_t launch_plan<float>(const GridDesc *, int, int64_t, const flo
 template hipError_t launch_plan<double>(const GridDesc *, int, int64_t, const double *, int, int, int, uint16_t *,
                                         uint32_t *, hipStream_t);
 
-// One thread per chain, after the sweep kernel of a pass: close the pass.
+// One thread per chain: close the last pass of a run.
 template <typename P>
 __global__ void k_pass_end(const SweepArgs<P> A) {
   const int ch = blockIdx.x * blockDim.x + threadIdx.x;
@@ -478,7 +491,7 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
     if (A.grids[mid].chain_base <= ch) lo = mid;
     else hi = mid - 1;
   }
-  chain_pass_end(A, A.grids[lo], ch);
+  apply_pass_end(A, A.grids[lo], ch, true);
 }
 
 template <typename P>
