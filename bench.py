@@ -30,6 +30,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spin-updates/sec + realisations/sec, batched FP32 vs plain FP64, equal MAE"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-
+# instructions per second (the published 157.3 TFLOP/s FP32 counts a packed
+# two-wide FMA, 4 flops, per lane-instruction).
+VALU_PEAK_TINST = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU lane-instructions of one FP32 gap-site update in the compiled sweep
+# kernel (the update loop of k_sweep<float>: 211 VALU instructions, of
+# which 21 v_mad_u64_u32 for Philox and 6 transcendental).
+VALU_INST_PER_UPDATE = 211
 
 
 def bytes_per_site_sweep(elem, p):
@@ -79,6 +87,46 @@ def run_arm(M, zt, kt, spec, table, params, steps, warmup):
     return dt, out, (kms, kl, kss)
 
 
+KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
+                  "paper_1710_03038_amd/csrc/internal.h")
+PROFILE = "profiles/k_sweep_fp32_grid1024.md"
+
+
+def profiled_traffic():
+    """HBM bytes per sweep launch measured by rocprofv3 (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy) for the default configuration, or
+    None when the kernel sources changed since that profile was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, PROFILE)).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+) kernel_sources_sha256: ([0-9a-f]+)", text)
+    if not m or m.group(2) != h.hexdigest():
+        return None
+    return float(m.group(1))
+
+
+def copy_calibration(nbytes=256 << 20, reps=10):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters of rocprofv3 to bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "GBps": 2 * nbytes / dt / 1e9}), flush=True)
+
+
 def cpu_baseline(z, known, T, spec, sweeps):
     """The FP64 NumPy oracle timed on this host on a bounded sample: the
     first ``sweeps`` hybrid sweeps of the same workload from the hot start."""
@@ -104,13 +152,17 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the MPR path here is a single-GPU build; "
               "chains and grids would shard across GPUs with no exchange during sweeps.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     from paper_1710_03038_amd import mpr as M
     from paper_1710_03038_amd.etable import load_table
@@ -134,14 +186,23 @@ def main():
     records = out32[2]["records"] * chains
 
     # plain FP64 arm: one sweep per pass, library default tiles, same input
-    prm64 = M.default_params(dtype="fp64", seed=spec["seed"], sweeps_per_pass=1)
-    dt64, out64, (kms64, kl64, kss64) = run_arm(M, zt, kt, spec, table, prm64, args.fp64_steps, 0)
-    zh64 = out64[0].cpu().numpy()
-    mae64 = float(np.abs(zh64[~kn] - z[~kn]).mean())
+    fp64 = None
+    if args.fp64_steps > 0:
+        prm64 = M.default_params(dtype="fp64", seed=spec["seed"], sweeps_per_pass=1)
+        dt64, out64, _ = run_arm(M, zt, kt, spec, table, prm64, args.fp64_steps, 0)
+        zh64 = out64[0].cpu().numpy()
+        mae64 = float(np.abs(zh64[~kn] - z[~kn]).mean())
+        fp64 = {"spin_updates_per_s": updates / dt64, "realisations_per_s": records / dt64,
+                "ms_per_step": dt64 * 1e3, "mae": mae64, "speedup_fp32_over_fp64": dt64 / dt32}
 
     elem = 4
     b_site = bytes_per_site_sweep(elem, p)
-    achieved = kss * b_site / (kms * 1e-3) / 1e9 if kms > 0 else None
+    default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
+                      and "MPR_SWEEP_THREADS" not in os.environ)
+    ksec = kms * 1e-3
+    hbm_gbs = kss * b_site / ksec / 1e9 if kms > 0 else None
+    useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
+    achieved = useful_updates * VALU_INST_PER_UPDATE / ksec / 1e12 if kms > 0 else None
     res = {
         "metric": METRIC,
         "value": updates / dt32,
@@ -162,13 +223,17 @@ def main():
                    "T_hat": out32[3], "e_s": out32[4]},
         "realisations_per_s": records / dt32,
         "mae_fp32": mae32,
-        "fp64_plain": {"spin_updates_per_s": updates / dt64, "realisations_per_s": records / dt64,
-                       "ms_per_step": dt64 * 1e3, "mae": mae64, "speedup_fp32_over_fp64": dt64 / dt32},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep<float>",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "bytes_per_site_sweep": b_site, "avg_launch_us": kms * 1e3 / kl if kl else None,
-                     "launches": kl, "site_sweeps_per_launch": kss / kl if kl else None},
+        "fp64_plain": fp64,
+        "roofline": {"bound": "alu", "kernel": "k_sweep<float>",
+                     "achieved": achieved, "peak": VALU_PEAK_TINST, "unit": "Tinst/s (VALU lane-instructions)",
+                     "frac": (achieved / VALU_PEAK_TINST) if achieved else None,
+                     "traffic": profiled_traffic() if default_config else None,
+                     "inst_per_update": VALU_INST_PER_UPDATE,
+                     "avg_launch_us": kms * 1e3 / kl if kl else None, "launches": kl,
+                     "site_sweeps_per_launch": kss / kl if kl else None,
+                     "hbm_one_pass": {"achieved_GBps": hbm_gbs, "peak_GBps": HBM_PEAK_GBS,
+                                      "frac": hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
+                                      "bytes_per_site_sweep": b_site}},
     }
     if not args.no_cpu:
         os.environ.setdefault("OMP_NUM_THREADS", "1")

@@ -56,6 +56,9 @@ def lib():
     """The loaded libmpr.so (ctypes.CDLL).  Raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch first: libmpr.so then binds to the HIP runtime torch has
+        # loaded, so both share one runtime, device list and streams.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_03038_amd.build`")
         L = ctypes.CDLL(LIB_PATH)

@@ -1,0 +1,23 @@
+"""Both e(T) tables against what the mathematics fixes: monotone in T, the
+low-temperature equipartition slope eps = (L + 1) T / (4 L) of an
+unconditional L x L grid (harmonic limit of Eq. 3), and the infinite-
+temperature limit e = -4/pi^2 for q = 1/2 as an upper bound."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.etable import load_table as load_oracle_table
+from paper_1710_03038_amd.etable import load_table as load_product_table
+
+
+@pytest.mark.parametrize("loader,L", [(load_oracle_table, 32), (load_product_table, 128)])
+def test_table_shape_and_limits(loader, L):
+    T, e, err = loader()
+    assert np.all(np.diff(T) > 0) and np.all(np.diff(e) > 0)
+    eps = 1.0 + e
+    low = T < 3e-3
+    ratio = eps[low] / ((L + 1) * T[low] / (4 * L))
+    assert np.all(np.abs(ratio - 1.0) < 0.01), ratio
+    assert np.all(e < -4.0 / math.pi ** 2)
+    assert np.all(err < 5e-3 * eps + 1e-12)
