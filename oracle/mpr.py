@@ -65,13 +65,18 @@ def split_seed(seed):
     return seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
 
 
-def site_uniforms(seed, ny, nx, sweep, chains, grid):
-    """Uniforms (u, r) of every site for one sweep; arrays (C, ny, nx)."""
+def site_uniforms(seed, ny, nx, sweep, chains, grid, origin=(0, 0), npair=None):
+    """Uniforms (u, r) of every site for one sweep; arrays (C, ny, nx).
+
+    ``origin`` and ``npair`` place the array as a window at (y0, x0) of a
+    larger grid with ``npair`` Philox pairs per row: the stream is keyed by
+    the sites' coordinates in that grid.
+    """
     k0, k1 = split_seed(seed)
     chains = np.asarray(chains, dtype=np.uint64).reshape(-1, 1, 1)
-    y = np.arange(ny, dtype=np.uint64).reshape(1, ny, 1)
-    x = np.arange(nx, dtype=np.uint64).reshape(1, 1, nx)
-    npair = (nx + 1) // 2
+    y = np.arange(origin[0], origin[0] + ny, dtype=np.uint64).reshape(1, ny, 1)
+    x = np.arange(origin[1], origin[1] + nx, dtype=np.uint64).reshape(1, 1, nx)
+    npair = (nx + 1) // 2 if npair is None else npair
     pair = y * np.uint64(npair) + x // np.uint64(2)
     w0, w1, w2, w3 = philox4x32(pair, sweep, chains, grid, k0, k1)
     even = (x % np.uint64(2)) == 0
@@ -83,16 +88,22 @@ def site_uniforms(seed, ny, nx, sweep, chains, grid):
 # --------------------------------------------------------------------------
 # Data transform, Eq. (2), and its inverse (Algorithm 2, step 5.3)
 # --------------------------------------------------------------------------
-def transform(z, known):
+def transform(z, known, bounds=None):
     """Map sample values linearly onto [0, 2*pi]; gaps are set to 0.
 
-    Returns (phi, z_min, z_max) with z_min, z_max taken over the samples.
+    Returns (phi, z_min, z_max) with z_min, z_max taken over the samples,
+    or given as ``bounds`` (for a window of a larger grid).
     """
     z = np.asarray(z, dtype=np.float64)
     known = np.asarray(known, dtype=bool)
+    zs = z[known]
+    if bounds is not None:
+        zmin, zmax = bounds
+        phi = np.zeros(z.shape, dtype=np.float64)
+        phi[known] = (zs - zmin) / (zmax - zmin) * TWO_PI
+        return phi, float(zmin), float(zmax)
     if not known.any():
         raise OracleError("no sample sites")
-    zs = z[known]
     if not np.all(np.isfinite(zs)):
         raise OracleError("non-finite sample value")
     zmin, zmax = zs.min(), zs.max()
@@ -107,11 +118,12 @@ def inverse_transform(phi, zmin, zmax):
     return zmin + (zmax - zmin) * (np.asarray(phi, dtype=np.float64) / TWO_PI)
 
 
-def hot_start(phi_s, known, seed, chains, grid):
-    """Paramagnetic start: every gap gets 2*pi*U (Algorithm 2, step 1.8)."""
+def hot_start(phi_s, known, seed, chains, grid, origin=(0, 0), npair=None):
+    """Paramagnetic start: every gap gets 2*pi*U (Algorithm 2, step 1.8).
+    origin, npair: a window of a larger grid (see site_uniforms)."""
     ny, nx = phi_s.shape
     chains = np.atleast_1d(np.asarray(chains))
-    u, _ = site_uniforms(seed, ny, nx, HOT_START_SWEEP, chains, grid)
+    u, _ = site_uniforms(seed, ny, nx, HOT_START_SWEEP, chains, grid, origin, npair)
     phi = np.where(known[None], phi_s[None], TWO_PI * u)
     return phi
 
@@ -209,7 +221,7 @@ def site_energy(phi, nbrs, q):
     return -sum(np.where(np.isnan(n), 0.0, np.cos(q * (phi - np.nan_to_num(n)))) for n in nbrs)
 
 
-def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None):
+def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), npair=None):
     """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
 
     phi: (C, ny, nx) float64 current states (not modified).
@@ -222,14 +234,17 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
       "or_edge" = distance of the reflected angle from 0 and 2*pi, "wrap" =
       distance of the unwrapped proposal from 0 and 2*pi.  inf at sites not
       updated.
+    origin, npair: run on a window of a larger grid (see site_uniforms);
+      the window's edges are then open boundaries, which is exact only for
+      sites far enough from them.
     Returns (new phi, accepted count per chain).
     """
     phi = np.array(phi, dtype=np.float64, copy=True)
     C, ny, nx = phi.shape
     beta = np.broadcast_to(np.asarray(beta, dtype=np.float64), (C,)).reshape(C, 1, 1)
     alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (C,)).reshape(C, 1, 1)
-    u, r = site_uniforms(seed, ny, nx, sweep, chains, grid)
-    yy, xx = np.mgrid[0:ny, 0:nx]
+    u, r = site_uniforms(seed, ny, nx, sweep, chains, grid, origin, npair)
+    yy, xx = np.mgrid[origin[0]:origin[0] + ny, origin[1]:origin[1] + nx]
     accepted = np.zeros(C, dtype=np.int64)
     if margins is not None:
         for k in ("accept", "or_edge", "wrap"):

@@ -1,0 +1,141 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+bench.py times (library defaults: 64 x 64 tiles, 8 sweeps per pass in FP32,
+1024-thread workgroups), on outputs the oracle computes window by window.
+
+After k sweeps a site depends only on sites within 2k of it, so the oracle
+runs on a window plus a (2k+1)-site halo of the full grid, with its random
+stream keyed by full-grid coordinates, transform bounds of the full grid and
+a hot start computed on the window itself: every oracle input comes from the
+oracle.  The window interior is then exact and is compared site by site.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mpr as om
+from tests.gpu_util import TWO_PI, as_fp32_state, beta_of, explained_mismatches, make_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _windows(ny, nx, w=64):
+    """Corner, edge and centre windows (y0, y1, x0, x1)."""
+    cy, cx = ny // 2 - w // 2, nx // 2 - w // 2
+    return [(0, w, 0, w), (ny - w, ny, nx - w, nx), (cy, cy + w, cx, cx + w), (0, w, cx, cx + w)]
+
+
+def _oracle_window(z, known, bounds, seed, chain, grid, T, a, sweep0, nsw, win, dtype):
+    ny, nx = z.shape
+    y0, y1, x0, x1 = win
+    H = 2 * nsw + 1
+    ey0, ey1, ex0, ex1 = max(y0 - H, 0), min(y1 + H, ny), max(x0 - H, 0), min(x1 + H, nx)
+    kw = known[ey0:ey1, ex0:ex1].astype(bool)
+    ws, _, _ = om.transform(z[ey0:ey1, ex0:ex1], kw, bounds=bounds)
+    npair = (nx + 1) // 2
+    phi = om.hot_start(ws, kw, seed, [chain], grid, origin=(ey0, ex0), npair=npair)
+    if dtype == "fp32":
+        phi = as_fp32_state(phi[0], kw)[None]
+    margins = {}
+    for s in range(nsw):
+        phi, _ = om.hybrid_sweep(phi, kw, [beta_of(T)], [TWO_PI / a], 0.5, seed, sweep0 + s, [chain], grid,
+                                 margins=margins, origin=(ey0, ex0), npair=npair)
+    cut = (slice(y0 - ey0, y1 - ey0), slice(x0 - ex0, x1 - ex0))
+    return phi[0][cut], {k: v[0][cut] for k, v in margins.items()}, kw[cut]
+
+
+def _check_workload(name, chains_checked, dtype, nsw, T=None, a=2.0, sweep0=3):
+    import mprgen
+    z, known, spec = mprgen.workload(name)
+    kn = known.astype(bool)
+    bounds = (float(z[kn].min()), float(z[kn].max()))
+    if T is None:
+        phi_s, _, _ = om.transform(z, kn, bounds=bounds)
+        es, _, _ = om.sample_specific_energy(phi_s, kn, 0.5)
+        T = 4.0 * (1.0 + es)           # low-temperature estimate of the fitted T
+    params = dict(dtype=dtype, seed=spec["seed"])
+    if dtype == "fp64":
+        params["sweeps_per_pass"] = nsw
+    f = make_field([(z, known, spec["chains"])], **params)
+    f.set_chain_state(sweep0, np.full(f.total_chains, a))
+    f.sweep(nsw, [T])
+    ny, nx = z.shape
+    total_bad = total_gap = 0
+    for c in chains_checked:
+        got_full = f.get_phi(0, c).cpu().numpy()
+        for win in _windows(ny, nx):
+            ref, margins, kw = _oracle_window(z, known, bounds, spec["seed"], c, 0, T, a, sweep0, nsw, win, dtype)
+            got = got_full[win[0]:win[1], win[2]:win[3]]
+            if dtype == "fp64":
+                d = float(np.abs(got - ref).max())
+                assert d <= 1e-5, (name, c, win, d)
+            else:
+                n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, kw, 1e-3)
+                assert len(unexpl) == 0, (name, c, win, unexpl[:4])
+                total_bad += n_bad
+                total_gap += int((~kw).sum())
+    if dtype == "fp32":
+        assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+    f.close()
+
+
+def test_grid1024_fp64_full_pass():
+    # FP64: one 8-sweep pass (the fused path), exact within 1e-5 rad
+    _check_workload("grid1024", [0], "fp64", 8)
+
+
+def test_grid1024_fp32_one_sweep():
+    _check_workload("grid1024", [0], "fp32", 1)
+
+
+def test_grid512x512chains_fp32_one_sweep():
+    _check_workload("grid512x512chains", [0, 255, 511], "fp32", 1)
+
+
+def test_grid512x512chains_fp64_full_pass():
+    _check_workload("grid512x512chains", [0, 511], "fp64", 4)
+
+
+def test_grid8192x64chains_fp32_one_sweep():
+    _check_workload("grid8192x64chains", [0, 63], "fp32", 1)
+
+
+@pytest.mark.parametrize("name,chains", [("grid1024", [0]), ("grid512x512chains", [0, 300])])
+def test_bench_pass_equals_single_sweep_passes(name, chains):
+    # The sampling passes bench.py times fuse 8 sweeps; their output must be
+    # bit-identical to 8 single-sweep passes (which the tests above check).
+    import mprgen
+    z, known, spec = mprgen.workload(name)
+    T = 1e-3
+    outs = []
+    for nsw in (0, 1):   # 0: library default (8 per pass), 1: one per pass
+        f = make_field([(z, known, spec["chains"])], dtype="fp32", seed=spec["seed"], sweeps_per_pass=nsw)
+        f.sweep(8, [T])
+        outs.append([f.get_phi(0, c).cpu().numpy() for c in chains])
+        f.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_fill_grid1024_fp32_vs_fp64_equal_mae():
+    """The bench's two arms reach the same gap-fill MAE against the held-out
+    truth (3 sigma over seeds): the FP32/FP64 speed factor is quoted at equal
+    accuracy."""
+    import mprgen
+    from oracle.etable import load_table
+    tT, te, _ = load_table()
+    z, known, spec = mprgen.workload("grid1024")
+    kn = known.astype(bool)
+    maes = {"fp32": [], "fp64": []}
+    for r in range(4):
+        for dt in ("fp32", "fp64"):
+            f = make_field([(z, known, 1)], dtype=dt, seed=spec["seed"] + 1000 * r,
+                           sweeps_per_pass=(1 if dt == "fp64" else 0))
+            e_s, _ = f.specific_energy(0)
+            T, _ = om.match_T(e_s, tT, te)
+            zh, _, _ = f.fill(T, 100, 200, 2)
+            maes[dt].append(om.mae(z, zh[0].cpu().numpy(), ~kn))
+            f.close()
+    m32, m64 = np.mean(maes["fp32"]), np.mean(maes["fp64"])
+    s = math.hypot(np.std(maes["fp32"], ddof=1), np.std(maes["fp64"], ddof=1)) / math.sqrt(4)
+    assert abs(m32 - m64) <= 3 * s + 1e-4, (maes, s)
