@@ -3,8 +3,10 @@
 
 One step = the whole path on one synthetic workload with inputs resident in
 HBM: mpr_init_field (Eq. 2, hot start), mpr_specific_energy (Eq. 4),
-mpr_match_T (SEM, Sec. 2.3) and mpr_fill (Algorithm 2 with fixed counts:
-equilibration with the a-rule, sampling, conditional mean and std).
+mpr_match_T (specific energy matching, Sec. 2.3, one T per grid),
+mpr_autotune (a cached lookup after the first step) and mpr_fill
+(Algorithm 2 with fixed counts: equilibration with the a-rule, sampling,
+conditional mean and std).
 
 Prints one JSON line.  value = spin-updates/s (hybrid updates of gap sites,
 whole job); realisations/s is reported beside it.  The default workload is
@@ -14,10 +16,12 @@ sampling, every 9th recorded: 100 realisations), FP32.  The plain FP64 arm
 (one sweep per pass) and the FP64 CPU oracle are timed on the same input.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+
+Workloads: grid64_fp64, grid1024 (default), grid512x512chains,
+grid8192x64chains, uneven2000.
 """
 import argparse
 import json
-import math
 import os
 import platform
 import sys
@@ -38,58 +42,15 @@ VALU_PEAK_TINST = 256 * 4 * 16 * 2.4e9 / 1e12
 # kernel (the update loop of k_sweep<float>: 211 VALU instructions, of
 # which 21 v_mad_u64_u32 for Philox and 6 transcendental).
 VALU_INST_PER_UPDATE = 211
+KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
+                  "paper_1710_03038_amd/csrc/internal.h")
+PROFILE = "profiles/k_sweep_fp32_grid1024.md"
 
 
 def bytes_per_site_sweep(elem, p):
     """Algorithmic HBM bytes of one site in one single-pass sweep: read the
     angle, write it back at gap sites, one mask bit."""
     return elem * (1.0 + p) + 0.125
-
-
-def load_inputs(name):
-    import torch
-
-    import mprgen
-    z, known, spec = mprgen.workload(name)
-    dev = torch.device("cuda:0")
-    zt = torch.from_numpy(z).to(dev)
-    kt = torch.from_numpy(known).to(dev)
-    return z, known, zt, kt, spec
-
-
-def one_step(M, zt, kt, spec, table, params, timing=False):
-    f = M.Field([(zt, kt, spec["chains"])], params)
-    if timing:
-        f.set_timing(True)
-    e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
-    T, _ = M.match_T(e_s, table[0], table[1])
-    zh, zs, rep = f.fill(T, spec["n_eq"], spec["n_samp"], spec["stride"])
-    kt_ = f.timing() if timing else (0.0, 0, 0)
-    f.close()
-    return zh[0], zs[0], rep, float(T[0]), float(e_s[0]), kt_
-
-
-def run_arm(M, zt, kt, spec, table, params, steps, warmup):
-    import torch
-    for _ in range(warmup):
-        one_step(M, zt, kt, spec, table, params)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kms = kl = kss = 0
-    out = None
-    for _ in range(steps):
-        out = one_step(M, zt, kt, spec, table, params, timing=True)
-        kms += out[5][0]
-        kl += out[5][1]
-        kss += out[5][2]
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    return dt, out, (kms, kl, kss)
-
-
-KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
-                  "paper_1710_03038_amd/csrc/internal.h")
-PROFILE = "profiles/k_sweep_fp32_grid1024.md"
 
 
 def profiled_traffic():
@@ -127,18 +88,95 @@ def copy_calibration(nbytes=256 << 20, reps=10):
                       "GBps": 2 * nbytes / dt / 1e9}), flush=True)
 
 
-def cpu_baseline(z, known, T, spec, sweeps):
-    """The FP64 NumPy oracle timed on this host on a bounded sample: the
-    first ``sweeps`` hybrid sweeps of the same workload from the hot start."""
-    from oracle import mpr as om
-    kn = known.astype(bool)
-    phi_s, _, _ = om.transform(z, kn)
-    phi = om.hot_start(phi_s, kn, spec["seed"], [0], 0)
+def _batch_grid(spec):
+    import mprgen
+    return mprgen.batch_grid(spec)
+
+
+def load_workload(name):
+    """Host inputs of a named workload: grids [(z, known)], chains per grid,
+    sweep counts, Philox seed and a description."""
+    import mprgen
+    if name == "uneven2000":
+        specs = mprgen.uneven_batch(2000, seed=401)
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+            grids = pool.map(_batch_grid, specs, chunksize=8)
+        return dict(grids=grids, chains=[1] * len(grids), n_eq=100, n_samp=100, stride=1, seed=403,
+                    config={"grids": len(grids), "sides": "log-uniform [32, 2048]", "gap_fraction_per_grid":
+                            "U(0.1, 0.9)", "field": "Gaussian or lognormal", "chains": 1})
+    z, known, spec = mprgen.workload(name)
+    return dict(grids=[(z, known)], chains=[spec["chains"]], n_eq=spec["n_eq"], n_samp=spec["n_samp"],
+                stride=spec["stride"], seed=spec["seed"],
+                config={"grid": [spec["n"], spec["n"]], "field": spec["field"], "corr_len": spec["corr_len"],
+                        "mask": spec["mask"], "chains": spec["chains"]})
+
+
+def one_step(M, dev_grids, W, table, params, timing=False):
+    f = M.Field(dev_grids, params)
+    if timing:
+        f.set_timing(True)
+    e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
+    T, _ = M.match_T(e_s, table[0], table[1])
+    tuned = f.autotune(T, 16) if params.dtype == M.FP32 else (1, None)
+    zh, zs, rep = f.fill(T, W["n_eq"], W["n_samp"], W["stride"])
+    kt = f.timing() if timing else (0.0, 0, 0)
+    f.close()
+    return zh, rep, T, e_s, kt, tuned
+
+
+def run_arm(M, dev_grids, W, table, params, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        one_step(M, dev_grids, W, table, params)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    phi, a, _, _ = om.run_sweeps(phi, kn, T, 1.0, 0.5, spec["seed"], 0, sweeps, [0], 0, adapt=True)
-    dt = time.perf_counter() - t0
-    P = int((~kn).sum())
-    return sweeps * P / dt, dt
+    kms = kl = kss = 0
+    out = None
+    for _ in range(steps):
+        out = one_step(M, dev_grids, W, table, params, timing=True)
+        kms += out[4][0]
+        kl += out[4][1]
+        kss += out[4][2]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, out, (kms, kl, kss)
+
+
+def fill_mae(W, zh):
+    err = n = 0.0
+    for (z, known), h in zip(W["grids"], zh):
+        gap = known == 0
+        err += float(np.abs(h.cpu().numpy()[gap] - z[gap]).sum())
+        n += int(gap.sum())
+    return err / n
+
+
+def cpu_baseline(W, T, budget_s=10.0, max_side=1024):
+    """The FP64 NumPy oracle timed on this host on a bounded sample of the
+    same workload: hybrid sweeps (with the a-rule) of its grids in order,
+    each cut to at most max_side x max_side, until budget_s has elapsed."""
+    from oracle import mpr as om
+    done = 0
+    spent = 0.0
+    used = []
+    for g, (z, known) in enumerate(W["grids"]):
+        kn = known.astype(bool)
+        zc, kc = z[:max_side, :max_side], kn[:max_side, :max_side]
+        phi_s, _, _ = om.transform(zc, kc, bounds=(float(z[kn].min()), float(z[kn].max())))
+        phi = om.hot_start(phi_s, kc, W["seed"], [0], g)
+        P = int((~kc).sum())
+        s = 0
+        t0 = time.perf_counter()
+        while s < 2 or (time.perf_counter() - t0 < budget_s - spent and s < 1000):
+            phi, _, _, _ = om.run_sweeps(phi, kc, T[g], 1.0, 0.5, W["seed"], s, 1, [0], g, adapt=True)
+            s += 1
+        spent += time.perf_counter() - t0
+        done += s * P
+        used.append((zc.shape, s))
+        if spent >= budget_s:
+            break
+    return done / spent, spent, used
 
 
 def main():
@@ -151,58 +189,69 @@ def main():
     ap.add_argument("--tile", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the MPR path here is a single-GPU build; "
-              "chains and grids would shard across GPUs with no exchange during sweeps.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures one GPU; chains and "
+              "grids would shard across GPUs with no exchange during sweeps.", file=sys.stderr)
         sys.exit(2)
-
     if args.copy_calibration:
         copy_calibration()
         return
+
+    import torch
 
     from paper_1710_03038_amd import mpr as M
     from paper_1710_03038_amd.etable import load_table
 
     M.lib()
     table = load_table()
-    z, known, zt, kt, spec = load_inputs(args.workload)
-    kn = known.astype(bool)
-    P = int((~kn).sum())
-    N = z.size
-    p = P / N
-    chains = spec["chains"]
-    sweeps = spec["n_eq"] + spec["n_samp"]
+    W = load_workload(args.workload)
+    dev = torch.device("cuda:0")
+    dev_grids = [(torch.from_numpy(z).to(dev), torch.from_numpy(k).to(dev), c)
+                 for (z, k), c in zip(W["grids"], W["chains"])]
+    gaps = [int((k == 0).sum()) for _, k in W["grids"]]
+    sites = [int(k.size) for _, k in W["grids"]]
+    P = sum(g * c for g, c in zip(gaps, W["chains"]))
+    p = sum(gaps) / sum(sites)
+    sweeps = W["n_eq"] + W["n_samp"]
+    updates = sweeps * P
 
-    prm32 = M.default_params(dtype="fp32", seed=spec["seed"], sweeps_per_pass=args.sweeps_per_pass,
+    prm32 = M.default_params(dtype="fp32", seed=W["seed"], sweeps_per_pass=args.sweeps_per_pass,
                              tile_x=args.tile[0], tile_y=args.tile[1])
-    dt32, out32, (kms, kl, kss) = run_arm(M, zt, kt, spec, table, prm32, args.steps, args.warmup)
-    zh32 = out32[0].cpu().numpy()
-    mae32 = float(np.abs(zh32[~kn] - z[~kn]).mean())
-    updates = sweeps * P * chains
-    records = out32[2]["records"] * chains
+    dt32, out32, (kms, kl, kss) = run_arm(M, dev_grids, W, table, prm32, args.steps, args.warmup)
+    mae32 = fill_mae(W, out32[0])
+    records = out32[1]["records"] * sum(W["chains"])
+    T_hat = out32[2]
 
     # plain FP64 arm: one sweep per pass, library default tiles, same input
     fp64 = None
     if args.fp64_steps > 0:
-        prm64 = M.default_params(dtype="fp64", seed=spec["seed"], sweeps_per_pass=1)
-        dt64, out64, _ = run_arm(M, zt, kt, spec, table, prm64, args.fp64_steps, 0)
-        zh64 = out64[0].cpu().numpy()
-        mae64 = float(np.abs(zh64[~kn] - z[~kn]).mean())
+        torch.cuda.empty_cache()
+        prm64 = M.default_params(dtype="fp64", seed=W["seed"], sweeps_per_pass=1)
+        dt64, out64, _ = run_arm(M, dev_grids, W, table, prm64, args.fp64_steps, 0)
+        mae64 = fill_mae(W, out64[0])
         fp64 = {"spin_updates_per_s": updates / dt64, "realisations_per_s": records / dt64,
                 "ms_per_step": dt64 * 1e3, "mae": mae64, "speedup_fp32_over_fp64": dt64 / dt32}
+        del out64
+        torch.cuda.empty_cache()
 
-    elem = 4
-    b_site = bytes_per_site_sweep(elem, p)
-    default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
-                      and "MPR_SWEEP_THREADS" not in os.environ)
+    b_site = bytes_per_site_sweep(4, p)
     ksec = kms * 1e-3
     hbm_gbs = kss * b_site / ksec / 1e9 if kms > 0 else None
     useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
     achieved = useful_updates * VALU_INST_PER_UPDATE / ksec / 1e12 if kms > 0 else None
+    default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
+                      and "MPR_SWEEP_THREADS" not in os.environ)
+    cfg = dict(W["config"])
+    cfg.update({"workload": args.workload, "gap_fraction": p, "n_eq": W["n_eq"], "n_samp": W["n_samp"],
+                "stride": W["stride"], "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
+                "sweeps_per_pass_max": prm32.sweeps_per_pass or 8,
+                "autotuned_sweeps_per_pass_threads": list(out32[5]),
+                "T_hat": float(T_hat[0]) if len(T_hat) == 1 else [float(T_hat.min()), float(T_hat.max())],
+                "e_s": float(out32[3][0]) if len(T_hat) == 1 else None})
     res = {
         "metric": METRIC,
         "value": updates / dt32,
@@ -215,12 +264,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "fp32",
-        "data": "synthetic (seeded Gaussian random field and random gap mask; no dataset)",
-        "config": {"workload": args.workload, "grid": [spec["n"], spec["n"]], "gap_fraction": p,
-                   "field": spec["field"], "corr_len": spec["corr_len"], "mask": spec["mask"], "chains": chains,
-                   "n_eq": spec["n_eq"], "n_samp": spec["n_samp"], "stride": spec["stride"],
-                   "sweeps_per_pass": prm32.sweeps_per_pass or 8, "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
-                   "T_hat": out32[3], "e_s": out32[4]},
+        "data": "synthetic (seeded Gaussian/lognormal random fields and gap masks; no dataset)",
+        "config": cfg,
         "realisations_per_s": records / dt32,
         "mae_fp32": mae32,
         "fp64_plain": fp64,
@@ -237,10 +282,10 @@ def main():
     }
     if not args.no_cpu:
         os.environ.setdefault("OMP_NUM_THREADS", "1")
-        v, dt = cpu_baseline(z, known, out32[3], spec, args.cpu_sweeps)
+        v, dt, used = cpu_baseline(W, T_hat, budget_s=args.cpu_seconds)
+        desc = ", ".join(f"{s} sweeps of {sh[0]}x{sh[1]}" for sh, s in used[:4]) + (" ..." if len(used) > 4 else "")
         res["cpu_baseline"] = {"value": v, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.cpu_sweeps} hybrid sweeps of the {spec['n']}x{spec['n']} workload "
-                                         f"(1 chain, {P} gap sites) from the hot start, FP64 NumPy oracle, "
+                               "sample": f"{desc} (1 chain each, from the hot start, a-rule on), FP64 NumPy oracle, "
                                          f"one thread, {dt:.1f} s on {platform.processor() or platform.machine()}"}
     print(json.dumps(res), flush=True)
 

@@ -194,6 +194,20 @@ mpr_status mpr_get_chain_state(mpr_ctx *ctx, int64_t *sweep_index, double *a);
 mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *a);
 
 /*
+ * Autotuner: choose the sweeps fused per pass (up to the context's
+ * sweeps_per_pass) and the sweep workgroup size by timing trial passes of
+ * at least trial_sweeps sweeps on the context's own grids at the host
+ * temperatures T[n_grids].  The angles, the sweep counter and every chain's
+ * a are restored exactly afterwards, so the call has no effect on results;
+ * neither choice changes results either (tiling and fusion are bitwise
+ * invariant).  Choices are cached per batch shape for the process, so a
+ * later context of the same shape reuses them without timing.  nsw_out,
+ * threads_out (nullable) receive the choice.  Uses the fill accumulators as
+ * scratch: do not call during a fill.  Synchronises the stream.
+ */
+mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out);
+
+/*
  * Kernel timing, for measurement.  With enable != 0 every later launch of
  * the sweep kernel is bracketed by two HIP events on the context's stream;
  * mpr_get_timing synchronises the stream and returns the summed

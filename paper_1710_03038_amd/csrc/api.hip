@@ -9,7 +9,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -58,7 +61,8 @@ struct mpr_ctx {
   int64_t sweep_index = 0;     // global sweep counter (keys the random stream)
   int64_t pass_no = 0;         // passes run so far: selects the counter and a buffers
   PassEnd pending{};           // the last pass, until its end has been applied
-  int nsw_max = 1;
+  int nsw_max = 1;             // the most sweeps per pass the plan supports
+  int nsw_run = 1;             // sweeps per pass used (autotuned, <= nsw_max)
   int threads = 256;           // workgroup size of the sweep kernel
   size_t lds_limit = 65536;
   std::vector<double> beta_h;  // staging for per-chain inverse temperatures
@@ -391,7 +395,7 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
   if (c->sweep_index + n >= 0xFFFFFFFFLL) return fail(c, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
   int64_t done = 0;
   while (done < n) {
-    int64_t len = std::min<int64_t>(c->nsw_max, n - done);
+    int64_t len = std::min<int64_t>(c->nsw_run, n - done);
     if (adapt) {
       const int64_t ae = c->p.adapt_every;
       len = std::min<int64_t>(len, ae - (c->sweep_index % ae));
@@ -529,6 +533,7 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
   c->plan = plan;
   bind(c->v, plan.v, workspace);
   c->nsw_max = plan.nsw_max;
+  c->nsw_run = plan.nsw_max;
   c->threads = p->dtype == MPR_FP64 ? 256 : 1024;
   if (const char *env = std::getenv("MPR_SWEEP_THREADS")) {
     const int t = std::atoi(env);
@@ -804,6 +809,116 @@ mpr_status mpr_set_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, const double *
     HIP_TRY(ctx, launch_set_phi<float>((float *)ctx->v.st[ctx->cur] + off, (float *)ctx->v.st[ctx->cur ^ 1] + off, n,
                                        phi, ctx->stream));
   }
+  return MPR_OK;
+}
+
+// Key of a batch shape for the autotuner's process-wide cache.
+static std::string tune_key(const mpr_ctx *c) {
+  std::string k = std::to_string(c->p.dtype) + ":" + std::to_string(c->plan.tile_x) + "x" +
+                  std::to_string(c->plan.tile_y) + ":" + std::to_string(c->nsw_max) + ":" +
+                  std::to_string(c->p.q == 1.0);
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the grid shapes and gap counts
+  for (const GridDesc &d : c->plan.gd)
+    for (int64_t v : {(int64_t)d.nx, (int64_t)d.ny, (int64_t)d.chains, d.n_gap}) {
+      h ^= (uint64_t)v;
+      h *= 1099511628211ull;
+    }
+  return k + ":" + std::to_string(c->n_grids) + ":" + std::to_string(h);
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+
+mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (trial_sweeps < 1) return fail(ctx, MPR_E_ARG, "trial_sweeps must be >= 1");
+  const std::string key = tune_key(ctx);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      ctx->nsw_run = it->second.first;
+      ctx->threads = it->second.second;
+      if (nsw_out) *nsw_out = ctx->nsw_run;
+      if (threads_out) *threads_out = ctx->threads;
+      return MPR_OK;
+    }
+  }
+  mpr_status st = set_beta(ctx, T);
+  if (st != MPR_OK) return st;
+  const int64_t C = ctx->plan.total_chains;
+  // Save the state, the sweep counter, the pass number and a; the fill
+  // accumulator `ref` serves as the copy of the angles.
+  const size_t bytes = ctx->plan.elem * (size_t)ctx->plan.state_elems;
+  std::vector<double> a_save(C);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->v.acc_ref, ctx->v.st[ctx->cur], bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(a_save.data(), a_buf(ctx, ctx->pass_no), 8 * C, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const int cur0 = ctx->cur;
+  const int64_t sweep0 = ctx->sweep_index, pass0 = ctx->pass_no;
+  const bool timing0 = ctx->timing;
+  ctx->timing = false;
+
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  double best = 1e300;
+  int best_nsw = ctx->nsw_run, best_thr = ctx->threads;
+  const int nsws[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  for (int thr : {256, 512, 1024}) {
+    const bool ok = (ctx->p.dtype == MPR_FP64 ? sweep_max_threads<double>(thr) : sweep_max_threads<float>(thr)) >= thr;
+    if (!ok) continue;
+    for (int nsw : nsws) {
+      if (nsw > ctx->nsw_max) break;
+      int w, h;
+      size_t lds;
+      lds_extent(ctx, nsw, w, h, lds);
+      if (lds > ctx->lds_limit) break;
+      ctx->threads = thr;
+      ctx->nsw_run = nsw;
+      const int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
+      st = run_sweeps(ctx, nsw, false, false, nullptr, 0);  // warm-up pass
+      if (st == MPR_OK) {
+        HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+        st = run_sweeps(ctx, n, false, false, nullptr, 0);
+        HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+      }
+      if (st != MPR_OK) break;
+      HIP_TRY(ctx, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+      const double per_sweep = ms / (double)n;
+      if (per_sweep < best) {
+        best = per_sweep;
+        best_nsw = nsw;
+        best_thr = thr;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // Restore everything the trial passes changed.
+  ctx->cur = cur0;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->v.st[ctx->cur], ctx->v.acc_ref, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->sweep_index = sweep0;
+  ctx->pass_no = pass0;
+  ctx->pending.valid = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(a_buf(ctx, ctx->pass_no), a_save.data(), 8 * C, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_zero_u32(ctx->v.counts, 3 * C * kMaxPass, ctx->stream));
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.energy, 3 * C * kMaxPass, 0.0, ctx->stream));
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->timing = timing0;
+  if (st != MPR_OK) return st;
+  ctx->nsw_run = best_nsw;
+  ctx->threads = best_thr;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best_nsw, best_thr};
+  }
+  if (nsw_out) *nsw_out = best_nsw;
+  if (threads_out) *threads_out = best_thr;
   return MPR_OK;
 }
 

@@ -91,6 +91,10 @@ template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds_bytes, hipStream_t s);
 template <typename P>
 hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s);
+// Largest workgroup the sweep kernel instance for `threads` can run with
+// (0 if it cannot be queried).
+template <typename P>
+int sweep_max_threads(int threads);
 template <typename P>
 hipError_t launch_plan(const GridDesc *g, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y,
                        int dmax, uint16_t *plan, uint32_t *plan_cum, hipStream_t s);

@@ -505,6 +505,20 @@ hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, siz
   return hipGetLastError();
 }
 
+template <typename P> int sweep_max_threads(int threads) {
+  hipFuncAttributes at{};
+  hipError_t e = hipErrorInvalidValue;
+  switch (threads) {
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024>)); break;
+    default: break;
+  }
+  return e == hipSuccess ? at.maxThreadsPerBlock : 0;
+}
+template int sweep_max_threads<float>(int);
+template int sweep_max_threads<double>(int);
+
 template <typename P> hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s) {
   hipLaunchKernelGGL(k_pass_end<P>, dim3((a.total_chains + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -76,6 +76,7 @@ def lib():
         L.mpr_set_phi.argtypes = [vp, i32, i32, vp]
         L.mpr_get_chain_state.argtypes = [vp, ctypes.POINTER(i64), dp]
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
+        L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_set_timing.argtypes = [vp, i32]
         L.mpr_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.mpr_destroy.argtypes = [vp]
@@ -84,7 +85,7 @@ def lib():
         L.mpr_last_error.restype = ctypes.c_char_p
         for name in ("mpr_init_field", "mpr_sweep", "mpr_specific_energy", "mpr_match_T", "mpr_fill",
                      "mpr_get_phi", "mpr_set_phi", "mpr_get_chain_state", "mpr_set_chain_state",
-                     "mpr_set_timing", "mpr_get_timing"):
+                     "mpr_set_timing", "mpr_get_timing", "mpr_autotune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -271,6 +272,14 @@ class Field:
             raise ValueError("phi shape mismatch")
         _check(lib().mpr_set_phi(self.ctx, grid, chain, ctypes.c_void_p(t.data_ptr())), self.ctx)
         self.stream.synchronize()
+
+    def autotune(self, T, trial_sweeps=16):
+        """mpr_autotune: returns (sweeps per pass, workgroup size) chosen."""
+        T = self._T(T)
+        nsw = ctypes.c_int32(0)
+        thr = ctypes.c_int32(0)
+        _check(lib().mpr_autotune(self.ctx, _dptr(T), trial_sweeps, ctypes.byref(nsw), ctypes.byref(thr)), self.ctx)
+        return nsw.value, thr.value
 
     def set_timing(self, enable=True):
         _check(lib().mpr_set_timing(self.ctx, 1 if enable else 0), self.ctx)

@@ -322,3 +322,25 @@ def test_error_paths_on_device():
     with pytest.raises(M.MPRError) as ei:
         f.sweep(1, [-1.0])
     assert ei.value.status == M.MPR_E_ARG
+
+
+def test_autotune_leaves_state_and_results_unchanged():
+    grids = _grids(71)
+    T = [0.01, 0.05, 0.2, 1.0, 0.003]
+    f1 = make_field(grids, dtype="fp32", seed=12)
+    f2 = make_field(grids, dtype="fp32", seed=12)
+    f1.sweep(3, T, adapt=True)
+    f2.sweep(3, T, adapt=True)
+    before = [f2.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
+    idx, a = f2.chain_state()
+    nsw, thr = f2.autotune(T, 8)
+    assert 1 <= nsw <= 8 and thr in (256, 512, 1024)
+    idx2, a2 = f2.chain_state()
+    assert idx2 == idx and np.array_equal(a2, a)
+    after = [f2.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    f1.sweep(10, T, adapt=True)
+    f2.sweep(10, T, adapt=True)
+    for g, gr in enumerate(grids):
+        for c in range(gr[2]):
+            assert np.array_equal(f1.get_phi(g, c).cpu().numpy(), f2.get_phi(g, c).cpu().numpy())
