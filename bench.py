@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # two-wide FMA, 4 flops, per lane-instruction).
 VALU_PEAK_TINST = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU lane-instructions of one FP32 gap-site update in the compiled sweep
-# kernel (the update loop of k_sweep<float>: 211 VALU instructions, of
-# which 21 v_mad_u64_u32 for Philox and 6 transcendental).
-VALU_INST_PER_UPDATE = 211
+# kernel (the update loop of k_sweep<float> for q = 1/2: 177 VALU
+# instructions, of which 21 v_mad_u64_u32 for Philox and 5 transcendental).
+VALU_INST_PER_UPDATE = 177
 KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
                   "paper_1710_03038_amd/csrc/internal.h")
 PROFILE = "profiles/k_sweep_fp32_grid1024.md"

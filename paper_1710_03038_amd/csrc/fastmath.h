@@ -54,6 +54,23 @@ __device__ __forceinline__ void sincos(float x, float *s, float *c) {
   *c = cv;
 }
 
+// sin and cos of x in [0, pi] (q*phi with q <= 1/2): r = x - pi/2 in
+// [-pi/2, pi/2], sin x = cos r and cos x = -sin r, with the Taylor
+// polynomials of sin r to r^13 and cos r to r^12 (truncation below 1e-8).
+__device__ __forceinline__ void sincos_0pi(float x, float *s, float *c) {
+  float r = x - kPio2Hi;
+  r = r - kPio2Lo;
+  const float r2 = r * r;
+  float ps = fmaf(fmaf(fmaf(-1.60590438e-10f, r2, 2.50521084e-08f), r2, -2.75573192e-06f), r2, 1.98412698e-04f);
+  ps = fmaf(fmaf(ps, r2, -8.33333333e-03f), r2, 1.66666667e-01f);
+  const float sr = fmaf(-r * r2, ps, r);  // sin r = r - r^3/6 + ...
+  float pc = fmaf(fmaf(fmaf(2.08767570e-09f, r2, -2.75573192e-07f), r2, 2.48015873e-05f), r2, -1.38888889e-03f);
+  pc = fmaf(fmaf(pc, r2, 4.16666667e-02f), r2, -0.5f);
+  const float cr = fmaf(pc, r2, 1.0f);
+  *s = cr;
+  *c = -sr;
+}
+
 __device__ __forceinline__ float sin(float x) {
   int q;
   const float r = reduce(x, q);

@@ -75,6 +75,7 @@ template <> struct Prec<float> {
   __device__ static float sin_(float x) { return fm::sin(x); }
   __device__ static float sin_dh_(float x) { return fm::sin_hw(x); }
   __device__ static void sincos_(float x, float *s, float *c) { fm::sincos(x, s, c); }
+  __device__ static void sincos_0pi_(float x, float *s, float *c) { fm::sincos_0pi(x, s, c); }
   __device__ static float atan2_(float y, float x) { return fm::atan2(y, x); }
   __device__ static float exp_(float x) { return fm::exp(x); }
   __device__ static float sqrt_(float x) { return fm::sqrt(x); }
@@ -88,6 +89,7 @@ template <> struct Prec<double> {
   __device__ static double sin_(double x) { return ::sin(x); }
   __device__ static double sin_dh_(double x) { return ::sin(x); }
   __device__ static void sincos_(double x, double *s, double *c) { ::sincos(x, s, c); }
+  __device__ static void sincos_0pi_(double x, double *s, double *c) { ::sincos(x, s, c); }
   __device__ static double atan2_(double y, double x) { return ::atan2(y, x); }
   __device__ static double exp_(double x) { return ::exp(x); }
   __device__ static double sqrt_(double x) { return ::sqrt(x); }
@@ -201,7 +203,7 @@ __device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int c
 // the interior; the halo of 2*nsw + 1 sites keeps every neighbour read by
 // those sites exact, and after each full sweep the interior plus one ring
 // is exact, which the energy of interior pairs needs.
-template <typename P, int NT>
+template <typename P, int NT, bool QONE>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   using V2 = typename Prec<P>::V2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -244,7 +246,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       if (gx >= lxs && gx < lxe && gy >= lys && gy < lye) {
         v = src[(int64_t)gy * nx + gx];
         P s_, c_;
-        Prec<P>::sincos_(q * fabs(v), &s_, &c_);
+        if (QONE) Prec<P>::sincos_(q * fabs(v), &s_, &c_);
+        else Prec<P>::sincos_0pi_(q * fabs(v), &s_, &c_);
         c = {c_, s_};
       }
       ph[o] = v;
@@ -280,7 +283,11 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
   const int iw = ix1 - x0, ih = iy1 - y0;
   const float inv_iw = 1.0f / (float)iw;
-  const uint32_t npair = (uint32_t)G.npair;
+  const int npair = G.npair;
+  // A plan entry e gives LDS row ly = (e >> 8) + Ly and column lx = (e & 255)
+  // + Lx; the Philox pair of that site is pbase + ly * npair + (lx >> 1).
+  const int Ly = y0 - oy - kPlanOffset, Lx = x0 - ox - kPlanOffset;
+  const int pbase = oy * npair + (ox >> 1);
 
   for (int s = 0; s < A.nsw; ++s) {
     const uint32_t sweep = A.sweep0 + (uint32_t)s;
@@ -295,21 +302,19 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       const V2 *cn = cs + (c ^ 1) * plane;
       for (uint32_t f = threadIdx.x; f < n; f += NT) {
         const uint32_t e = lc[f];
-        const int gx = x0 + (int)(e & 255u) - kPlanOffset, gy = y0 + (int)(e >> 8) - kPlanOffset;
-        const int lx = gx - ox, ly = gy - oy;
-        const int j = lx >> 1;
+        const int ly = (int)(e >> 8) + Ly, lx = (int)(e & 255u) + Lx;
+        const int j = lx >> 1, par = lx & 1;  // par = parity of the site's x
         const int o = ly * P2 + j;
         const P phi = pc[o];
-        const int jl = (gx & 1) ? j : j - 1, jr = (gx & 1) ? j + 1 : j;
-        const V2 nl = cn[ly * P2 + jl], nr = cn[ly * P2 + jr];
+        const V2 nl = cn[o - 1 + par], nr = cn[o + par];
         const V2 nu = cn[o - P2], nd = cn[o + P2];
         const P hx = nl.x + nr.x + nu.x + nd.x;
         const P hy = nl.y + nr.y + nu.y + nd.y;
 
         uint32_t w[4];
-        philox4x32_10((uint32_t)gy * npair + (uint32_t)(gx >> 1), sweep, cid, gid, k0, k1, w);
-        const P u = unit<P>((gx & 1) ? w[2] : w[0]);
-        const P rr = unit<P>((gx & 1) ? w[3] : w[1]);
+        philox4x32_10((uint32_t)(pbase + ly * npair + j), sweep, cid, gid, k0, k1, w);
+        const P u = unit<P>(par ? w[2] : w[0]);
+        const P rr = unit<P>(par ? w[3] : w[1]);
 
         // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
         const P h2 = hx * hx + hy * hy;
@@ -318,7 +323,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         P p1 = phi;
         if (live) {
           const P star = (P(2) * psi - q * phi) * inv_q;
-          if (A.q_is_one) p1 = wrap_any(star);
+          if (QONE) p1 = wrap_any(star);
           else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
         }
         // Steps 2-3: restricted Metropolis proposal.
@@ -333,7 +338,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         const P nv = ok ? p2 : p1;
         pc[o] = nv;
         P s_, c_;
-        Prec<P>::sincos_(q * nv, &s_, &c_);
+        if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
+        else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
         cc[o] = {c_, s_};
         if (ok && f < n_inner) ++acc;
       }
@@ -494,14 +500,20 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
   apply_pass_end(A, A.grids[lo], ch, true);
 }
 
+template <typename P, bool QONE>
+static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
+  switch (threads) {
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256, QONE>), dim3((unsigned)n_items), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512, QONE>), dim3((unsigned)n_items), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<P, 1024, QONE>), dim3((unsigned)n_items), dim3(1024), lds, s, a); break;
+  }
+}
+
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  switch (threads) {
-    case 256: hipLaunchKernelGGL((k_sweep<P, 256>), dim3((unsigned)n_items), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_sweep<P, 512>), dim3((unsigned)n_items), dim3(512), lds, s, a); break;
-    case 1024: hipLaunchKernelGGL((k_sweep<P, 1024>), dim3((unsigned)n_items), dim3(1024), lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+  if (a.q_is_one) launch_sweep_q<P, true>(a, threads, n_items, lds, s);
+  else launch_sweep_q<P, false>(a, threads, n_items, lds, s);
   return hipGetLastError();
 }
 
@@ -509,9 +521,9 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
-    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256>)); break;
-    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512>)); break;
-    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024>)); break;
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, false>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, false>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, false>)); break;
     default: break;
   }
   return e == hipSuccess ? at.maxThreadsPerBlock : 0;
