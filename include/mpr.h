@@ -208,12 +208,14 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
 mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out);
 
 /*
- * Kernel timing, for measurement.  With enable != 0 every later launch of
- * the sweep kernel is bracketed by two HIP events on the context's stream;
- * mpr_get_timing synchronises the stream and returns the summed
- * milliseconds between those event pairs, the number of launches and the
- * site-sweeps they processed (lattice sites times sweeps, summed over
- * chains), then resets the sums.  enable == 0 stops recording.
+ * Kernel timing, for measurement.  With enable != 0 every later run of
+ * back-to-back sweep-kernel launches (one mpr_sweep call, or one phase of
+ * mpr_fill) is bracketed by two HIP events on the context's stream, with no
+ * other kernel inside the bracket; mpr_get_timing synchronises the stream
+ * and returns the summed milliseconds between those event pairs, the number
+ * of sweep launches and the site-sweeps they processed (lattice sites times
+ * sweeps, summed over chains), then resets the sums.  The bracket includes
+ * the short queue gaps between launches.  enable == 0 stops recording.
  */
 mpr_status mpr_set_timing(mpr_ctx *ctx, int32_t enable);
 mpr_status mpr_get_timing(mpr_ctx *ctx, double *sweep_ms, int64_t *launches, int64_t *site_sweeps);

@@ -324,25 +324,8 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.plan = c->v.plan;
   A.plan_cum = c->v.plan_cum;
   A.plan_dmax = c->plan.dmax;
-  if (c->timing) {
-    if (c->ev_used + 2 > c->ev.size()) {
-      if (c->ev.size() < 8192) {
-        for (int i = 0; i < 256; ++i) {
-          hipEvent_t e;
-          HIP_TRY(c, hipEventCreate(&e));
-          c->ev.push_back(e);
-        }
-      } else {
-        const mpr_status st = drain_timing(c);
-        if (st != MPR_OK) return st;
-      }
-    }
-    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-  }
   HIP_TRY(c, launch_sweep<P>(A, c->threads, c->plan.n_items, lds, c->stream));
   if (c->timing) {
-    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
-    c->ev_used += 2;
     c->t_launches += 1;
     c->t_site_sweeps += (int64_t)nsw * c->sites_all_chains;
   }
@@ -393,6 +376,23 @@ mpr_status close_pending(mpr_ctx *c) {
 // rec_stride > 0 records every rec_stride-th sweep of this run.
 mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *trace, int rec_stride) {
   if (c->sweep_index + n >= 0xFFFFFFFFLL) return fail(c, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
+  // Timing brackets the whole run of back-to-back sweep launches with one
+  // event pair: per-launch events would stall the queue between launches.
+  if (c->timing && n > 0) {
+    if (c->ev_used + 2 > c->ev.size()) {
+      if (c->ev.size() < 64) {
+        for (int i = 0; i < 2; ++i) {
+          hipEvent_t e;
+          HIP_TRY(c, hipEventCreate(&e));
+          c->ev.push_back(e);
+        }
+      } else {
+        const mpr_status st = drain_timing(c);
+        if (st != MPR_OK) return st;
+      }
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+  }
   int64_t done = 0;
   while (done < n) {
     int64_t len = std::min<int64_t>(c->nsw_run, n - done);
@@ -414,6 +414,10 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
                               : run_pass<float>(c, (int)len, adapt, trace_e, trace, done, rec, first);
     if (st != MPR_OK) return st;
     done += len;
+  }
+  if (c->timing && n > 0) {
+    HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+    c->ev_used += 2;
   }
   return close_pending(c);
 }

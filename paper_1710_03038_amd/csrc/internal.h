@@ -73,7 +73,7 @@ struct SweepArgs {
   P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
   // Gap-site plan (k_plan): per tile, the gap sites within ring distance
   // plan_dmax of the interior, colour 0 then colour 1, each sorted by ring
-  // (ring = Chebyshev distance from the interior rectangle); entry =
+  // (ring = Manhattan distance from the interior rectangle); entry =
   // ((y - y0 + 32) << 8) | (x - x0 + 32).  plan_cum[tile][c][r] = number of
   // colour-c entries with ring < r, r = 0 .. plan_dmax + 1.
   const uint16_t *plan;

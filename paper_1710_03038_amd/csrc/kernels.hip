@@ -198,11 +198,14 @@ __device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int c
 }
 
 // ---------------------------------------------------------------- sweep
-// One workgroup = one (grid, chain, tile) item.  Half-sweep hs of the pass
-// updates the colour-(hs & 1) gap sites within distance D = 2*nsw - hs of
-// the interior; the halo of 2*nsw + 1 sites keeps every neighbour read by
-// those sites exact, and after each full sweep the interior plus one ring
-// is exact, which the energy of interior pairs needs.
+// One workgroup = one (grid, chain, tile) item.  Distances from the
+// interior are Manhattan distances (dx + dy outside the tile), the reach of
+// nearest-neighbour dependencies.  Half-sweep hs of the pass updates the
+// colour-(hs & 1) gap sites within distance D = 2*nsw - 1 - hs: each reads
+// neighbours within D + 1, exact after half-sweep hs - 1 (the staged halo of
+// 2*nsw + 1 sites covers hs = 0), so the interior is exact after the last
+// half-sweep.  When the energy of interior pairs is traced, every D is one
+// larger, so that the interior plus one ring is exact after each sweep.
 template <typename P, int NT, bool QONE>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   using V2 = typename Prec<P>::V2;
@@ -258,7 +261,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 
   if (threadIdx.x < kMaxPass) acc_lds[threadIdx.x] = 0u;
   // Stage this pass's part of the tile's gap-site plan: colour-0 entries
-  // within ring 2*nsw, then colour-1 entries within ring 2*nsw - 1.
+  // within distance 2*nsw, then colour-1 entries within distance 2*nsw - 1.
   uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);
   const int64_t pitem = G.plan_begin + t;
   const uint32_t *cum = A.plan_cum + pitem * 2 * (A.plan_dmax + 2);
@@ -293,7 +296,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
     const uint32_t sweep = A.sweep0 + (uint32_t)s;
     uint32_t acc = 0;
     for (int c = 0; c < 2; ++c) {
-      const int D = 2 * A.nsw - (2 * s + c);
+      const int D = 2 * A.nsw - (2 * s + c) - (A.energy ? 0 : 1);
       const uint32_t n = cum[c * cstride + D + 1];      // entries within ring D
       const uint32_t n_inner = cum[c * cstride + 1];    // ring 0: the interior
       const uint16_t *lc = list + (c ? na : 0);
@@ -415,9 +418,9 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 }
 
 // ------------------------------------------------------------------- plan
-// One workgroup per (grid, tile): list the tile's gap sites within ring
-// distance dmax of its interior, colour 0 first, each colour sorted by ring
-// (a counting sort).  The order inside one ring follows the LDS atomics and
+// One workgroup per (grid, tile): list the tile's gap sites within
+// Manhattan distance dmax of its interior, colour 0 first, each colour
+// sorted by distance (a counting sort).  The order inside one ring follows the LDS atomics and
 // may vary between runs; the sweep's results do not depend on it.
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
@@ -444,7 +447,8 @@ __global__ void __launch_bounds__(kThreads)
     split_index(f, rw, inv, r, cx);
     const int gx = rx0 + cx, gy = ry0 + r;
     if (signbit(st[(int64_t)gy * nx + gx])) continue;
-    const int ring = max(max(max(x0 - gx, gx - (ix1 - 1)), max(y0 - gy, gy - (iy1 - 1))), 0);
+    const int ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
+    if (ring > dmax) continue;  // the corners of the scanned square
     atomicAdd(&cnt[(gx + gy) & 1][ring], 1u);
   }
   __syncthreads();
@@ -468,7 +472,8 @@ __global__ void __launch_bounds__(kThreads)
     split_index(f, rw, inv, r, cx);
     const int gx = rx0 + cx, gy = ry0 + r;
     if (signbit(st[(int64_t)gy * nx + gx])) continue;
-    const int ring = max(max(max(x0 - gx, gx - (ix1 - 1)), max(y0 - gy, gy - (iy1 - 1))), 0);
+    const int ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
+    if (ring > dmax) continue;
     const uint32_t pos = atomicAdd(&cur[(gx + gy) & 1][ring], 1u);
     out[pos] = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (gx - x0 + kPlanOffset));
   }
