@@ -34,14 +34,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spin-updates/sec + realisations/sec, batched FP32 vs plain FP64, equal MAE"
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-
-# instructions per second (the published 157.3 TFLOP/s FP32 counts a packed
-# two-wide FMA, 4 flops, per lane-instruction).
-VALU_PEAK_TINST = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU lane-instructions of one FP32 gap-site update in the compiled sweep
-# kernel (the update loop of k_sweep<float> for q = 1/2: 177 VALU
-# instructions, of which 21 v_mad_u64_u32 for Philox and 5 transcendental).
-VALU_INST_PER_UPDATE = 177
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz lane-
+# instructions per second.  A SIMD issues a plain wave64 FP32 or INT32
+# instruction (v_mad_u64_u32 included) every 2 cycles and a transcendental
+# (v_sin, v_exp, v_sqrt, v_rcp) every 8, measured on gfx950 with throughput
+# probes; the published 157.3 TFLOP/s FP32 is this peak times 2 flops per FMA.
+VALU_PEAK_TINST = 256 * 4 * 32 * 2.4e9 / 1e12
+# Issue slots (2-cycle units) of one FP32 gap-site update in the compiled
+# sweep kernel: the update loop of k_sweep<float> for q = 1/2 has 177 VALU
+# instructions, of which 21 v_mad_u64_u32 for Philox and 5 transcendentals
+# at 4 slots each: 172 + 5 * 4 = 192.
+VALU_INST_PER_UPDATE = 192
 KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
                   "paper_1710_03038_amd/csrc/internal.h")
 PROFILE = "profiles/k_sweep_fp32_grid1024.md"
@@ -270,7 +273,7 @@ def main():
         "mae_fp32": mae32,
         "fp64_plain": fp64,
         "roofline": {"bound": "alu", "kernel": "k_sweep<float>",
-                     "achieved": achieved, "peak": VALU_PEAK_TINST, "unit": "Tinst/s (VALU lane-instructions)",
+                     "achieved": achieved, "peak": VALU_PEAK_TINST, "unit": "T VALU issue slots/s (lane-instructions, transcendentals x4)",
                      "frac": (achieved / VALU_PEAK_TINST) if achieved else None,
                      "traffic": profiled_traffic() if default_config else None,
                      "inst_per_update": VALU_INST_PER_UPDATE,

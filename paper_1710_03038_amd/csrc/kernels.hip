@@ -198,6 +198,78 @@ __device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int c
 }
 
 // ---------------------------------------------------------------- sweep
+// What one colour phase of the sweep kernel needs to update a site.
+template <typename P> struct UpdateCtx {
+  using V2 = typename Prec<P>::V2;
+  const uint16_t *lc;  // this colour's staged plan entries
+  P *pc;               // this colour's angle plane
+  V2 *cc;              // this colour's (cos, sin) plane
+  const V2 *cn;        // the other colour's (cos, sin) plane
+  int Ly, Lx, P2, pbase, npair;
+  uint32_t sweep, cid, gid, k0, k1;
+  P q, inv_q, alpha, beta;
+};
+
+// Algorithm 1 for the K plan entries fs[] of one thread, interleaved step
+// by step; returns the accepted updates among those with cnt[] set.
+template <typename P, bool QONE, int K>
+__device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
+                                                 const bool (&cnt)[K]) {
+  using V2 = typename Prec<P>::V2;
+  const P q = U.q;
+  int o[K];
+  P phi[K], hx[K], hy[K], u[K], rr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // A plan entry e gives LDS row (e >> 8) + Ly and column (e & 255) + Lx.
+    const uint32_t e = U.lc[fs[k]];
+    const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
+    const int j = lx >> 1, par = lx & 1;  // par = parity of the site's x
+    o[k] = ly * U.P2 + j;
+    phi[k] = U.pc[o[k]];
+    const V2 nl = U.cn[o[k] - 1 + par], nr = U.cn[o[k] + par];
+    const V2 nu = U.cn[o[k] - U.P2], nd = U.cn[o[k] + U.P2];
+    hx[k] = nl.x + nr.x + nu.x + nd.x;
+    hy[k] = nl.y + nr.y + nu.y + nd.y;
+    // Philox pair of the site: its LDS pair index offset by the tile origin.
+    uint32_t w[4];
+    philox4x32_10((uint32_t)(U.pbase + ly * U.npair + j), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
+    u[k] = unit<P>(par ? w[2] : w[0]);
+    rr[k] = unit<P>(par ? w[3] : w[1]);
+  }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
+    const P h2 = hx[k] * hx[k] + hy[k] * hy[k];
+    const bool live = h2 > Prec<P>::tiny_h2;
+    const P psi = live ? Prec<P>::atan2_(hy[k], hx[k]) : P(0);
+    P p1 = phi[k];
+    if (live) {
+      const P star = (P(2) * psi - q * phi[k]) * U.inv_q;
+      if (QONE) p1 = wrap_any(star);
+      else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+    }
+    // Steps 2-3: restricted Metropolis proposal.
+    const P p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
+    // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
+    //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
+    P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_dh_(q * (p2 + p1) * P(0.5) - psi) *
+           Prec<P>::sin_dh_(q * (p2 - p1) * P(0.5));
+    dH = live ? dH : P(0);
+    // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
+    const bool ok = (dH <= P(0)) || (rr[k] < Prec<P>::exp_(-U.beta * dH));
+    const P nv = ok ? p2 : p1;
+    P s_, c_;
+    if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
+    else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
+    U.pc[o[k]] = nv;
+    U.cc[o[k]] = V2{c_, s_};
+    acc += (ok && cnt[k]) ? 1u : 0u;
+  }
+  return acc;
+}
+
 // One workgroup = one (grid, chain, tile) item.  Distances from the
 // interior are Manhattan distances (dx + dy outside the tile), the reach of
 // nearest-neighbour dependencies.  Half-sweep hs of the pass updates the
@@ -236,42 +308,72 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
   const P *src = A.src + cbase;
 
-  // Stage the tile, its halo and a frozen zero ring around them.
-  {
-    const float invw = 1.0f / (float)W;
-    for (int idx = threadIdx.x; idx < W * A.lds_h; idx += NT) {
-      int ly, lx;
-      split_index(idx, W, invw, ly, lx);
-      const int gx = ox + lx, gy = oy + ly;
-      const int o = ((gx + gy) & 1) * plane + ly * P2 + (lx >> 1);
-      P v = -P(0);
-      V2 c = {P(0), P(0)};
-      if (gx >= lxs && gx < lxe && gy >= lys && gy < lye) {
-        v = src[(int64_t)gy * nx + gx];
-        P s_, c_;
-        if (QONE) Prec<P>::sincos_(q * fabs(v), &s_, &c_);
-        else Prec<P>::sincos_0pi_(q * fabs(v), &s_, &c_);
-        c = {c_, s_};
-      }
-      ph[o] = v;
-      cs[o] = c;
-    }
-  }
-  __syncthreads();
-
+  // Stage the tile, its halo and a frozen zero ring around them, and this
+  // pass's part of the tile's gap-site plan: colour-0 entries within
+  // distance 2*nsw, then colour-1 entries within distance 2*nsw - 1.  Each
+  // thread issues the loads of up to kStage sites and kPlanStage plan
+  // entries before it waits for any, so the staging costs one memory
+  // latency per batch (one batch for the library's default shapes).  Sites
+  // outside the grid and lanes past the end read element 0 and discard it.
   if (threadIdx.x < kMaxPass) acc_lds[threadIdx.x] = 0u;
-  // Stage this pass's part of the tile's gap-site plan: colour-0 entries
-  // within distance 2*nsw, then colour-1 entries within distance 2*nsw - 1.
-  uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);
+  uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);  // past both planes
   const int64_t pitem = G.plan_begin + t;
   const uint32_t *cum = A.plan_cum + pitem * 2 * (A.plan_dmax + 2);
   const int cstride = A.plan_dmax + 2;
   const uint32_t n0_all = cum[A.plan_dmax + 1];
   const uint32_t na = cum[2 * A.nsw + 1], nb = cum[cstride + 2 * A.nsw];
   {
+    constexpr int kStage = 16, kPlanStage = 8;
+    const int n_lds = W * A.lds_h;
+    const float invw = 1.0f / (float)W;
     const uint16_t *pl = A.plan + G.plan_ebase + (int64_t)t * G.plan_cap;
-    for (uint32_t f = threadIdx.x; f < na; f += NT) list[f] = pl[f];
-    for (uint32_t f = threadIdx.x; f < nb; f += NT) list[na + f] = pl[n0_all + f];
+    const uint32_t n_all = na + nb;
+    for (int base = 0, pb = 0; base < n_lds || pb < (int)n_all; base += NT * kStage, pb += NT * kPlanStage) {
+      // Slots wholly past the end (a workgroup-uniform test) issue nothing.
+      uint16_t e[kPlanStage] = {};
+#pragma unroll
+      for (int k = 0; k < kPlanStage; ++k) {
+        if (pb + k * NT >= (int)n_all) break;
+        const uint32_t f = (uint32_t)(pb + k * NT) + threadIdx.x;
+        e[k] = pl[f < na ? f : (f < n_all ? n0_all + (f - na) : 0u)];
+      }
+      P v[kStage] = {};
+      int o[kStage];
+      bool in[kStage];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        o[k] = -1;
+        in[k] = false;
+      }
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        if (base + k * NT >= n_lds) break;
+        const int idx = base + k * NT + (int)threadIdx.x;
+        int ly, lx;
+        split_index(idx, W, invw, ly, lx);
+        const int gx = ox + lx, gy = oy + ly;
+        o[k] = idx < n_lds ? ((gx + gy) & 1) * plane + ly * P2 + (lx >> 1) : -1;
+        in[k] = idx < n_lds && gx >= lxs && gx < lxe && gy >= lys && gy < lye;
+        v[k] = src[in[k] ? (int64_t)gy * nx + gx : 0];
+      }
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        if (o[k] < 0) continue;
+        P s_ = P(0), c_ = P(0), val = -P(0);
+        if (in[k]) {
+          val = v[k];
+          if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
+          else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+        }
+        ph[o[k]] = val;
+        cs[o[k]] = V2{c_, s_};
+      }
+#pragma unroll
+      for (int k = 0; k < kPlanStage; ++k) {
+        const uint32_t f = (uint32_t)(pb + k * NT) + threadIdx.x;
+        if (f < n_all) list[f] = e[k];
+      }
+    }
   }
   __syncthreads();
 
@@ -287,8 +389,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int iw = ix1 - x0, ih = iy1 - y0;
   const float inv_iw = 1.0f / (float)iw;
   const int npair = G.npair;
-  // A plan entry e gives LDS row ly = (e >> 8) + Ly and column lx = (e & 255)
-  // + Lx; the Philox pair of that site is pbase + ly * npair + (lx >> 1).
+  // Plan entries are decoded relative to these LDS offsets; the Philox pair
+  // of LDS site (ly, lx) is pbase + ly * npair + (lx >> 1).
   const int Ly = y0 - oy - kPlanOffset, Lx = x0 - ox - kPlanOffset;
   const int pbase = oy * npair + (ox >> 1);
 
@@ -303,48 +405,24 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       P *pc = ph + c * plane;
       V2 *cc = cs + c * plane;
       const V2 *cn = cs + (c ^ 1) * plane;
-      for (uint32_t f = threadIdx.x; f < n; f += NT) {
-        const uint32_t e = lc[f];
-        const int ly = (int)(e >> 8) + Ly, lx = (int)(e & 255u) + Lx;
-        const int j = lx >> 1, par = lx & 1;  // par = parity of the site's x
-        const int o = ly * P2 + j;
-        const P phi = pc[o];
-        const V2 nl = cn[o - 1 + par], nr = cn[o + par];
-        const V2 nu = cn[o - P2], nd = cn[o + P2];
-        const P hx = nl.x + nr.x + nu.x + nd.x;
-        const P hy = nl.y + nr.y + nu.y + nd.y;
-
-        uint32_t w[4];
-        philox4x32_10((uint32_t)(pbase + ly * npair + j), sweep, cid, gid, k0, k1, w);
-        const P u = unit<P>(par ? w[2] : w[0]);
-        const P rr = unit<P>(par ? w[3] : w[1]);
-
-        // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
-        const P h2 = hx * hx + hy * hy;
-        const bool live = h2 > Prec<P>::tiny_h2;
-        const P psi = live ? Prec<P>::atan2_(hy, hx) : P(0);
-        P p1 = phi;
-        if (live) {
-          const P star = (P(2) * psi - q * phi) * inv_q;
-          if (QONE) p1 = wrap_any(star);
-          else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+      const UpdateCtx<P> U{lc, pc, cc, cn, Ly, Lx, P2, pbase, npair, sweep, cid, gid, k0, k1, q, inv_q, alpha, beta};
+      // In FP32, two independent updates per thread and iteration (items f
+      // and f + NT) give the scheduler two dependency chains to interleave;
+      // a lane without a second item repeats its first, whose identical
+      // write is harmless, and counts it once.  FP64 keeps one per iteration
+      // (its registers would cost occupancy).
+      constexpr uint32_t kIlp = sizeof(P) == 4 ? 2 : 1;
+      for (uint32_t f = threadIdx.x; f < n; f += kIlp * NT) {
+        const uint32_t f2 = f + NT;
+        if (kIlp == 2 && __any(f2 < n)) {
+          const uint32_t fs[2] = {f, f2 < n ? f2 : f};
+          const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
+          acc += update_sites<P, QONE, 2>(U, fs, cnt);
+        } else {
+          const uint32_t fs[1] = {f};
+          const bool cnt[1] = {f < n_inner};
+          acc += update_sites<P, QONE, 1>(U, fs, cnt);
         }
-        // Steps 2-3: restricted Metropolis proposal.
-        const P p2 = wrap_step(p1 + alpha * (u - P(0.5)));
-        // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
-        //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
-        P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_dh_(q * (p2 + p1) * P(0.5) - psi) *
-               Prec<P>::sin_dh_(q * (p2 - p1) * P(0.5));
-        dH = live ? dH : P(0);
-        // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
-        const bool ok = (dH <= P(0)) || (rr < Prec<P>::exp_(-beta * dH));
-        const P nv = ok ? p2 : p1;
-        pc[o] = nv;
-        P s_, c_;
-        if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
-        else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
-        cc[o] = {c_, s_};
-        if (ok && f < n_inner) ++acc;
       }
       __syncthreads();
     }
