@@ -175,6 +175,30 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
                     double *zstd, mpr_fill_report *rep);
 
 /*
+ * Set the context up again from the caller's z and known buffers given to
+ * mpr_init_field (same shapes; the values and the gap pattern may have
+ * changed): Eq. (2) bounds, the hot start of Algorithm 2, steps 1.8 and
+ * 2.1, a = 1 (step 1.10), sweep counter 0 -- the state of a fresh context,
+ * without its host set-up.  Keeps the tuned launch shape and the fill
+ * graph.  Synchronises the stream.  Errors: MPR_E_ARG (non-finite z at a
+ * sample site), MPR_E_DEGENERATE (z_max == z_min); the context is then
+ * unusable until a successful mpr_reinit.
+ */
+mpr_status mpr_reinit(mpr_ctx *ctx);
+
+/*
+ * Fill graph (enable != 0; off by default): mpr_fill records its device
+ * work from the equilibration sweeps to the last sampling pass into a
+ * hipGraph and replays it when called again from the same sweep counter,
+ * pass parity, launch shape and sweep counts -- e.g. after mpr_reinit --
+ * recording afresh otherwise.  Results are bitwise those of the plain
+ * path.  The temperatures, the a-rule state and the accumulators live in
+ * device memory, so a replay reads the current ones.  enable == 0 drops the
+ * graph.
+ */
+mpr_status mpr_set_graph(mpr_ctx *ctx, int32_t enable);
+
+/*
  * Copy the angles of one chain out (mpr_get_phi) or in (mpr_set_phi), as
  * ny*nx device doubles in natural row-major order.  mpr_set_phi writes gap
  * sites only (sample sites keep their Eq. (2) values); gap values must lie
@@ -215,7 +239,9 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
  * and returns the summed milliseconds between those event pairs, the number
  * of sweep launches and the site-sweeps they processed (lattice sites times
  * sweeps, summed over chains), then resets the sums.  The bracket includes
- * the short queue gaps between launches.  enable == 0 stops recording.
+ * the short queue gaps between launches; with the fill graph on, it spans
+ * the whole graph, whose few clearing and copy kernels are then inside it.
+ * enable == 0 stops recording.
  */
 mpr_status mpr_set_timing(mpr_ctx *ctx, int32_t enable);
 mpr_status mpr_get_timing(mpr_ctx *ctx, double *sweep_ms, int64_t *launches, int64_t *site_sweeps);

@@ -34,6 +34,7 @@ struct Views {
   uint32_t *counts = nullptr;
   double *energy = nullptr;
   double *part = nullptr, *out = nullptr;
+  double *rep = nullptr;  // fill report scratch: a and acceptance after equilibration [2][C]
   uint16_t *plan = nullptr;
   uint32_t *plan_cum = nullptr;
 };
@@ -74,7 +75,34 @@ struct mpr_ctx {
   double t_ms = 0.0;
   int64_t t_launches = 0, t_site_sweeps = 0;
   int64_t sites_all_chains = 0;
+  // hipGraph of the fill's sweep sequence (mpr_set_graph): valid for the
+  // host state and arguments in key, after which the host state is post.
+  bool graph_on = false;
+  bool capturing = false;
+  struct GraphState {
+    int64_t sweep_index, pass_no;
+    int cur, nsw_run, threads;
+    int32_t n_eq, n_samp, stride;
+    bool keep_a;
+    bool operator==(const GraphState &o) const {
+      return sweep_index == o.sweep_index && pass_no == o.pass_no && cur == o.cur && nsw_run == o.nsw_run &&
+             threads == o.threads && n_eq == o.n_eq && n_samp == o.n_samp && stride == o.stride && keep_a == o.keep_a;
+    }
+  };
+  GraphState g_key{}, g_post{};
+  int64_t g_launches = 0, g_site_sweeps = 0;  // sweep launches inside the graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   ~mpr_ctx() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -196,6 +224,7 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.energy = (double *)take(8 * 3 * C * kMaxPass);
   v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * 4, pl.n_cblocks * 2));
   v.out = (double *)take(8 * std::max<size_t>((size_t)n * 4, C * 2));
+  v.rep = (double *)take(8 * 2 * C);
   v.plan = (uint16_t *)take(2 * (size_t)pl.plan_entries);
   v.plan_cum = (uint32_t *)take(4 * (size_t)pl.n_tiles * 2 * (pl.dmax + 2));
   pl.bytes = off;
@@ -221,6 +250,7 @@ void bind(Views &v, const Views &o, void *ws) {
   v.energy = rebase(o.energy, b);
   v.part = rebase(o.part, b);
   v.out = rebase(o.out, b);
+  v.rep = rebase(o.rep, b);
   v.plan = rebase(o.plan, b);
   v.plan_cum = rebase(o.plan_cum, b);
 }
@@ -325,7 +355,10 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.plan_cum = c->v.plan_cum;
   A.plan_dmax = c->plan.dmax;
   HIP_TRY(c, launch_sweep<P>(A, c->threads, c->plan.n_items, lds, c->stream));
-  if (c->timing) {
+  if (c->capturing) {
+    c->g_launches += 1;
+    c->g_site_sweeps += (int64_t)nsw * c->sites_all_chains;
+  } else if (c->timing) {
     c->t_launches += 1;
     c->t_site_sweeps += (int64_t)nsw * c->sites_all_chains;
   }
@@ -378,7 +411,8 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
   if (c->sweep_index + n >= 0xFFFFFFFFLL) return fail(c, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
   // Timing brackets the whole run of back-to-back sweep launches with one
   // event pair: per-launch events would stall the queue between launches.
-  if (c->timing && n > 0) {
+  const bool timed = c->timing && !c->capturing && n > 0;
+  if (timed) {
     if (c->ev_used + 2 > c->ev.size()) {
       if (c->ev.size() < 64) {
         for (int i = 0; i < 2; ++i) {
@@ -415,7 +449,7 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
     if (st != MPR_OK) return st;
     done += len;
   }
-  if (c->timing && n > 0) {
+  if (timed) {
     HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
     c->ev_used += 2;
   }
@@ -436,6 +470,60 @@ mpr_status reduce_energy(mpr_ctx *c, int what, std::vector<double> &out) {
   out.resize((size_t)units * 2);
   HIP_TRY(c, hipMemcpyAsync(out.data(), c->v.out, 16 * (size_t)units, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MPR_OK;
+}
+
+// Device part of set-up (mpr_init_field, mpr_reinit): Eq. (2) bounds and
+// gap counts of every grid from the caller's z and known, the hot start,
+// the gap-site plan, a = 1 and cleared counters; resets the host-side
+// sweep state.  Synchronises the stream.
+mpr_status device_init(mpr_ctx *c) {
+  const int n_grids = c->n_grids;
+  std::vector<double> mm((size_t)n_grids * 4);
+  for (GridDesc &d : c->plan.gd) d.zmin = d.zmax = NAN;
+  HIP_TRY(c, hipMemcpyAsync(c->v.gd, c->plan.gd.data(), sizeof(GridDesc) * n_grids, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, launch_minmax(c->v.gd, n_grids, c->plan.n_sblocks, c->v.zp, c->v.kp, c->v.part, c->stream));
+  HIP_TRY(c, launch_minmax_final(c->v.gd, n_grids, c->v.part, c->v.out, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(mm.data(), c->v.out, 8 * mm.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int g = 0; g < n_grids; ++g) {
+    const double mn = mm[g * 4], mx = mm[g * 4 + 1], cnt = mm[g * 4 + 2], bad = mm[g * 4 + 3];
+    if (bad > 0) return fail(c, MPR_E_ARG, "grid " + std::to_string(g) + ": non-finite z at a sample site");
+    GridDesc &d = c->plan.gd[g];
+    d.n_gap = (int64_t)d.nx * d.ny - (int64_t)cnt;
+    if (cnt > 0) {
+      if (!(mx > mn)) return fail(c, MPR_E_DEGENERATE, "grid " + std::to_string(g) + ": z_max == z_min");
+      d.zmin = mn;
+      d.zmax = mx;
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->v.gd, c->plan.gd.data(), sizeof(GridDesc) * n_grids, hipMemcpyHostToDevice,
+                            c->stream));
+  const uint32_t key0 = (uint32_t)(c->p.seed & 0xffffffffu), key1 = (uint32_t)(c->p.seed >> 32);
+  if (c->p.dtype == MPR_FP64) {
+    HIP_TRY(c, launch_init<double>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (double *)c->v.st[0],
+                                   (double *)c->v.st[1], 0.0, key0, key1, c->stream));
+    HIP_TRY(c, launch_plan<double>(c->v.gd, n_grids, c->plan.n_tiles, (const double *)c->v.st[0], c->plan.tile_x,
+                                   c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
+  } else {
+    HIP_TRY(c, launch_init<float>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (float *)c->v.st[0],
+                                  (float *)c->v.st[1], 0.0f, key0, key1, c->stream));
+    HIP_TRY(c, launch_plan<float>(c->v.gd, n_grids, c->plan.n_tiles, (const float *)c->v.st[0], c->plan.tile_x,
+                                  c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
+  }
+  const int64_t C = c->plan.total_chains;
+  HIP_TRY(c, launch_fill_f64(c->v.a, 2 * C, 1.0, c->stream));
+  HIP_TRY(c, launch_fill_f64(c->v.beta, C, 0.0, c->stream));
+  HIP_TRY(c, launch_fill_f64(c->v.window, 2 * C, 0.0, c->stream));
+  HIP_TRY(c, launch_fill_f64(c->v.accsum, C, 0.0, c->stream));
+  HIP_TRY(c, launch_zero_u32(c->v.counts, 3 * C * kMaxPass, c->stream));
+  HIP_TRY(c, launch_fill_f64(c->v.energy, 3 * C * kMaxPass, 0.0, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->sweep_index = 0;
+  c->pass_no = 0;
+  c->pending = PassEnd{};
   return MPR_OK;
 }
 
@@ -569,55 +657,15 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
     zp[g] = grids[g].z;
     kp[g] = grids[g].known;
   }
-  std::vector<double> mm((size_t)n_grids * 4);
 #define TRY(call)                                      \
   do {                                                 \
     hipError_t e_ = (call);                            \
     if (e_ != hipSuccess) return bail(hip_fail(c, e_, #call)); \
   } while (0)
-  TRY(hipMemcpyAsync(c->v.gd, c->plan.gd.data(), sizeof(GridDesc) * n_grids, hipMemcpyHostToDevice, c->stream));
   TRY(hipMemcpyAsync(c->v.zp, zp.data(), sizeof(void *) * n_grids, hipMemcpyHostToDevice, c->stream));
   TRY(hipMemcpyAsync(c->v.kp, kp.data(), sizeof(void *) * n_grids, hipMemcpyHostToDevice, c->stream));
-  TRY(launch_minmax(c->v.gd, n_grids, c->plan.n_sblocks, c->v.zp, c->v.kp, c->v.part, c->stream));
-  TRY(launch_minmax_final(c->v.gd, n_grids, c->v.part, c->v.out, c->stream));
-  TRY(hipMemcpyAsync(mm.data(), c->v.out, 8 * mm.size(), hipMemcpyDeviceToHost, c->stream));
-  TRY(hipStreamSynchronize(c->stream));
-  for (int g = 0; g < n_grids; ++g) {
-    const double mn = mm[g * 4], mx = mm[g * 4 + 1], cnt = mm[g * 4 + 2], bad = mm[g * 4 + 3];
-    if (bad > 0) return bail(fail(c, MPR_E_ARG, "grid " + std::to_string(g) + ": non-finite z at a sample site"));
-    GridDesc &d = c->plan.gd[g];
-    d.n_gap = (int64_t)d.nx * d.ny - (int64_t)cnt;
-    if (cnt > 0) {
-      if (!(mx > mn)) return bail(fail(c, MPR_E_DEGENERATE, "grid " + std::to_string(g) + ": z_max == z_min"));
-      d.zmin = mn;
-      d.zmax = mx;
-    }
-  }
-  TRY(hipMemcpyAsync(c->v.gd, c->plan.gd.data(), sizeof(GridDesc) * n_grids, hipMemcpyHostToDevice, c->stream));
-  if (p->dtype == MPR_FP64) {
-    TRY(launch_init<double>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (double *)c->v.st[0],
-                            (double *)c->v.st[1], 0.0, (uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32),
-                            c->stream));
-  } else {
-    TRY(launch_init<float>(c->v.gd, n_grids, c->plan.n_cblocks, c->v.zp, c->v.kp, (float *)c->v.st[0],
-                           (float *)c->v.st[1], 0.0f, (uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32),
-                           c->stream));
-  }
-  if (p->dtype == MPR_FP64) {
-    TRY(launch_plan<double>(c->v.gd, n_grids, c->plan.n_tiles, (const double *)c->v.st[0], c->plan.tile_x,
-                            c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
-  } else {
-    TRY(launch_plan<float>(c->v.gd, n_grids, c->plan.n_tiles, (const float *)c->v.st[0], c->plan.tile_x,
-                           c->plan.tile_y, c->plan.dmax, c->v.plan, c->v.plan_cum, c->stream));
-  }
-  const int64_t C = c->plan.total_chains;
-  TRY(launch_fill_f64(c->v.a, 2 * C, 1.0, c->stream));
-  TRY(launch_fill_f64(c->v.beta, C, 0.0, c->stream));
-  TRY(launch_fill_f64(c->v.window, 2 * C, 0.0, c->stream));
-  TRY(launch_fill_f64(c->v.accsum, C, 0.0, c->stream));
-  TRY(launch_zero_u32(c->v.counts, 3 * C * kMaxPass, c->stream));
-  TRY(launch_fill_f64(c->v.energy, 3 * C * kMaxPass, 0.0, c->stream));
-  TRY(hipStreamSynchronize(c->stream));
+  const mpr_status ist = device_init(c);
+  if (ist != MPR_OK) return bail(ist);
 #undef TRY
   *ctx = c;
   return MPR_OK;
@@ -720,6 +768,97 @@ mpr_status mpr_match_T(const double *e_s, int32_t n, const double *tab_T, const 
   return ret;
 }
 
+// The device work of a fill up to its last sampling pass (Algorithm 2,
+// steps 4-5): no host synchronisation, so a stream capture can record it.
+// The a and acceptance sums after equilibration go to the report scratch.
+static mpr_status fill_sweeps(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_t stride) {
+  const int64_t C = ctx->plan.total_chains;
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
+  HIP_TRY(ctx, launch_fill_f64(win_buf(ctx, ctx->pass_no), C, 0.0, ctx->stream));
+  mpr_status st = run_sweeps(ctx, n_eq, true, false, nullptr, 0);
+  if (st != MPR_OK) return st;
+  HIP_TRY(ctx, launch_copy_f64(ctx->v.rep, a_buf(ctx, ctx->pass_no), C, ctx->stream));
+  HIP_TRY(ctx, launch_copy_f64(ctx->v.rep + C, ctx->v.accsum, C, ctx->stream));
+  if (!ctx->p.a_sample_keep) HIP_TRY(ctx, launch_fill_f64(a_buf(ctx, ctx->pass_no), C, 1.0, ctx->stream));
+  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
+  return run_sweeps(ctx, n_samp, false, false, nullptr, stride);
+}
+
+// fill_sweeps through the context's graph: replayed when the host state and
+// arguments match those it was captured for, captured afresh otherwise.
+// Clears use fill kernels, never memset nodes.
+static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_t stride) {
+  const mpr_ctx::GraphState key{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
+                                n_eq,             n_samp,       stride,    ctx->p.a_sample_keep != 0};
+  if (!ctx->graph_exec || !(key == ctx->g_key)) {
+    ctx->drop_graph();
+    if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const hipStream_t user = ctx->stream;
+    const int64_t sweep0 = ctx->sweep_index, pass0 = ctx->pass_no;
+    const int cur0 = ctx->cur;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    ctx->g_launches = ctx->g_site_sweeps = 0;
+    hipGraph_t g = nullptr;
+    mpr_status st = MPR_OK;
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      st = fill_sweeps(ctx, n_eq, n_samp, stride);
+      e = hipStreamEndCapture(ctx->stream, &g);
+    }
+    ctx->capturing = false;
+    ctx->stream = user;
+    const mpr_ctx::GraphState post{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
+                                   n_eq,             n_samp,       stride,    key.keep_a};
+    // nothing has run yet: the host state goes back until the graph launches
+    ctx->sweep_index = sweep0;
+    ctx->pass_no = pass0;
+    ctx->cur = cur0;
+    ctx->pending = PassEnd{};
+    if (st == MPR_OK && e != hipSuccess) st = hip_fail(ctx, e, "graph capture");
+    if (st == MPR_OK) {
+      e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    if (st != MPR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      ctx->graph_exec = nullptr;
+      return st;
+    }
+    ctx->graph = g;
+    ctx->g_key = key;
+    ctx->g_post = post;
+  }
+  const bool timed = ctx->timing;
+  if (timed) {
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+      if (ctx->ev.size() < 64) {
+        for (int i = 0; i < 2; ++i) {
+          hipEvent_t ev;
+          HIP_TRY(ctx, hipEventCreate(&ev));
+          ctx->ev.push_back(ev);
+        }
+      } else {
+        const mpr_status st = drain_timing(ctx);
+        if (st != MPR_OK) return st;
+      }
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used], ctx->stream));
+  }
+  HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  if (timed) {
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream));
+    ctx->ev_used += 2;
+    ctx->t_launches += ctx->g_launches;
+    ctx->t_site_sweeps += ctx->g_site_sweeps;
+  }
+  ctx->sweep_index = ctx->g_post.sweep_index;
+  ctx->pass_no = ctx->g_post.pass_no;
+  ctx->cur = ctx->g_post.cur;
+  ctx->pending = PassEnd{};
+  return MPR_OK;
+}
+
 mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp, int32_t stride, double *zhat,
                     double *zstd, mpr_fill_report *rep) {
   if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
@@ -729,29 +868,13 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
   for (int g = 0; g < ctx->n_grids; ++g)
     if (std::isnan(ctx->plan.gd[g].zmin))
       return fail(ctx, MPR_E_DEGENERATE, "grid " + std::to_string(g) + " has no samples to fill from");
+  if (ctx->sweep_index + (int64_t)n_eq + n_samp >= 0xFFFFFFFFLL)
+    return fail(ctx, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
   mpr_status st = set_beta(ctx, T);
   if (st != MPR_OK) return st;
-  const int64_t C = ctx->plan.total_chains;
-  std::vector<double> hv;
-  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
-  HIP_TRY(ctx, launch_fill_f64(win_buf(ctx, ctx->pass_no), C, 0.0, ctx->stream));
-  st = run_sweeps(ctx, n_eq, true, false, nullptr, 0);
+  st = close_pending(ctx);
   if (st != MPR_OK) return st;
-  if (rep && (rep->a_eq || rep->acc_eq)) {
-    hv.resize(C);
-    if (rep->a_eq) {
-      HIP_TRY(ctx, hipMemcpyAsync(rep->a_eq, a_buf(ctx, ctx->pass_no), 8 * C, hipMemcpyDeviceToHost, ctx->stream));
-    }
-    HIP_TRY(ctx, hipMemcpyAsync(hv.data(), ctx->v.accsum, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (rep->acc_eq)
-      for (int64_t k = 0; k < C; ++k) rep->acc_eq[k] = n_eq ? hv[k] / n_eq : NAN;
-  }
-  if (!ctx->p.a_sample_keep) {
-    HIP_TRY(ctx, launch_fill_f64(a_buf(ctx, ctx->pass_no), C, 1.0, ctx->stream));
-  }
-  HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
-  st = run_sweeps(ctx, n_samp, false, false, nullptr, stride);
+  st = ctx->graph_on ? fill_sweeps_graph(ctx, n_eq, n_samp, stride) : fill_sweeps(ctx, n_eq, n_samp, stride);
   if (st != MPR_OK) return st;
   const int32_t records = n_samp / stride;
   if (ctx->p.dtype == MPR_FP64) {
@@ -767,14 +890,34 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
   }
   if (rep) {
     rep->records = records;
-    if (rep->acc_samp) {
-      hv.resize(C);
-      HIP_TRY(ctx, hipMemcpyAsync(hv.data(), ctx->v.accsum, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
+    if (rep->a_eq || rep->acc_eq || rep->acc_samp) {
+      const int64_t C = ctx->plan.total_chains;
+      std::vector<double> hv((size_t)C * 3);
+      HIP_TRY(ctx, hipMemcpyAsync(hv.data(), ctx->v.rep, 16 * C, hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipMemcpyAsync(hv.data() + 2 * C, ctx->v.accsum, 8 * C, hipMemcpyDeviceToHost, ctx->stream));
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-      for (int64_t k = 0; k < C; ++k) rep->acc_samp[k] = hv[k] / n_samp;
+      for (int64_t k = 0; k < C; ++k) {
+        if (rep->a_eq) rep->a_eq[k] = hv[k];
+        if (rep->acc_eq) rep->acc_eq[k] = n_eq ? hv[C + k] / n_eq : NAN;
+        if (rep->acc_samp) rep->acc_samp[k] = hv[2 * C + k] / n_samp;
+      }
     }
   }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPR_OK;
+}
+
+mpr_status mpr_reinit(mpr_ctx *ctx) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  const mpr_status st = close_pending(ctx);
+  if (st != MPR_OK) return st;
+  return device_init(ctx);
+}
+
+mpr_status mpr_set_graph(mpr_ctx *ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  ctx->graph_on = enable != 0;
+  if (!ctx->graph_on) ctx->drop_graph();
   return MPR_OK;
 }
 

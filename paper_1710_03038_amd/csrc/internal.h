@@ -120,5 +120,6 @@ template <typename P>
 hipError_t launch_set_phi(P *s0, P *s1, int64_t n, const double *in, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
 
 }  // namespace mpr

@@ -971,5 +971,14 @@ hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, p, n);
   return hipGetLastError();
 }
+__global__ void k_copy_f64(double *dst, const double *src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, dst, src, n);
+  return hipGetLastError();
+}
 
 }  // namespace mpr

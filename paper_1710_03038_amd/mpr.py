@@ -77,6 +77,8 @@ def lib():
         L.mpr_get_chain_state.argtypes = [vp, ctypes.POINTER(i64), dp]
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
         L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.mpr_reinit.argtypes = [vp]
+        L.mpr_set_graph.argtypes = [vp, i32]
         L.mpr_set_timing.argtypes = [vp, i32]
         L.mpr_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.mpr_destroy.argtypes = [vp]
@@ -280,6 +282,15 @@ class Field:
         thr = ctypes.c_int32(0)
         _check(lib().mpr_autotune(self.ctx, _dptr(T), trial_sweeps, ctypes.byref(nsw), ctypes.byref(thr)), self.ctx)
         return nsw.value, thr.value
+
+    def reinit(self):
+        """mpr_reinit: hot start again from the z and known tensors given at
+        construction (their values may have changed in place)."""
+        _check(lib().mpr_reinit(self.ctx), self.ctx)
+
+    def set_graph(self, enable=True):
+        """mpr_set_graph: record and replay mpr_fill's sweeps as a hipGraph."""
+        _check(lib().mpr_set_graph(self.ctx, 1 if enable else 0), self.ctx)
 
     def set_timing(self, enable=True):
         _check(lib().mpr_set_timing(self.ctx, 1 if enable else 0), self.ctx)

@@ -15,7 +15,7 @@ from paper_1710_03038_amd import mpr as M
 def test_library_exports_every_declared_symbol():
     L = M.lib()
     names = M.header_functions()
-    assert len(names) == 15
+    assert len(names) == 17
     for n in names:
         assert hasattr(L, n), n
 
@@ -114,5 +114,7 @@ def test_null_context_calls_fail_cleanly():
     assert L.mpr_specific_energy(None, 0, M._dptr(e), None) == M.MPR_E_STATE
     assert L.mpr_fill(None, M._dptr(T), 1, 1, 1, None, None, None) == M.MPR_E_STATE
     assert L.mpr_get_phi(None, 0, 0, None) == M.MPR_E_STATE
+    assert L.mpr_reinit(None) == M.MPR_E_STATE
+    assert L.mpr_set_graph(None, 1) == M.MPR_E_STATE
     L.mpr_destroy(None)
     assert b"NULL" in L.mpr_last_error(None)
