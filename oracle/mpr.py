@@ -36,6 +36,11 @@ Readings of points the paper leaves open (each also used by the library):
   (Algorithm 2, step 5.2) unless ``a_sample_keep``.
 * The fill records every ``stride``-th sampling sweep; the prediction is the
   arithmetic mean in angle space mapped back by the inverse of Eq. (2).
+* The Savitzky-Golay filter of Algorithm 2, step 4.4 has degree 1: the
+  slope is that of the least-squares line through the last n_fit specific
+  energies (one per sweep), checked after sweep i + 1 when i >= n_fit and
+  i is a multiple of n_f.  Chains of a batch sweep in lock-step until every
+  chain has passed a check.
 
 Random stream (a definition of this project): key = (seed mod 2^32,
 seed >> 32); counter = (pair, sweep, chain, grid) with
@@ -221,7 +226,8 @@ def site_energy(phi, nbrs, q):
     return -sum(np.where(np.isnan(n), 0.0, np.cos(q * (phi - np.nan_to_num(n)))) for n in nbrs)
 
 
-def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), npair=None):
+def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), npair=None,
+                 or_step=True):
     """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
 
     phi: (C, ny, nx) float64 current states (not modified).
@@ -237,6 +243,8 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     origin, npair: run on a window of a larger grid (see site_uniforms);
       the window's edges are then open boundaries, which is exact only for
       sites far enough from them.
+    or_step: False skips step 1 (no over-relaxation): the restricted
+      Metropolis update alone, or standard Metropolis with a = 1 (Sec. 2.4).
     Returns (new phi, accepted count per chain).
     """
     phi = np.array(phi, dtype=np.float64, copy=True)
@@ -252,7 +260,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     for colour in (0, 1):
         update = (((xx + yy) % 2) == colour) & ~known
         nbrs = _neighbours(phi)
-        phi1 = over_relax(phi, nbrs, q)                      # step 1
+        phi1 = over_relax(phi, nbrs, q) if or_step else phi  # step 1
         phi2 = wrap(phi1 + alpha * (u - 0.5))                # steps 2-3
         dH = site_energy(phi2, nbrs, q) - site_energy(phi1, nbrs, q)   # step 4
         with np.errstate(invalid="ignore", over="ignore"):
@@ -266,7 +274,9 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
             star = (2.0 * np.arctan2(hy, hx) - q * phi) / q
             raw = phi1 + alpha * (u - 0.5)
             margins["accept"] = np.where(sel, np.abs(r - ap), margins["accept"])
-            margins["or_edge"] = np.where(sel, np.minimum(np.abs(star), np.abs(star - TWO_PI)), margins["or_edge"])
+            if or_step:
+                margins["or_edge"] = np.where(sel, np.minimum(np.abs(star), np.abs(star - TWO_PI)),
+                                              margins["or_edge"])
             margins["wrap"] = np.where(sel, np.minimum(np.abs(raw), np.abs(raw - TWO_PI)), margins["wrap"])
         new = np.where(accept, phi2, phi1)
         phi = np.where(update[None], new, phi)
@@ -274,7 +284,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     return phi, accepted
 
 
-def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid):
+def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, or_step=True):
     """Algorithm 1 for one chain as a plain per-site loop (small grids only).
 
     Same checkerboard order and random stream as ``hybrid_sweep``; written
@@ -299,7 +309,7 @@ def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid):
                 cur = phi[y][x]
                 hx = sum(math.cos(q * v) for v in nb)
                 hy = sum(math.sin(q * v) for v in nb)
-                if hx * hx + hy * hy <= 1e-24:
+                if not or_step or hx * hx + hy * hy <= 1e-24:
                     p1 = cur
                 else:
                     star = (2.0 * math.atan2(hy, hx) - q * cur) / q
@@ -330,13 +340,15 @@ def adapt_a(a, acceptance, i, a_targ=0.3, k_a=3.0):
 
 
 def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
-               adapt=False, adapt_every=1, a_targ=0.3, k_a=3.0, trace_energy=False):
+               adapt=False, adapt_every=1, a_targ=0.3, k_a=3.0, trace_energy=False, or_step=True, window=None):
     """Advance C chains of one grid by ``n_sweeps`` hybrid sweeps.
 
     Returns (phi, a, acceptance per sweep (n, C), specific energy per sweep
     (n, C) or None).  With ``adapt`` the a-rule is applied every
     ``adapt_every`` sweeps using the mean acceptance of that window; the
-    rule's counter i is the global sweep index.
+    rule's counter i is the global sweep index.  ``window`` (C,), if given,
+    carries the running window sum across calls and is updated in place.
+    ``or_step`` = False leaves out over-relaxation.
     """
     C = phi.shape[0]
     T = np.broadcast_to(np.asarray(T, dtype=np.float64), (C,))
@@ -346,10 +358,11 @@ def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
     n_gap = int((~np.asarray(known, dtype=bool)).sum())
     acc_trace = np.zeros((n_sweeps, C))
     e_trace = np.zeros((n_sweeps, C)) if trace_energy else None
-    window = np.zeros(C)
+    if window is None:
+        window = np.zeros(C)
     for s in range(n_sweeps):
         i = first_sweep + s
-        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid)
+        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid, or_step=or_step)
         A = acc / n_gap if n_gap > 0 else np.ones(C)
         acc_trace[s] = A
         if trace_energy:
@@ -401,6 +414,75 @@ def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
     z_std = np.where(known, 0.0, (zmax - zmin) / TWO_PI * np.sqrt(var))
     return dict(z_hat=z_hat, z_std=z_std, records=m, zmin=zmin, zmax=zmax, a_eq=a_eq,
                 acc_eq=acc_eq, acc_samp=np.array(acc_samp), phi=phi)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2, step 4: automatic detection of equilibrium
+# --------------------------------------------------------------------------
+def ols_slope(y):
+    """Slope of the least-squares line through (k, y[k]), k = 0..n-1, over
+    the last axis.  This is the derivative estimate of the Savitzky-Golay
+    filter of degree 1 on that window (the same at every point of it).
+
+    With x centred, sum x_k y_k pairs mirrored points:
+    sum_{k < n/2} x_k (y_k - y_{n-1-k}); a constant or mirror-symmetric
+    window then gives exactly 0, so a flat energy never reads as falling.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[-1]
+    h = n // 2
+    x = np.arange(n, dtype=np.float64) - (n - 1) / 2.0
+    num = (x[:h] * (y[..., :h] - y[..., ::-1][..., :h])).sum(axis=-1)
+    return num / (x * x).sum()
+
+
+def sg_stop_index(e_after, n_f, n_fit, i_max):
+    """The loop of Algorithm 2, step 4, for one chain, on a given energy
+    series: e_after[j] is the specific energy after sweep j + 1.  The
+    slope k starts at -1; after sweep i + 1, when i >= n_fit and i is a
+    multiple of n_f, k becomes the degree-1 Savitzky-Golay slope of the
+    last n_fit energies (step 4.4); the loop runs while k < 0 and
+    i <= i_max.  Returns the number of sweeps it runs, or None when the
+    series is too short to tell."""
+    i, k = 0, -1.0
+    while k < 0 and i <= i_max:
+        if i >= len(e_after):
+            return None
+        if i >= n_fit and i % n_f == 0:
+            k = float(ols_slope(e_after[i + 1 - n_fit:i + 1]))
+        i += 1
+    return i
+
+
+def equilibrate(phi, known, T, a, q, seed, first_sweep, chains, grid, n_f=5, n_fit=20, i_max=1000,
+                adapt=True, or_step=True, adapt_every=1, a_targ=0.3, k_a=3.0):
+    """Algorithm 2, step 4, for C chains of one grid swept in lock-step:
+    hybrid sweeps (4.1), the a-rule (4.2, with ``adapt``), the specific
+    energy after every sweep (4.3) and the Savitzky-Golay slope check of
+    ``sg_stop_index`` per chain (4.4).  The batch runs until every chain's
+    slope has been >= 0 at a check, or i_max + 1 sweeps.  i counts the
+    sweeps of this call; the a-rule's counter is first_sweep + i.
+
+    Returns (phi, a, sweeps run, eq_at (C,): the sweep count after which
+    each chain's slope was first >= 0, or -1; energy trace (n, C);
+    acceptance trace (n, C)).
+    """
+    C = phi.shape[0]
+    eq_at = np.full(C, -1)
+    window = np.zeros(C)
+    e_hist, acc_hist = [], []
+    i = 0
+    while i <= i_max and np.any(eq_at < 0):
+        phi, a, acc, e = run_sweeps(phi, known, T, a, q, seed, first_sweep + i, 1, chains, grid, adapt=adapt,
+                                    adapt_every=adapt_every, a_targ=a_targ, k_a=k_a, trace_energy=True,
+                                    or_step=or_step, window=window)
+        e_hist.append(e[0])
+        acc_hist.append(acc[0])
+        if i >= n_fit and i % n_f == 0:
+            k = ols_slope(np.array(e_hist[i + 1 - n_fit:i + 1]).T)
+            eq_at = np.where((eq_at < 0) & (k >= 0), i + 1, eq_at)
+        i += 1
+    return phi, a, i, eq_at, np.array(e_hist), np.array(acc_hist)
 
 
 # --------------------------------------------------------------------------
