@@ -54,6 +54,8 @@ typedef enum { MPR_FP32 = 0, MPR_FP64 = 1 } mpr_dtype;
 /* mpr_sweep flags */
 #define MPR_ADAPT   1u /* apply the a-rule of Algorithm 2, step 4.2 */
 #define MPR_TRACE_E 2u /* record the specific energy e of Eq. (5) after every sweep */
+#define MPR_NO_OR   4u /* leave out Algorithm 1, step 1 (over-relaxation): restricted Metropolis
+                          alone, or standard Metropolis without MPR_ADAPT (a = 1, Sec. 2.4) */
 
 /* mpr_specific_energy selectors */
 #define MPR_SAMPLE_PAIRS 0 /* Eq. (4), one value per grid */
@@ -123,12 +125,36 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
  * T: host [n_grids], reduced temperatures; +INF (beta = 0) and 0 allowed.
  * flags: MPR_ADAPT applies the a-rule after every adapt_every sweeps
  *   (Algorithm 2, step 4.2) with the global sweep index as its counter;
- *   MPR_TRACE_E evaluates e of Eq. (5) after every sweep.
+ *   MPR_TRACE_E evaluates e of Eq. (5) after every sweep;
+ *   MPR_NO_OR leaves out over-relaxation.
  * trace: device [n_sweeps][total chains][2] doubles or NULL; receives the
  *   acceptance ratio A and (with MPR_TRACE_E, else NaN) e of each sweep.
  * Asynchronous.  Errors: MPR_E_ARG, MPR_E_STATE, MPR_E_HIP.
  */
 mpr_status mpr_sweep(mpr_ctx *ctx, int32_t n_sweeps, const double *T, uint32_t flags, double *trace);
+
+/*
+ * Algorithm 2, step 4 with automatic detection of equilibrium: sweeps of
+ * every chain (step 4.1; over-relaxation unless MPR_NO_OR), the a-rule
+ * (4.2) with MPR_ADAPT, the specific energy e of Eq. (5) after every sweep
+ * (4.3), and after sweep i + 1 (i counting this call's sweeps from 0), when
+ * i >= n_fit and i is a multiple of n_f, the slope of each chain's last
+ * n_fit energies by the Savitzky-Golay filter of degree 1, i.e. of their
+ * least-squares line (4.4).  A chain is equilibrated at the first check
+ * whose slope is >= 0; the chains of the context sweep in lock-step until
+ * all are, or for i_max + 1 sweeps.  The a-rule's counter is the global
+ * sweep index, as in mpr_sweep.  Follow with mpr_fill(n_eq = 0) to sample.
+ * T: host [n_grids].  flags: MPR_ADAPT, MPR_NO_OR.  n_f >= 1, n_fit >= 2,
+ * i_max >= 0.
+ * trace: device [i_max + 1][total chains][2] doubles (required): A and e
+ *   of each sweep run.
+ * n_done: host, nullable: sweeps run.  eq_at: host [total chains],
+ *   nullable: sweeps after which each chain's slope was first >= 0, or -1.
+ * Synchronises the stream every n_f sweeps once i >= n_fit (host-driven
+ * checks).  Errors: MPR_E_ARG, MPR_E_STATE, MPR_E_HIP.
+ */
+mpr_status mpr_equilibrate(mpr_ctx *ctx, const double *T, int32_t n_f, int32_t n_fit, int32_t i_max, uint32_t flags,
+                           double *trace, int32_t *n_done, int32_t *eq_at);
 
 /*
  * Specific energies of the current state.

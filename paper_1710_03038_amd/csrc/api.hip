@@ -308,7 +308,7 @@ mpr_status drain_timing(mpr_ctx *c) {
 
 template <typename P>
 mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace, int64_t trace_row0,
-                    uint32_t record_mask, uint32_t first_mask) {
+                    uint32_t record_mask, uint32_t first_mask, bool or_step) {
   SweepArgs<P> A{};
   int w, h;
   size_t lds;
@@ -325,6 +325,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.lds_w = w;
   A.lds_h = h;
   A.q_is_one = c->p.q == 1.0;
+  A.or_step = or_step ? 1 : 0;
   A.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
   A.key1 = (uint32_t)(c->p.seed >> 32);
   A.sweep0 = (uint32_t)c->sweep_index;
@@ -407,7 +408,8 @@ mpr_status close_pending(mpr_ctx *c) {
 // n sweeps in passes of at most nsw_max; with the a-rule no pass crosses the
 // end of an adapt_every window, so a is constant within every pass.
 // rec_stride > 0 records every rec_stride-th sweep of this run.
-mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *trace, int rec_stride) {
+mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *trace, int rec_stride,
+                      bool or_step = true) {
   if (c->sweep_index + n >= 0xFFFFFFFFLL) return fail(c, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
   // Timing brackets the whole run of back-to-back sweep launches with one
   // event pair: per-launch events would stall the queue between launches.
@@ -444,8 +446,8 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
         }
       }
     const mpr_status st = c->p.dtype == MPR_FP64
-                              ? run_pass<double>(c, (int)len, adapt, trace_e, trace, done, rec, first)
-                              : run_pass<float>(c, (int)len, adapt, trace_e, trace, done, rec, first);
+                              ? run_pass<double>(c, (int)len, adapt, trace_e, trace, done, rec, first, or_step)
+                              : run_pass<float>(c, (int)len, adapt, trace_e, trace, done, rec, first, or_step);
     if (st != MPR_OK) return st;
     done += len;
   }
@@ -674,10 +676,65 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
 mpr_status mpr_sweep(mpr_ctx *ctx, int32_t n_sweeps, const double *T, uint32_t flags, double *trace) {
   if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
   if (n_sweeps < 0) return fail(ctx, MPR_E_ARG, "n_sweeps must be >= 0");
-  if (flags & ~(MPR_ADAPT | MPR_TRACE_E)) return fail(ctx, MPR_E_ARG, "unknown flag");
+  if (flags & ~(MPR_ADAPT | MPR_TRACE_E | MPR_NO_OR)) return fail(ctx, MPR_E_ARG, "unknown flag");
   mpr_status st = set_beta(ctx, T);
   if (st != MPR_OK) return st;
-  return run_sweeps(ctx, n_sweeps, (flags & MPR_ADAPT) != 0, (flags & MPR_TRACE_E) != 0, trace, 0);
+  return run_sweeps(ctx, n_sweeps, (flags & MPR_ADAPT) != 0, (flags & MPR_TRACE_E) != 0, trace, 0,
+                    (flags & MPR_NO_OR) == 0);
+}
+
+// Slope of the least-squares line through (k, y[k * stride]), k = 0..n-1,
+// from the differences of mirrored values: sum_{k < n/2} x_k (y_k -
+// y_{n-1-k}) / sum x_k^2 with x centred, exactly 0 for a flat window.
+static double ls_slope(const double *y, int n, int64_t stride) {
+  const double c = 0.5 * (n - 1);
+  double num = 0.0, den = 0.0;
+  for (int k = 0; k < n / 2; ++k) num += (k - c) * (y[k * stride] - y[(n - 1 - k) * stride]);
+  for (int k = 0; k < n; ++k) den += (k - c) * (k - c);
+  return num / den;
+}
+
+mpr_status mpr_equilibrate(mpr_ctx *ctx, const double *T, int32_t n_f, int32_t n_fit, int32_t i_max, uint32_t flags,
+                           double *trace, int32_t *n_done, int32_t *eq_at) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (flags & ~(MPR_ADAPT | MPR_NO_OR)) return fail(ctx, MPR_E_ARG, "unknown flag");
+  if (n_f < 1 || n_fit < 2 || i_max < 0) return fail(ctx, MPR_E_ARG, "need n_f >= 1, n_fit >= 2, i_max >= 0");
+  if (!trace) return fail(ctx, MPR_E_ARG, "trace is NULL");
+  if (ctx->sweep_index + (int64_t)i_max + 1 >= 0xFFFFFFFFLL)
+    return fail(ctx, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
+  mpr_status st = set_beta(ctx, T);
+  if (st != MPR_OK) return st;
+  st = close_pending(ctx);
+  if (st != MPR_OK) return st;
+  const int64_t C = ctx->plan.total_chains;
+  const bool adapt = (flags & MPR_ADAPT) != 0, or_step = (flags & MPR_NO_OR) == 0;
+  if (adapt) HIP_TRY(ctx, launch_fill_f64(win_buf(ctx, ctx->pass_no), C, 0.0, ctx->stream));
+  std::vector<int32_t> at((size_t)C, -1);
+  std::vector<double> rows((size_t)n_fit * C * 2);
+  int64_t left = C;
+  int32_t i = 0;  // sweeps run by this call
+  while (i <= i_max && left > 0) {
+    // the next check follows sweep chk: chk >= n_fit and a multiple of n_f
+    int32_t chk = std::max(i, n_fit);
+    chk = (chk + n_f - 1) / n_f * n_f;
+    const int32_t last = std::min(chk, i_max);
+    st = run_sweeps(ctx, last - i + 1, adapt, true, trace + (size_t)i * C * 2, 0, or_step);
+    if (st != MPR_OK) return st;
+    i = last + 1;
+    if (last != chk) break;  // i_max reached before the check
+    HIP_TRY(ctx, hipMemcpyAsync(rows.data(), trace + (size_t)(chk + 1 - n_fit) * C * 2, rows.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t c = 0; c < C; ++c)
+      if (at[c] < 0 && ls_slope(rows.data() + c * 2 + 1, n_fit, C * 2) >= 0.0) {
+        at[c] = chk + 1;
+        --left;
+      }
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (n_done) *n_done = i;
+  if (eq_at) std::copy(at.begin(), at.end(), eq_at);
+  return MPR_OK;
 }
 
 mpr_status mpr_specific_energy(mpr_ctx *ctx, int32_t what, double *e_out, int64_t *npairs_out) {

@@ -54,6 +54,7 @@ struct SweepArgs {
   int32_t nsw;                     // sweeps in this pass
   int32_t lds_w, lds_h;            // LDS extent in sites (lds_w even)
   int32_t q_is_one;
+  int32_t or_step;                 // 1: Algorithm 1, step 1 (over-relaxation); 0: Metropolis only
   uint32_t key0, key1;
   uint32_t sweep0;                 // global index of the pass's first sweep
   uint32_t record_mask, first_mask;

@@ -208,6 +208,7 @@ template <typename P> struct UpdateCtx {
   int Ly, Lx, P2, pbase, npair;
   uint32_t sweep, cid, gid, k0, k1;
   P q, inv_q, alpha, beta;
+  bool or_step;        // over-relaxation on
 };
 
 // Algorithm 1 for the K plan entries fs[] of one thread, interleaved step
@@ -245,7 +246,7 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
     const bool live = h2 > Prec<P>::tiny_h2;
     const P psi = live ? Prec<P>::atan2_(hy[k], hx[k]) : P(0);
     P p1 = phi[k];
-    if (live) {
+    if (live && U.or_step) {
       const P star = (P(2) * psi - q * phi[k]) * U.inv_q;
       if (QONE) p1 = wrap_any(star);
       else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
@@ -405,7 +406,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       P *pc = ph + c * plane;
       V2 *cc = cs + c * plane;
       const V2 *cn = cs + (c ^ 1) * plane;
-      const UpdateCtx<P> U{lc, pc, cc, cn, Ly, Lx, P2, pbase, npair, sweep, cid, gid, k0, k1, q, inv_q, alpha, beta};
+      const UpdateCtx<P> U{lc,  pc,  cc,  cn, Ly, Lx,    P2,    pbase, npair,        sweep,
+                           cid, gid, k0, k1, q,  inv_q, alpha, beta,  A.or_step != 0};
       // In FP32, two independent updates per thread and iteration (items f
       // and f + NT) give the scheduler two dependency chains to interleave;
       // a lane without a second item repeats its first, whose identical

@@ -22,7 +22,7 @@ MPR_OK, MPR_E_ARG, MPR_E_SHAPE, MPR_E_DEGENERATE, MPR_E_NOPAIRS, MPR_E_RANGE, \
 STATUS_NAMES = ["MPR_OK", "MPR_E_ARG", "MPR_E_SHAPE", "MPR_E_DEGENERATE", "MPR_E_NOPAIRS",
                 "MPR_E_RANGE", "MPR_E_WORKSPACE", "MPR_E_HIP", "MPR_E_STATE"]
 FP32, FP64 = 0, 1
-ADAPT, TRACE_E = 1, 2
+ADAPT, TRACE_E, NO_OR = 1, 2, 4
 SAMPLE_PAIRS, STATE = 0, 1
 
 
@@ -78,6 +78,7 @@ def lib():
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
         L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_reinit.argtypes = [vp]
+        L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_set_graph.argtypes = [vp, i32]
         L.mpr_set_timing.argtypes = [vp, i32]
         L.mpr_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -214,16 +215,31 @@ class Field:
         return np.ascontiguousarray(T)
 
     # -- Algorithm 1
-    def sweep(self, n_sweeps, T, adapt=False, trace_energy=False, trace=False):
-        """Run n hybrid sweeps.  Returns a (n, chains, 2) tensor of (A, e) per
-        sweep when ``trace`` (e is NaN unless ``trace_energy``)."""
+    def sweep(self, n_sweeps, T, adapt=False, trace_energy=False, trace=False, over_relax=True):
+        """Run n hybrid sweeps (Metropolis only when not ``over_relax``).
+        Returns a (n, chains, 2) tensor of (A, e) per sweep when ``trace`` (e
+        is NaN unless ``trace_energy``)."""
         torch = self._torch
         T = self._T(T)
         tr = torch.empty((n_sweeps, self.total_chains, 2), dtype=torch.float64, device=self.device) if trace else None
-        flags = (ADAPT if adapt else 0) | (TRACE_E if trace_energy else 0)
+        flags = (ADAPT if adapt else 0) | (TRACE_E if trace_energy else 0) | (0 if over_relax else NO_OR)
         _check(lib().mpr_sweep(self.ctx, n_sweeps, _dptr(T), flags,
                                ctypes.c_void_p(tr.data_ptr() if tr is not None else 0)), self.ctx)
         return tr
+
+    def equilibrate(self, T, n_f=5, n_fit=20, i_max=1000, adapt=True, over_relax=True):
+        """mpr_equilibrate (Algorithm 2, step 4, stopped by the Savitzky-Golay
+        slope test).  Returns (sweeps run, per-chain sweeps at which the
+        slope was first >= 0 or -1, (n, chains, 2) tensor of (A, e))."""
+        torch = self._torch
+        T = self._T(T)
+        tr = torch.empty((i_max + 1, self.total_chains, 2), dtype=torch.float64, device=self.device)
+        n = ctypes.c_int32(0)
+        at = np.empty(self.total_chains, dtype=np.int32)
+        flags = (ADAPT if adapt else 0) | (0 if over_relax else NO_OR)
+        _check(lib().mpr_equilibrate(self.ctx, _dptr(T), n_f, n_fit, i_max, flags, ctypes.c_void_p(tr.data_ptr()),
+                                     ctypes.byref(n), at.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), self.ctx)
+        return n.value, at, tr[:n.value]
 
     # -- Eqs. (4), (5)
     def specific_energy(self, what=SAMPLE_PAIRS, allow_nopairs=False):

@@ -73,7 +73,7 @@ def test_specific_energies(dtype):
 CASES = [(0.3, 1.0), (0.02, 5.0), (1e-3, 40.0), (math.inf, 1.0), (0.0, 3.0)]
 
 
-def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11):
+def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True):
     grids = _grids(21)
     f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw)
     C = f.total_chains
@@ -90,7 +90,7 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11):
             for c in range(chains):
                 f.set_phi(phi[c], g, c)
         f.set_chain_state(sweep_index, np.full(C, a))
-        tr = f.sweep(nsw, np.full(len(grids), T), trace=True).cpu().numpy()
+        tr = f.sweep(nsw, np.full(len(grids), T), trace=True, over_relax=or_step).cpu().numpy()
         k = 0
         for g, (z, known, chains) in enumerate(grids):
             beta = beta_of(T)
@@ -99,7 +99,8 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11):
             accs = []
             for s in range(nsw):
                 phi, acc = om.hybrid_sweep(phi, known.astype(bool), [beta] * chains, [TWO_PI / a] * chains, 0.5,
-                                           seed, sweep_index + s, np.arange(chains), g, margins=margins)
+                                           seed, sweep_index + s, np.arange(chains), g, margins=margins,
+                                           or_step=or_step)
                 accs.append(acc)
             for c in range(chains):
                 got = f.get_phi(g, c).cpu().numpy()
@@ -135,6 +136,20 @@ def test_teacher_forced_sweep_fp32(tile, nsw):
         total_bad += n_bad
         total_gap += int((~known.astype(bool)).sum())
     assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_teacher_forced_sweep_without_over_relaxation(dtype):
+    # Metropolis alone (MPR_NO_OR), the update the paper compares with the
+    # hybrid: same tolerances as the hybrid sweep.
+    total_gap = total_bad = 0
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced(dtype, (32, 24), 2, or_step=False):
+        if dtype == "fp64":
+            assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
+        else:
+            total_bad += int(((np.abs(got - ref) > 1e-3) & ~known.astype(bool)).sum())
+            total_gap += int((~known.astype(bool)).sum())
+    assert total_bad <= max(3, 1e-3 * max(total_gap, 1)), (total_bad, total_gap)
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
