@@ -42,10 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # probes; the published 157.3 TFLOP/s FP32 is this peak times 2 flops per FMA.
 VALU_PEAK_TINST = 256 * 4 * 32 * 2.4e9 / 1e12
 # Issue slots (2-cycle units) of one FP32 gap-site update in the compiled
-# sweep kernel: the update loop of k_sweep<float> for q = 1/2 has 177 VALU
-# instructions, of which 21 v_mad_u64_u32 for Philox and 5 transcendentals
-# at 4 slots each: 172 + 5 * 4 = 192.
-VALU_INST_PER_UPDATE = 192
+# sweep kernel for q = 1/2: the two-update iteration of k_sweep<float> has
+# 347 VALU instructions for two updates, of which 2 x 20 v_mad_u64_u32 for
+# Philox and 2 x 5 transcendentals at 4 slots each: (337 + 40) / 2 = 188.5
+# (the one-update iteration: 165 + 5 * 4 = 185).
+VALU_INST_PER_UPDATE = 188
 KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
                   "paper_1710_03038_amd/csrc/internal.h")
 PROFILE = "profiles/k_sweep_fp32_grid1024.md"
@@ -74,6 +75,61 @@ def profiled_traffic():
     if not m or m.group(2) != h.hexdigest():
         return None
     return float(m.group(1))
+
+
+def relaxation_study(L, p, sweeps, chains=4, seed=512, field="wm"):
+    """Relaxation of the specific energy from the hot start under the three
+    updates the paper compares (Sec. 2.4): hybrid (over-relaxation and the
+    a-rule), restricted Metropolis (a-rule, no over-relaxation) and standard
+    Metropolis (a = 1, no over-relaxation).  Input: WM(0.5, 0.5) field, mean
+    50, std 10, on an L x L grid with floor(p L^2) random gaps, at the
+    temperature fitted by specific energy matching (field="se16": a smooth
+    squared-exponential field, length 16, instead).  Reports each update's
+    Savitzky-Golay equilibration point (Algorithm 2, step 4: n_f = 5,
+    n_fit = 20) and its mean energy at fixed sweep counts."""
+    import torch
+
+    import mprgen
+    from paper_1710_03038_amd import mpr as M
+    from paper_1710_03038_amd.etable import load_table
+
+    table = load_table()
+    if field == "wm":
+        z = mprgen.matern_field(L, L, 0.5, 0.5, seed + 1, mean=50.0, std=10.0)
+        desc = "WM(0.5, 0.5), mean 50, std 10 (synthetic)"
+    else:
+        z = mprgen.gaussian_field(L, L, 16.0, seed + 1, mean=50.0, std=10.0)
+        desc = "squared-exponential, length 16, mean 50, std 10 (synthetic)"
+    known = mprgen.mask_random(L, L, p, seed + 2)
+    dev = torch.device("cuda:0")
+    grids = [(torch.from_numpy(z).to(dev), torch.from_numpy(known).to(dev), chains)]
+    f = M.Field(grids, M.default_params(dtype="fp32", seed=seed + 3))
+    e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
+    T, _ = M.match_T(e_s, table[0], table[1])
+    marks = [m for m in (10, 20, 50, 100, 200, 500, 1000, 2000, 5000, 10000, 20000, 50000, 100000) if m <= sweeps]
+    out = {"study": "relaxation", "grid": [L, L], "field": desc,
+           "gap_fraction": p, "chains": chains, "T_hat": float(T[0]), "e_s": float(e_s[0]), "n_f": 5, "n_fit": 20,
+           "updates": {}}
+    for name, adapt, over_relax in (("hybrid", True, True), ("restricted", True, False), ("standard", False, False)):
+        f.reinit()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_sg, at, tr_sg = f.equilibrate(T, n_f=5, n_fit=20, i_max=sweeps - 1, adapt=adapt, over_relax=over_relax)
+        torch.cuda.synchronize()
+        t_sg = time.perf_counter() - t0
+        f.reinit()
+        tr = f.sweep(sweeps, T, adapt=adapt, trace=True, trace_energy=True, over_relax=over_relax).cpu().numpy()
+        e = tr[:, :, 1].mean(axis=1)
+        out["updates"][name] = {"sg_equilibrated_at": [int(v) for v in at], "sg_sweeps_run": n_sg,
+                                "sg_seconds": t_sg, "acceptance_last": float(tr[-1, :, 0].mean()),
+                                "e_at": {str(m): float(e[m - 1]) for m in marks}}
+    f.close()
+    h = out["updates"]["hybrid"]["e_at"]
+    ref = np.mean([h[str(m)] for m in marks[-3:]])  # hybrid's late level as the equilibrium energy
+    out["e_equilibrium_hybrid"] = float(ref)
+    for name, u in out["updates"].items():
+        u["e_minus_equilibrium"] = {k: v - ref for k, v in u["e_at"].items()}
+    print(json.dumps(out), flush=True)
 
 
 def copy_calibration(nbytes=256 << 20, reps=10):
@@ -205,6 +261,14 @@ def main():
                     help="keep the library's default launch shape (for profiling runs, whose timing would sway "
                          "the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--study", choices=["relaxation"], default=None,
+                    help="relaxation: energy relaxation of the hybrid, restricted and standard Metropolis updates "
+                         "and their Savitzky-Golay equilibration points (L x L Whittle-Matern field, p gaps)")
+    ap.add_argument("--L", type=int, default=512)
+    ap.add_argument("--p", type=float, default=0.9)
+    ap.add_argument("--sweeps", type=int, default=20000)
+    ap.add_argument("--field", choices=["wm", "se16"], default="wm",
+                    help="relaxation study input: WM(0.5, 0.5) (the paper's) or squared-exponential, length 16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -214,6 +278,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.study == "relaxation":
+        relaxation_study(args.L, args.p, args.sweeps, field=args.field)
         return
 
     import torch

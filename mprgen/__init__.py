@@ -8,9 +8,9 @@ The paper validates on Gaussian fields with mean 50 and standard deviation 10
 sampled by a spectral method, with sites removed by random thinning or as
 solid blocks (Sec. 4.1), and on lognormal data (Sec. 4.3).  Its own fields
 and the two real datasets are not available here; these generators stand in
-for them.  The covariance used is squared-exponential,
-C(h) = sigma^2 exp(-h^2 / (2 l^2)), sampled exactly on a periodic torus by
-circulant embedding and cropped.
+for them.  The covariances are squared-exponential,
+C(h) = sigma^2 exp(-h^2 / (2 l^2)), and the paper's Whittle-Matern family,
+sampled on a periodic torus by circulant embedding and cropped.
 """
 import math
 
@@ -34,20 +34,20 @@ def _fft_size(n):
     return best
 
 
-def gaussian_field(ny, nx, corr_len, seed, mean=0.0, std=1.0):
-    """Stationary Gaussian field with squared-exponential covariance.
+def _circulant_field(ny, nx, corr_sq, margin, seed, mean, std):
+    """Stationary Gaussian field with correlation corr_sq(h^2) (1 at 0).
 
-    Circulant embedding on a torus at least 4 correlation lengths larger
-    than the grid: eigenvalues lambda = Re FFT2(c), clipped at 0;
+    Circulant embedding on a torus ``margin`` sites larger than the grid:
+    eigenvalues lambda = Re FFT2(c), clipped at 0;
     Y = Re IFFT2(sqrt(lambda) * FFT2(W)) with W iid N(0, 1); crop to ny x nx.
     """
     import scipy.fft as sfft
 
-    my = _fft_size(ny + int(math.ceil(4 * corr_len)))
-    mx = _fft_size(nx + int(math.ceil(4 * corr_len)))
+    my = _fft_size(ny + margin)
+    mx = _fft_size(nx + margin)
     dy = np.minimum(np.arange(my), my - np.arange(my)).astype(np.float64)
     dx = np.minimum(np.arange(mx), mx - np.arange(mx)).astype(np.float64)
-    cov = np.exp(-(dy[:, None] ** 2 + dx[None, :] ** 2) / (2.0 * corr_len ** 2))
+    cov = corr_sq(dy[:, None] ** 2 + dx[None, :] ** 2)
     lam = np.maximum(sfft.rfft2(cov, workers=-1).real, 0.0)
     del cov
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -57,6 +57,34 @@ def gaussian_field(ny, nx, corr_len, seed, mean=0.0, std=1.0):
     spec *= np.sqrt(lam)
     y = sfft.irfft2(spec, s=(my, mx), workers=-1)[:ny, :nx]
     return np.ascontiguousarray(mean + std * y)
+
+
+def gaussian_field(ny, nx, corr_len, seed, mean=0.0, std=1.0):
+    """Stationary Gaussian field with squared-exponential covariance
+    sigma^2 exp(-h^2 / (2 l^2)), on a torus 4 correlation lengths larger."""
+    return _circulant_field(ny, nx, lambda h2: np.exp(-h2 / (2.0 * corr_len ** 2)),
+                            int(math.ceil(4 * corr_len)), seed, mean, std)
+
+
+def matern_corr(h, kappa, nu):
+    """Whittle-Matern correlation 2^(1-nu) / Gamma(nu) (kappa h)^nu
+    K_nu(kappa h), 1 at h = 0 (the paper's WM(kappa, nu) covariance divided
+    by sigma^2)."""
+    from scipy.special import gamma, kv
+
+    x = kappa * np.asarray(h, dtype=np.float64)
+    out = np.ones_like(x)
+    pos = x > 0
+    out[pos] = (2.0 ** (1.0 - nu) / gamma(nu)) * x[pos] ** nu * kv(nu, x[pos])
+    return out
+
+
+def matern_field(ny, nx, kappa, nu, seed, mean=0.0, std=1.0):
+    """Stationary Gaussian field with Whittle-Matern covariance WM(kappa, nu)
+    (nu = 1/2 is the exponential model), on a torus 12 / kappa larger than
+    the grid, where the correlation has fallen below 1e-4 for nu <= 1."""
+    return _circulant_field(ny, nx, lambda h2: matern_corr(np.sqrt(h2), kappa, nu), int(math.ceil(12.0 / kappa)),
+                            seed, mean, std)
 
 
 def lognormal_field(ny, nx, corr_len, seed, log_std=0.5, log_mean=0.0):
