@@ -105,6 +105,17 @@ def mask_random(ny, nx, p, seed):
     return known.reshape(ny, nx)
 
 
+def mask_block(ny, nx, side, seed):
+    """One solid side x side square of gaps at a uniform position (the
+    paper's block removal, Sec. 4.1).  Returns ``known`` as uint8."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    y0 = int(rng.integers(0, ny - side + 1))
+    x0 = int(rng.integers(0, nx - side + 1))
+    known = np.ones((ny, nx), dtype=np.uint8)
+    known[y0:y0 + side, x0:x0 + side] = 0
+    return known
+
+
 def mask_blocks(ny, nx, p, seed, block=16):
     """Solid block x block squares at uniform positions until gaps >= p."""
     rng = np.random.Generator(np.random.PCG64(seed))

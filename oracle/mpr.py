@@ -530,6 +530,22 @@ def match_T(e_s, tab_T, tab_e):
     return T_out, status
 
 
+def validation_measures(z_true, z_hat, gaps):
+    """The validation measures of Sec. 3.3 over the prediction sites (gaps),
+    with the estimation error eps = Z - Z_hat: AAE = mean |eps|,
+    ARE = mean eps / Z, AARE = mean |eps| / Z, RASE = sqrt(mean eps^2), and
+    R, the linear (Pearson) correlation coefficient of Z and Z_hat.  P is
+    the number of prediction sites."""
+    gaps = np.asarray(gaps, dtype=bool)
+    z = np.asarray(z_true, dtype=np.float64)[gaps]
+    zh = np.asarray(z_hat, dtype=np.float64)[gaps]
+    eps = z - zh
+    dz, dh = z - z.mean(), zh - zh.mean()
+    return dict(AAE=float(np.abs(eps).mean()), ARE=float((eps / z).mean()), AARE=float((np.abs(eps) / z).mean()),
+                RASE=float(math.sqrt((eps * eps).mean())),
+                R=float((dz * dh).sum() / math.sqrt((dz * dz).sum() * (dh * dh).sum())), P=int(z.size))
+
+
 def mae(z_true, z_hat, gaps):
     """Average absolute error over the prediction sites (Sec. 3, AAE)."""
     gaps = np.asarray(gaps, dtype=bool)

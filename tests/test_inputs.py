@@ -42,3 +42,11 @@ def test_random_mask_removes_exactly_floor_pN():
         known = mprgen.mask_random(37, 41, p, 3)
         assert known.dtype == np.uint8
         assert int((known == 0).sum()) == math.floor(p * 37 * 41)
+
+
+def test_single_block_mask():
+    for seed in range(5):
+        known = mprgen.mask_block(64, 48, 20, seed)
+        gy, gx = np.nonzero(known == 0)
+        assert gy.size == 400
+        assert gy.max() - gy.min() == 19 and gx.max() - gx.min() == 19
