@@ -132,6 +132,71 @@ def relaxation_study(L, p, sweeps, chains=4, seed=512, field="wm"):
     print(json.dumps(out), flush=True)
 
 
+PAPER_MPR = "tests/golden/paper_mpr_validation.txt"
+
+
+def validation_study(Ls, S):
+    """The paper's validation of the MPR method on synthetic data (Sec. 4):
+    WM(0.2, nu) Gaussian fields, mean 50, std 10, on L x L grids; case a:
+    33 % random gaps, b: 66 %, c: one 20 x 20 block.  Per configuration:
+    mpr_reinit, e_s, T-hat by SEM, mpr_equilibrate (n_f = 5, n_fit = 20),
+    mpr_fill with M = 100 recorded sweeps, mpr_validation_measures; timed on
+    the device from reinit to the measures.  Prints one JSON line per row
+    with the means over S configurations and the paper's printed values."""
+    import torch
+
+    import mprgen
+    from paper_1710_03038_amd import mpr as M
+    from paper_1710_03038_amd.etable import load_table
+
+    table = load_table()
+    paper = {}
+    for line in open(os.path.join(ROOT, PAPER_MPR)):
+        if line.startswith("#") or not line.strip():
+            continue
+        kappa, nu, L, case, *vals = line.split()
+        paper[(float(nu), int(L), case)] = dict(zip(("MAAE", "MARE", "MAARE", "MRASE", "MR"), map(float, vals)))
+    dev = torch.device("cuda:0")
+    for L in Ls:
+        n_cfg = S or (100 if L <= 256 else 40 if L <= 512 else 16 if L <= 1024 else 6)
+        for nu in (0.5, 0.25):
+            for case in ("a", "b", "c"):
+                zt = torch.empty((L, L), dtype=torch.float64, device=dev)
+                kt = torch.empty((L, L), dtype=torch.uint8, device=dev)
+                f = None
+                rows, secs, eqs = [], [], []
+                for s in range(n_cfg):
+                    base = 100000 * L + 1000 * int(nu * 100) + 10 * ord(case) + s
+                    z = mprgen.matern_field(L, L, 0.2, nu, base, mean=50.0, std=10.0)
+                    known = (mprgen.mask_block(L, L, 20, base + 1) if case == "c"
+                             else mprgen.mask_random(L, L, {"a": 0.33, "b": 0.66}[case], base + 1))
+                    zt.copy_(torch.from_numpy(z))
+                    kt.copy_(torch.from_numpy(known))
+                    if f is None:
+                        f = M.Field([(zt, kt, 1)], M.default_params(dtype="fp32", seed=base + 2))
+                        f.set_graph(True)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    f.reinit()
+                    e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
+                    T, _ = M.match_T(e_s, table[0], table[1])
+                    n, _, _ = f.equilibrate(T, n_f=5, n_fit=20, i_max=2000)
+                    zh, _, _ = f.fill(T, 0, 100, 1)
+                    m = f.validation_measures(0, zt, zh[0])
+                    secs.append(time.perf_counter() - t0)
+                    eqs.append(n)
+                    rows.append(m)
+                f.close()
+                mean = {k: float(np.mean([r[k] for r in rows])) for k in ("AAE", "ARE", "AARE", "RASE", "R")}
+                out = {"study": "validation", "L": L, "kappa": 0.2, "nu": nu, "case": case, "S": n_cfg,
+                       "MAAE": mean["AAE"], "MARE_pct": 100 * mean["ARE"], "MAARE_pct": 100 * mean["AARE"],
+                       "MRASE": mean["RASE"], "MR_pct": 100 * mean["R"],
+                       "MAAE_sd": float(np.std([r["AAE"] for r in rows])), "eq_sweeps_mean": float(np.mean(eqs)),
+                       "ms_per_configuration": 1e3 * float(np.mean(secs)),
+                       "paper": paper.get((nu, L, case))}
+                print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=256 << 20, reps=10):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters of rocprofv3 to bytes."""
@@ -261,9 +326,13 @@ def main():
                     help="keep the library's default launch shape (for profiling runs, whose timing would sway "
                          "the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--study", choices=["relaxation"], default=None,
+    ap.add_argument("--study", choices=["relaxation", "validation"], default=None,
                     help="relaxation: energy relaxation of the hybrid, restricted and standard Metropolis updates "
-                         "and their Savitzky-Golay equilibration points (L x L Whittle-Matern field, p gaps)")
+                         "and their Savitzky-Golay equilibration points (L x L Whittle-Matern field, p gaps); "
+                         "validation: the paper's MPR validation measures on WM(0.2, nu) data, one JSON line per "
+                         "(L, nu, case)")
+    ap.add_argument("--Ls", type=int, nargs="+", default=[256, 512, 1024])
+    ap.add_argument("--S", type=int, default=0, help="configurations per row (0: 100 at L <= 256, then fewer)")
     ap.add_argument("--L", type=int, default=512)
     ap.add_argument("--p", type=float, default=0.9)
     ap.add_argument("--sweeps", type=int, default=20000)
@@ -281,6 +350,9 @@ def main():
         return
     if args.study == "relaxation":
         relaxation_study(args.L, args.p, args.sweeps, field=args.field)
+        return
+    if args.study == "validation":
+        validation_study(args.Ls, args.S)
         return
 
     import torch

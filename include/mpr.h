@@ -201,6 +201,20 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
                     double *zstd, mpr_fill_report *rep);
 
 /*
+ * Validation measures of Sec. 3.3 for grid `grid` over its prediction sites
+ * (known == 0 in the context's mask), with eps = Z - Z_hat:
+ * out (host [8]) = AAE (mean |eps|), ARE (mean eps/Z), AARE (mean
+ * |eps|/Z), RASE (sqrt of mean eps^2), R (linear correlation coefficient
+ * of Z and Z_hat), P (number of prediction sites), mean Z, mean Z_hat.
+ * z_true: device [ny*nx], the complete field (the values the gaps hide);
+ * zhat: device [ny*nx], e.g. this grid's part of mpr_fill's output.
+ * FP64, deterministic order.  Synchronises the stream.  Errors: MPR_E_ARG,
+ * MPR_E_DEGENERATE (no prediction sites), MPR_E_HIP.
+ */
+mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_true, const double *zhat,
+                                   double *out);
+
+/*
  * Set the context up again from the caller's z and known buffers given to
  * mpr_init_field (same shapes; the values and the gap pattern may have
  * changed): Eq. (2) bounds, the hot start of Algorithm 2, steps 1.8 and

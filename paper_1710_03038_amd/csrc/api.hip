@@ -75,6 +75,7 @@ struct mpr_ctx {
   double t_ms = 0.0;
   int64_t t_launches = 0, t_site_sweeps = 0;
   int64_t sites_all_chains = 0;
+  std::vector<const uint8_t *> known_h;  // the caller's known buffers, per grid
   // hipGraph of the fill's sweep sequence (mpr_set_graph): valid for the
   // host state and arguments in key, after which the host state is post.
   bool graph_on = false;
@@ -222,8 +223,8 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.accsum = (double *)take(8 * C);
   v.counts = (uint32_t *)take(4 * 3 * C * kMaxPass);  // by pass number mod 3
   v.energy = (double *)take(8 * 3 * C * kMaxPass);
-  v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * 4, pl.n_cblocks * 2));
-  v.out = (double *)take(8 * std::max<size_t>((size_t)n * 4, C * 2));
+  v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * kMeasureSums, pl.n_cblocks * 2));
+  v.out = (double *)take(8 * std::max<size_t>({(size_t)n * 4, C * 2, (size_t)8}));
   v.rep = (double *)take(8 * 2 * C);
   v.plan = (uint16_t *)take(2 * (size_t)pl.plan_entries);
   v.plan_cum = (uint32_t *)take(4 * (size_t)pl.n_tiles * 2 * (pl.dmax + 2));
@@ -659,6 +660,7 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
     zp[g] = grids[g].z;
     kp[g] = grids[g].known;
   }
+  c->known_h = kp;
 #define TRY(call)                                      \
   do {                                                 \
     hipError_t e_ = (call);                            \
@@ -960,6 +962,21 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
       }
     }
   }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPR_OK;
+}
+
+mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_true, const double *zhat,
+                                   double *out) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (grid < 0 || grid >= ctx->n_grids) return fail(ctx, MPR_E_ARG, "grid index out of range");
+  if (!z_true || !zhat || !out) return fail(ctx, MPR_E_ARG, "z_true, zhat and out are required");
+  const GridDesc &d = ctx->plan.gd[grid];
+  if (d.n_gap == 0) return fail(ctx, MPR_E_DEGENERATE, "grid " + std::to_string(grid) + " has no prediction sites");
+  const double shift = std::isnan(d.zmin) ? 0.0 : d.zmin;
+  HIP_TRY(ctx, launch_measures(z_true, zhat, ctx->known_h[grid], (int64_t)d.nx * d.ny, shift, ctx->v.part,
+                               ctx->v.out, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->v.out, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return MPR_OK;
 }

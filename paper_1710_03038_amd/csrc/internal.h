@@ -122,5 +122,10 @@ hipError_t launch_set_phi(P *s0, P *s1, int64_t n, const double *in, hipStream_t
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
+// Validation measures of one grid (kMeasureSums partial sums per chunk of
+// kChunk sites in part; eight results in out).
+constexpr int kMeasureSums = 10;
+hipError_t launch_measures(const double *z, const double *zh, const uint8_t *known, int64_t n, double shift,
+                           double *part, double *out, hipStream_t s);
 
 }  // namespace mpr

@@ -869,6 +869,73 @@ hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_u
   return hipGetLastError();
 }
 
+// ---------------------------------------------------- validation measures
+// Sums over the gap sites of one chunk of a grid (Sec. 3.3): count, |eps|,
+// eps / Z, |eps| / Z, eps^2 with eps = Z - Z_hat, and the first and second
+// moments of Z - shift and Z_hat - shift for the correlation coefficient.
+__global__ void __launch_bounds__(kThreads)
+    k_measures(const double *z, const double *zh, const uint8_t *known, int64_t n, double shift, double *part) {
+  __shared__ double red[kThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double s[kMeasureSums] = {};
+  for (int64_t i = base + threadIdx.x; i < min(base + (int64_t)kChunk, n); i += kThreads) {
+    if (known[i]) continue;
+    const double zt = z[i], zp = zh[i], e = zt - zp, a = zt - shift, b = zp - shift;
+    s[0] += 1.0;
+    s[1] += fabs(e);
+    s[2] += e / zt;
+    s[3] += fabs(e) / zt;
+    s[4] += e * e;
+    s[5] += a;
+    s[6] += b;
+    s[7] += a * a;
+    s[8] += b * b;
+    s[9] += a * b;
+  }
+  for (int k = 0; k < kMeasureSums; ++k) {
+    const double v = block_sum<kThreads>(s[k], red);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kMeasureSums + k] = v;
+  }
+}
+
+// One workgroup: the chunk sums in a fixed order, then AAE, ARE, AARE, RASE,
+// R, P and the means of Z and Z_hat into out[0..7].
+__global__ void __launch_bounds__(kThreads) k_measures_final(const double *part, int64_t n_blocks, double shift,
+                                                             double *out) {
+  __shared__ double red[kThreads / 64];
+  __shared__ double tot[kMeasureSums];
+  for (int k = 0; k < kMeasureSums; ++k) {
+    double acc = 0.0;
+    for (int64_t j = threadIdx.x; j < n_blocks; j += kThreads) acc += part[j * kMeasureSums + k];
+    const double v = block_sum<kThreads>(acc, red);
+    if (threadIdx.x == 0) tot[k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double P = tot[0];
+    const double ma = tot[5] / P, mb = tot[6] / P;
+    const double saa = tot[7] - P * ma * ma, sbb = tot[8] - P * mb * mb, sab = tot[9] - P * ma * mb;
+    out[0] = tot[1] / P;
+    out[1] = tot[2] / P;
+    out[2] = tot[3] / P;
+    out[3] = sqrt(tot[4] / P);
+    out[4] = sab / sqrt(saa * sbb);
+    out[5] = P;
+    out[6] = ma + shift;
+    out[7] = mb + shift;
+  }
+}
+
+hipError_t launch_measures(const double *z, const double *zh, const uint8_t *known, int64_t n, double shift,
+                           double *part, double *out, hipStream_t s) {
+  const int64_t blocks = (n + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(k_measures, dim3((unsigned)blocks), dim3(kThreads), 0, s, z, zh, known, n, shift, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_measures_final, dim3(1), dim3(kThreads), 0, s, part, blocks, shift, out);
+  return hipGetLastError();
+}
+
 // -------------------------------------------------------------- finalize
 // Per site of each grid: pool the chains' recorded states (mean and
 // variance about each chain's first record), then map back with the

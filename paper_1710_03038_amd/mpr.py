@@ -78,6 +78,7 @@ def lib():
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
         L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_reinit.argtypes = [vp]
+        L.mpr_validation_measures.argtypes = [vp, i32, vp, vp, dp]
         L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_set_graph.argtypes = [vp, i32]
         L.mpr_set_timing.argtypes = [vp, i32]
@@ -273,6 +274,21 @@ class Field:
             off += ny * nx
         return out_h, (out_s if zstd is not None else None), dict(
             records=rep.records, a_eq=a_eq, acc_eq=acc_eq, acc_samp=acc_samp)
+
+    def validation_measures(self, grid, z_true, zhat):
+        """mpr_validation_measures: AAE, ARE, AARE, RASE, R (Sec. 3.3) of
+        zhat against the complete field z_true over the grid's gaps."""
+        torch = self._torch
+        ny, nx, _ = self.shapes[grid]
+        zt = torch.as_tensor(z_true, dtype=torch.float64).to(self.device).contiguous()
+        zh = torch.as_tensor(zhat, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(zt.shape) != (ny, nx) or tuple(zh.shape) != (ny, nx):
+            raise ValueError("z_true and zhat must have the grid's shape")
+        out = np.empty(8)
+        _check(lib().mpr_validation_measures(self.ctx, grid, ctypes.c_void_p(zt.data_ptr()),
+                                             ctypes.c_void_p(zh.data_ptr()), _dptr(out)), self.ctx)
+        return dict(AAE=out[0], ARE=out[1], AARE=out[2], RASE=out[3], R=out[4], P=int(out[5]),
+                    mean_z=out[6], mean_zhat=out[7])
 
     # -- state
     def get_phi(self, grid=0, chain=0):

@@ -15,7 +15,7 @@ from paper_1710_03038_amd import mpr as M
 def test_library_exports_every_declared_symbol():
     L = M.lib()
     names = M.header_functions()
-    assert len(names) == 18
+    assert len(names) == 19
     for n in names:
         assert hasattr(L, n), n
 
@@ -116,6 +116,7 @@ def test_null_context_calls_fail_cleanly():
     assert L.mpr_get_phi(None, 0, 0, None) == M.MPR_E_STATE
     assert L.mpr_reinit(None) == M.MPR_E_STATE
     assert L.mpr_set_graph(None, 1) == M.MPR_E_STATE
+    assert L.mpr_validation_measures(None, 0, None, None, M._dptr(e)) == M.MPR_E_STATE
     assert L.mpr_equilibrate(None, M._dptr(T), 5, 20, 10, 0, None, None, None) == M.MPR_E_STATE
     L.mpr_destroy(None)
     assert b"NULL" in L.mpr_last_error(None)

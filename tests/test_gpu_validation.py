@@ -1,0 +1,77 @@
+"""Validation measures on the GPU (mpr_validation_measures) against the
+oracle, and the whole method (Algorithm 2 with the Savitzky-Golay stop)
+against the validation measures the paper prints for its synthetic
+Whittle-Matern data (tests/golden/paper_mpr_validation.txt)."""
+import os
+
+import numpy as np
+import pytest
+
+import mprgen
+from oracle import mpr as om
+from tests.gpu_util import make_field
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_mpr_validation.txt")
+
+
+def paper_rows():
+    rows = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        kappa, nu, L, case, *vals = line.split()
+        rows[(float(kappa), float(nu), int(L), case)] = dict(zip(("MAAE", "MARE", "MAARE", "MRASE", "MR"),
+                                                                 map(float, vals)))
+    return rows
+
+
+def test_measures_match_oracle():
+    z = mprgen.matern_field(96, 80, 0.2, 0.5, 5, mean=50.0, std=10.0)
+    known = mprgen.mask_random(96, 80, 0.4, 6)
+    zhat = z + np.random.default_rng(7).normal(0.0, 3.0, z.shape)
+    f = make_field([(z, known, 1)], dtype="fp64", seed=1)
+    got = f.validation_measures(0, z, zhat)
+    ref = om.validation_measures(z, zhat, known == 0)
+    assert got["P"] == ref["P"]
+    for k in ("AAE", "ARE", "AARE", "RASE", "R"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-15), k
+    f.close()
+
+
+def _algorithm2(z, known, table, seed, M=100):
+    """Eq. (2), e_s, T-hat by SEM, hot start, equilibration until the
+    Savitzky-Golay slope is >= 0 (n_f = 5, n_fit = 20), M recorded sweeps."""
+    f = make_field([(z, known, 1)], dtype="fp32", seed=seed)
+    e_s, _ = f.specific_energy(0)
+    T, _ = om.match_T(e_s, table[0], table[1])
+    n, _, _ = f.equilibrate(T, n_f=5, n_fit=20, i_max=2000)
+    zh, _, _ = f.fill(T, 0, M, 1)
+    m = f.validation_measures(0, z, zh[0])
+    f.close()
+    return m, n
+
+
+@pytest.mark.parametrize("nu,case", [(0.5, "a"), (0.5, "b"), (0.25, "a")])
+def test_reproduces_the_papers_mpr_validation_measures(nu, case):
+    # L = 256, WM(0.2, nu), random thinning; four configurations here
+    # against the paper's S = 100.  Tolerances cover the spread of the
+    # four-configuration mean (MAAE: ~0.01 between configurations).
+    from paper_1710_03038_amd.etable import load_table
+    table = load_table()
+    want = paper_rows()[(0.2, nu, 256, case)]
+    p = {"a": 0.33, "b": 0.66}[case]
+    ms = []
+    for s in range(4):
+        z = mprgen.matern_field(256, 256, 0.2, nu, 7000 + s, mean=50.0, std=10.0)
+        known = mprgen.mask_random(256, 256, p, 8000 + s)
+        m, n = _algorithm2(z, known, table, 9000 + s)
+        assert n < 200
+        ms.append(m)
+    mean = {k: float(np.mean([m[k] for m in ms])) for k in ("AAE", "ARE", "AARE", "RASE", "R")}
+    assert abs(mean["AAE"] / want["MAAE"] - 1) < 0.015, (mean, want)
+    assert abs(mean["RASE"] / want["MRASE"] - 1) < 0.015, (mean, want)
+    assert abs(100 * mean["AARE"] - want["MAARE"]) < 0.2, (mean, want)
+    assert abs(100 * mean["ARE"] - want["MARE"]) < 0.35, (mean, want)
+    assert abs(100 * mean["R"] - want["MR"]) < 1.0, (mean, want)
