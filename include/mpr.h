@@ -51,6 +51,14 @@ typedef enum {
 
 typedef enum { MPR_FP32 = 0, MPR_FP64 = 1 } mpr_dtype;
 
+/* Pair interaction H_ij of H = -sum H_ij: the MPR energy of Eq. (3),
+ * cos(q (phi_i - phi_j)), or the Gaussian model on the same angles
+ * compared in Sec. 4.4, 1 - (phi_i - phi_j)^2 / (2 pi^2) (q unused).  The
+ * specific energies, the sample specific energy, over-relaxation (about the
+ * neighbours' mean for GMRF) and the Metropolis energy change follow the
+ * chosen interaction; the e(T) table must be that model's. */
+typedef enum { MPR_MODEL_MPR = 0, MPR_MODEL_GMRF = 1 } mpr_model;
+
 /* mpr_sweep flags */
 #define MPR_ADAPT   1u /* apply the a-rule of Algorithm 2, step 4.2 */
 #define MPR_TRACE_E 2u /* record the specific energy e of Eq. (5) after every sweep */
@@ -83,6 +91,8 @@ typedef struct {
   int32_t sweeps_per_pass;/* sweeps fused per HBM pass, 1..16; 0 = library choice */
   int32_t tile_x, tile_y; /* interior tile of one workgroup (even, 8..192); 0 = library choice */
   uint64_t seed;          /* Philox4x32-10 key: (seed mod 2^32, seed >> 32) */
+  int32_t model;          /* pair interaction: MPR_MODEL_MPR (Eq. 3) or MPR_MODEL_GMRF (Sec. 4.4) */
+  int32_t reserved;       /* must be 0 */
 } mpr_params;
 
 typedef struct {
@@ -95,7 +105,7 @@ typedef struct {
 
 /* Fill *p with the paper's defaults (Sec. 2.5): q = 0.5, A_targ = 0.3,
  * k_a = 3, adapt_every = 1, a_sample_keep = 0, FP32, library-chosen tiles,
- * seed 0. */
+ * seed 0, the MPR interaction. */
 void mpr_default_params(mpr_params *p);
 
 /*

@@ -27,22 +27,23 @@ from . import mpr
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "etable_L32.csv")
+GMRF_PATH = os.path.join(HERE, "etable_gmrf_L32.csv")
 
 
 def default_temperatures():
     return np.logspace(-5.0, math.log10(3.0), 46)
 
 
-def table_point(T, L=32, chains=8, n_eq=300, n_meas=900, q=0.5, seed=7, grid=0):
+def table_point(T, L=32, chains=8, n_eq=300, n_meas=900, q=0.5, seed=7, grid=0, model=mpr.MPR):
     known = np.zeros((L, L), dtype=bool)
     rng = np.random.Generator(np.random.PCG64(seed + grid))
     phi = np.broadcast_to(rng.uniform(0, 2 * math.pi, chains)[:, None, None],
                           (chains, L, L)).copy()
     a0 = max(1.0, 0.3 / math.sqrt(T))
     ids = np.arange(chains)
-    phi, a, _, _ = mpr.run_sweeps(phi, known, T, a0, q, seed, 0, n_eq, ids, grid, adapt=True)
+    phi, a, _, _ = mpr.run_sweeps(phi, known, T, a0, q, seed, 0, n_eq, ids, grid, adapt=True, model=model)
     _, _, _, e = mpr.run_sweeps(phi, known, T, a, q, seed, n_eq, n_meas, ids, grid,
-                                trace_energy=True)
+                                trace_energy=True, model=model)
     per_chain = e.mean(axis=0)
     return float(per_chain.mean()), float(per_chain.std(ddof=1) / math.sqrt(chains))
 
@@ -75,8 +76,10 @@ def save_table(path, T, e, err, header):
             f.write(f"{t:.17g},{v:.17g},{s:.6g}\n")
 
 
-def load_table(path=DEFAULT_PATH):
-    """Return (T, e, e_stderr) arrays of a table file."""
+def load_table(path=None, model=mpr.MPR):
+    """Return (T, e, e_stderr) arrays of a table file (default: the model's)."""
+    if path is None:
+        path = GMRF_PATH if model == mpr.GMRF else DEFAULT_PATH
     rows = []
     with open(path) as f:
         for line in f:
@@ -88,15 +91,20 @@ def load_table(path=DEFAULT_PATH):
 
 
 if __name__ == "__main__":
+    # python -m oracle.etable [processes] [mpr|gmrf]
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     procs = int(sys.argv[1]) if len(sys.argv) > 1 else 8
-    kw = dict(L=32, chains=8, n_eq=300, n_meas=900, q=0.5, seed=7)
+    model = sys.argv[2] if len(sys.argv) > 2 else mpr.MPR
+    kw = dict(L=32, chains=8, n_eq=300, n_meas=2400 if model == mpr.GMRF else 900, q=0.5, seed=7, model=model)
     T, e, err = build_table(processes=procs, **kw)
     order_ok = bool(np.all(np.diff(e) > 0))
-    save_table(DEFAULT_PATH, T, e, err, [
-        "Equilibrium MPR specific energy e(T) = <H>/N_GP, q = 1/2, open boundaries,",
+    path = GMRF_PATH if model == mpr.GMRF else DEFAULT_PATH
+    what = ("Equilibrium GMRF specific energy e(T) = <H>/N_GP, H_ij = 1 - dphi^2/(2 pi^2), open boundaries,"
+            if model == mpr.GMRF else "Equilibrium MPR specific energy e(T) = <H>/N_GP, q = 1/2, open boundaries,")
+    save_table(path, T, e, err, [
+        what,
         "from unconditional CPU-oracle chains (oracle/etable.py): "
-        + ", ".join(f"{k}={v}" for k, v in kw.items()),
+        + ", ".join(f"{k}={v}" for k, v in kw.items() if k != "model"),
         f"strictly increasing in T: {order_ok}",
     ])
-    print("wrote", DEFAULT_PATH, "monotone:", order_ok)
+    print("wrote", path, "monotone:", order_ok)

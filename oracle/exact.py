@@ -146,3 +146,20 @@ def uniform_gap_sample_cos(q, phi_j):
     """E[cos q(phi - phi_j)] for phi ~ U[0, 2*pi) and a fixed phi_j:
     (sin(q (2*pi - phi_j)) + sin(q phi_j)) / (2*pi*q)."""
     return (math.sin(q * (TWO_PI - phi_j)) + math.sin(q * phi_j)) / (TWO_PI * q)
+
+
+def gmrf_single_site_bins(nbr_angles, beta, nbins=8):
+    """Bin probabilities of one free site of the GMRF variant (Sec. 4.4)
+    whose n neighbours are frozen at ``nbr_angles``: the density
+    prod_j exp(-beta (phi - phi_j)^2 / (2 pi^2)) on [0, 2 pi) is a normal
+    density with mean m = mean(phi_j) and variance pi^2 / (beta n),
+    truncated to [0, 2 pi); its bin masses follow from the error function.
+    beta = 0 gives the uniform law."""
+    edges = np.linspace(0.0, TWO_PI, nbins + 1)
+    if beta == 0.0:
+        return np.diff(edges) / TWO_PI
+    m = float(np.mean(nbr_angles))
+    sd = math.pi / math.sqrt(beta * len(nbr_angles))
+    cdf = np.array([0.5 * math.erfc(-(e - m) / (sd * math.sqrt(2.0))) for e in edges])
+    mass = np.diff(cdf)
+    return mass / mass.sum()

@@ -42,6 +42,11 @@ Readings of points the paper leaves open (each also used by the library):
   i is a multiple of n_f.  Chains of a batch sweep in lock-step until every
   chain has passed a check.
 
+The GMRF variant (Sec. 4.4) replaces the pair interaction by
+H_ij = 1 - dphi^2 / (2 pi^2) on the same non-periodic angles; its
+over-relaxation reflects phi about the mean of its neighbours, kept only
+inside [0, 2 pi), and everything else is unchanged.
+
 Random stream (a definition of this project): key = (seed mod 2^32,
 seed >> 32); counter = (pair, sweep, chain, grid) with
 pair = y * ceil(nx/2) + x//2.  A site with even x uses words (w0 -> u,
@@ -56,6 +61,11 @@ from .philox import philox4x32, unit_float
 
 TWO_PI = 2.0 * math.pi
 HOT_START_SWEEP = 0xFFFFFFFF
+
+# Pair interactions (Sec. 4.4): the MPR energy of Eq. (3), H_ij = cos(q dphi),
+# or the Gaussian (GMRF) one, H_ij = 1 - dphi^2 / (2 pi^2); H = -sum H_ij.
+MPR, GMRF = "mpr", "gmrf"
+TWO_PI_SQ = 2.0 * math.pi * math.pi
 
 
 class OracleError(ValueError):
@@ -141,11 +151,25 @@ def _pairs(a):
     return ((a[..., :, :-1], a[..., :, 1:]), (a[..., :-1, :], a[..., 1:, :]))
 
 
-def energy(phi, q):
-    """Eq. (3) with J = 1: H = -sum over pairs cos(q (phi_i - phi_j))."""
+def _pair_eps(a, b, q, model):
+    """1 - H_ij of a pair: 2 sin^2(q (a - b) / 2) = 1 - cos(q (a - b)) for
+    MPR (the half-angle form keeps its relative precision for small
+    differences), (a - b)^2 / (2 pi^2) for GMRF."""
+    if model == GMRF:
+        d = a - b
+        return d * d / TWO_PI_SQ
+    return 2.0 * np.sin(0.5 * q * (a - b)) ** 2
+
+
+def energy(phi, q, model=MPR):
+    """Eq. (3) with J = 1: H = -sum over pairs H_ij, with H_ij =
+    cos(q (phi_i - phi_j)) (MPR) or 1 - (phi_i - phi_j)^2 / (2 pi^2) (GMRF)."""
     tot = 0.0
     for a, b in _pairs(np.asarray(phi, dtype=np.float64)):
-        tot = tot - np.cos(q * (a - b)).sum(axis=(-2, -1))
+        if model == GMRF:
+            tot = tot + ((a - b) ** 2 / TWO_PI_SQ - 1.0).sum(axis=(-2, -1))
+        else:
+            tot = tot - np.cos(q * (a - b)).sum(axis=(-2, -1))
     return tot
 
 
@@ -154,23 +178,24 @@ def n_pairs(ny, nx):
     return ny * (nx - 1) + nx * (ny - 1)
 
 
-def state_specific_energy(phi, q):
+def state_specific_energy(phi, q, model=MPR):
     """Eq. (5) for one state: e = H / N_GP.  Returns (e, eps) with eps = 1 + e.
 
-    eps is summed as 2 sin^2(q dphi / 2) (equal to 1 - cos(q dphi)), which
-    keeps its relative precision when the field is nearly uniform.
+    eps is summed as the pairs' 1 - H_ij (see _pair_eps), which keeps its
+    relative precision when the field is nearly uniform.
     """
     phi = np.asarray(phi, dtype=np.float64)
     ny, nx = phi.shape[-2:]
     s = 0.0
     for a, b in _pairs(phi):
-        s = s + (2.0 * np.sin(0.5 * q * (a - b)) ** 2).sum(axis=(-2, -1))
+        s = s + _pair_eps(a, b, q, model).sum(axis=(-2, -1))
     eps = s / n_pairs(ny, nx)
     return eps - 1.0, eps
 
 
-def sample_specific_energy(phi, known, q):
-    """Eq. (4): mean of -cos(q dphi) over unordered sample-sample pairs.
+def sample_specific_energy(phi, known, q, model=MPR):
+    """Eq. (4): mean of -H_ij over unordered sample-sample pairs (for GMRF
+    the sample specific energy of Sec. 4.4, the mean of dphi^2 / (2 pi^2) - 1).
 
     Returns (e_s, eps_s, N_SP).  Raises OracleError when N_SP = 0.
     """
@@ -180,7 +205,7 @@ def sample_specific_energy(phi, known, q):
     n = 0
     for (a, b), (ka, kb) in zip(_pairs(phi), _pairs(known)):
         both = ka & kb
-        s += (2.0 * np.sin(0.5 * q * (a[both] - b[both])) ** 2).sum()
+        s += _pair_eps(a[both], b[both], q, model).sum()
         n += int(both.sum())
     if n == 0:
         raise OracleError("no sample-sample pairs")
@@ -207,9 +232,18 @@ def _neighbours(phi):
     return [pad[..., 1:-1, :-2], pad[..., 1:-1, 2:], pad[..., :-2, 1:-1], pad[..., 2:, 1:-1]]
 
 
-def over_relax(phi, nbrs, q):
+def over_relax(phi, nbrs, q, model=MPR):
     """Energy-conserving reflection of each spin about its local field, Eq. (6)
-    in the q-aware reading.  ``nbrs`` are the neighbour angles (NaN = none)."""
+    in the q-aware reading.  ``nbrs`` are the neighbour angles (NaN = none).
+    For GMRF the site's energy is a parabola in phi about the neighbours'
+    mean m, and the reflection is 2 m - phi, kept only inside [0, 2 pi)."""
+    if model == GMRF:
+        cnt = sum((~np.isnan(n)).astype(np.float64) for n in nbrs)
+        tot = sum(np.nan_to_num(n) for n in nbrs)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            star = 2.0 * tot / cnt - phi
+        ok = (cnt > 0) & (star >= 0.0) & (star < TWO_PI)
+        return np.where(ok, star, phi)
     hx = sum(np.where(np.isnan(n), 0.0, np.cos(q * np.nan_to_num(n))) for n in nbrs)
     hy = sum(np.where(np.isnan(n), 0.0, np.sin(q * np.nan_to_num(n))) for n in nbrs)
     psi = np.arctan2(hy, hx)
@@ -221,13 +255,15 @@ def over_relax(phi, nbrs, q):
     return np.where(hx * hx + hy * hy <= 1e-24, phi, out)
 
 
-def site_energy(phi, nbrs, q):
-    """Energy of the bonds of one site: -sum_j cos(q (phi - phi_j))."""
+def site_energy(phi, nbrs, q, model=MPR):
+    """Energy of the bonds of one site: -sum_j H_ij."""
+    if model == GMRF:
+        return sum(np.where(np.isnan(n), 0.0, (phi - np.nan_to_num(n)) ** 2 / TWO_PI_SQ - 1.0) for n in nbrs)
     return -sum(np.where(np.isnan(n), 0.0, np.cos(q * (phi - np.nan_to_num(n)))) for n in nbrs)
 
 
 def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), npair=None,
-                 or_step=True):
+                 or_step=True, model=MPR):
     """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
 
     phi: (C, ny, nx) float64 current states (not modified).
@@ -245,6 +281,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
       sites far enough from them.
     or_step: False skips step 1 (no over-relaxation): the restricted
       Metropolis update alone, or standard Metropolis with a = 1 (Sec. 2.4).
+    model: MPR or GMRF pair interactions (Sec. 4.4).
     Returns (new phi, accepted count per chain).
     """
     phi = np.array(phi, dtype=np.float64, copy=True)
@@ -260,18 +297,23 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     for colour in (0, 1):
         update = (((xx + yy) % 2) == colour) & ~known
         nbrs = _neighbours(phi)
-        phi1 = over_relax(phi, nbrs, q) if or_step else phi  # step 1
+        phi1 = over_relax(phi, nbrs, q, model) if or_step else phi  # step 1
         phi2 = wrap(phi1 + alpha * (u - 0.5))                # steps 2-3
-        dH = site_energy(phi2, nbrs, q) - site_energy(phi1, nbrs, q)   # step 4
+        dH = site_energy(phi2, nbrs, q, model) - site_energy(phi1, nbrs, q, model)   # step 4
         with np.errstate(invalid="ignore", over="ignore"):
             boltz = np.exp(-beta * dH)                       # step 5
         accept = (dH <= 0.0) | (r < boltz)                   # step 6
         if margins is not None:
             sel = np.broadcast_to(update[None], phi.shape)
             ap = np.where(dH <= 0.0, 1.0, np.nan_to_num(boltz))
-            hx = sum(np.where(np.isnan(n), 0.0, np.cos(q * np.nan_to_num(n))) for n in nbrs)
-            hy = sum(np.where(np.isnan(n), 0.0, np.sin(q * np.nan_to_num(n))) for n in nbrs)
-            star = (2.0 * np.arctan2(hy, hx) - q * phi) / q
+            if model == GMRF:
+                cnt = sum((~np.isnan(n)).astype(np.float64) for n in nbrs)
+                with np.errstate(invalid="ignore", divide="ignore"):
+                    star = 2.0 * sum(np.nan_to_num(n) for n in nbrs) / cnt - phi
+            else:
+                hx = sum(np.where(np.isnan(n), 0.0, np.cos(q * np.nan_to_num(n))) for n in nbrs)
+                hy = sum(np.where(np.isnan(n), 0.0, np.sin(q * np.nan_to_num(n))) for n in nbrs)
+                star = (2.0 * np.arctan2(hy, hx) - q * phi) / q
             raw = phi1 + alpha * (u - 0.5)
             margins["accept"] = np.where(sel, np.abs(r - ap), margins["accept"])
             if or_step:
@@ -284,7 +326,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     return phi, accepted
 
 
-def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, or_step=True):
+def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, or_step=True, model=MPR):
     """Algorithm 1 for one chain as a plain per-site loop (small grids only).
 
     Same checkerboard order and random stream as ``hybrid_sweep``; written
@@ -307,18 +349,26 @@ def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, o
                 nb = [phi[yy][xx] for yy, xx in ((y, x - 1), (y, x + 1), (y - 1, x), (y + 1, x))
                       if 0 <= yy < ny and 0 <= xx < nx]
                 cur = phi[y][x]
-                hx = sum(math.cos(q * v) for v in nb)
-                hy = sum(math.sin(q * v) for v in nb)
-                if not or_step or hx * hx + hy * hy <= 1e-24:
+                if model == GMRF:
                     p1 = cur
-                else:
-                    star = (2.0 * math.atan2(hy, hx) - q * cur) / q
-                    if q == 1.0:
-                        p1 = float(wrap(np.float64(star)))
-                    else:
+                    if or_step and nb:
+                        star = 2.0 * sum(nb) / len(nb) - cur
                         p1 = star if 0.0 <= star < TWO_PI else cur
-                p2 = float(wrap(np.float64(p1 + alpha * (u - 0.5))))
-                dH = -sum(math.cos(q * (p2 - v)) - math.cos(q * (p1 - v)) for v in nb)
+                    p2 = float(wrap(np.float64(p1 + alpha * (u - 0.5))))
+                    dH = sum((p2 - v) ** 2 - (p1 - v) ** 2 for v in nb) / TWO_PI_SQ
+                else:
+                    hx = sum(math.cos(q * v) for v in nb)
+                    hy = sum(math.sin(q * v) for v in nb)
+                    if not or_step or hx * hx + hy * hy <= 1e-24:
+                        p1 = cur
+                    else:
+                        star = (2.0 * math.atan2(hy, hx) - q * cur) / q
+                        if q == 1.0:
+                            p1 = float(wrap(np.float64(star)))
+                        else:
+                            p1 = star if 0.0 <= star < TWO_PI else cur
+                    p2 = float(wrap(np.float64(p1 + alpha * (u - 0.5))))
+                    dH = -sum(math.cos(q * (p2 - v)) - math.cos(q * (p1 - v)) for v in nb)
                 if dH <= 0.0:
                     ok = True
                 elif beta == math.inf:
@@ -340,7 +390,8 @@ def adapt_a(a, acceptance, i, a_targ=0.3, k_a=3.0):
 
 
 def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
-               adapt=False, adapt_every=1, a_targ=0.3, k_a=3.0, trace_energy=False, or_step=True, window=None):
+               adapt=False, adapt_every=1, a_targ=0.3, k_a=3.0, trace_energy=False, or_step=True, window=None,
+               model=MPR):
     """Advance C chains of one grid by ``n_sweeps`` hybrid sweeps.
 
     Returns (phi, a, acceptance per sweep (n, C), specific energy per sweep
@@ -362,11 +413,11 @@ def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
         window = np.zeros(C)
     for s in range(n_sweeps):
         i = first_sweep + s
-        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid, or_step=or_step)
+        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid, or_step=or_step, model=model)
         A = acc / n_gap if n_gap > 0 else np.ones(C)
         acc_trace[s] = A
         if trace_energy:
-            e_trace[s] = state_specific_energy(phi, q)[0]
+            e_trace[s] = state_specific_energy(phi, q, model)[0]
         if adapt:
             window += A
             if (i + 1) % adapt_every == 0:
@@ -376,7 +427,7 @@ def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
 
 
 def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
-         a_targ=0.3, k_a=3.0, adapt_every=1, a_sample_keep=False):
+         a_targ=0.3, k_a=3.0, adapt_every=1, a_sample_keep=False, model=MPR):
     """Algorithm 2 with fixed sweep counts (no Savitzky-Golay stop).
 
     Hot start, ``n_eq`` equilibration sweeps with the a-rule, then
@@ -391,7 +442,7 @@ def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
     phi = hot_start(phi_s, known, seed, chain_ids, grid)
     a = np.ones(chains)
     phi, a, acc_eq, _ = run_sweeps(phi, known, T, a, q, seed, 0, n_eq, chain_ids, grid,
-                                   adapt=True, adapt_every=adapt_every, a_targ=a_targ, k_a=k_a)
+                                   adapt=True, adapt_every=adapt_every, a_targ=a_targ, k_a=k_a, model=model)
     a_eq = a.copy()
     if not a_sample_keep:
         a = np.ones(chains)
@@ -400,7 +451,7 @@ def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
     m = 0
     acc_samp = []
     for j in range(n_samp):
-        phi, a, acc, _ = run_sweeps(phi, known, T, a, q, seed, n_eq + j, 1, chain_ids, grid)
+        phi, a, acc, _ = run_sweeps(phi, known, T, a, q, seed, n_eq + j, 1, chain_ids, grid, model=model)
         acc_samp.append(acc[0])
         if (j + 1) % stride == 0:
             s1 += phi.sum(axis=0)
@@ -455,7 +506,7 @@ def sg_stop_index(e_after, n_f, n_fit, i_max):
 
 
 def equilibrate(phi, known, T, a, q, seed, first_sweep, chains, grid, n_f=5, n_fit=20, i_max=1000,
-                adapt=True, or_step=True, adapt_every=1, a_targ=0.3, k_a=3.0):
+                adapt=True, or_step=True, adapt_every=1, a_targ=0.3, k_a=3.0, model=MPR):
     """Algorithm 2, step 4, for C chains of one grid swept in lock-step:
     hybrid sweeps (4.1), the a-rule (4.2, with ``adapt``), the specific
     energy after every sweep (4.3) and the Savitzky-Golay slope check of
@@ -475,7 +526,7 @@ def equilibrate(phi, known, T, a, q, seed, first_sweep, chains, grid, n_f=5, n_f
     while i <= i_max and np.any(eq_at < 0):
         phi, a, acc, e = run_sweeps(phi, known, T, a, q, seed, first_sweep + i, 1, chains, grid, adapt=adapt,
                                     adapt_every=adapt_every, a_targ=a_targ, k_a=k_a, trace_energy=True,
-                                    or_step=or_step, window=window)
+                                    or_step=or_step, window=window, model=model)
         e_hist.append(e[0])
         acc_hist.append(acc[0])
         if i >= n_fit and i % n_f == 0:

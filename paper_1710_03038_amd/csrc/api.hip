@@ -142,6 +142,9 @@ mpr_status check_params(const mpr_params *p) {
   for (int t : {p->tile_x, p->tile_y})
     if (t != 0 && (t < 8 || t > kMaxTile || (t & 1)))
       return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 192]");
+  if (p->model != MPR_MODEL_MPR && p->model != MPR_MODEL_GMRF)
+    return fail(nullptr, MPR_E_ARG, "model must be MPR_MODEL_MPR or MPR_MODEL_GMRF");
+  if (p->reserved != 0) return fail(nullptr, MPR_E_ARG, "params.reserved must be 0");
   return MPR_OK;
 }
 
@@ -326,6 +329,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.lds_w = w;
   A.lds_h = h;
   A.q_is_one = c->p.q == 1.0;
+  A.gmrf = c->p.model == MPR_MODEL_GMRF ? 1 : 0;
   A.or_step = or_step ? 1 : 0;
   A.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
   A.key1 = (uint32_t)(c->p.seed >> 32);
@@ -464,10 +468,10 @@ mpr_status reduce_energy(mpr_ctx *c, int what, std::vector<double> &out) {
   const int64_t blocks = what ? c->plan.n_cblocks : c->plan.n_sblocks;
   if (c->p.dtype == MPR_FP64) {
     HIP_TRY(c, launch_energy<double>(c->v.gd, c->n_grids, blocks, what, (const double *)c->v.st[c->cur], c->p.q,
-                                     c->v.part, c->stream));
+                                     c->p.model, c->v.part, c->stream));
   } else {
     HIP_TRY(c, launch_energy<float>(c->v.gd, c->n_grids, blocks, what, (const float *)c->v.st[c->cur],
-                                    (float)c->p.q, c->v.part, c->stream));
+                                    (float)c->p.q, c->p.model, c->v.part, c->stream));
   }
   HIP_TRY(c, launch_energy_final(c->v.gd, c->n_grids, what, units, c->v.part, c->v.out, c->stream));
   out.resize((size_t)units * 2);
@@ -596,6 +600,7 @@ void mpr_default_params(mpr_params *p) {
   p->tile_x = 0;
   p->tile_y = 0;
   p->seed = 0;
+  p->model = MPR_MODEL_MPR;
 }
 
 const char *mpr_last_error(const mpr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_thread_err.c_str(); }

@@ -46,6 +46,11 @@ struct PassEnd {
   const double *a_in, *win_in;     // a and a-rule window before that pass
 };
 
+// Pair interaction of the sweep kernel, a template parameter: the MPR
+// energy of Eq. (3) with q < 1 or q = 1, or the Gaussian (GMRF) variant
+// H_ij = 1 - dphi^2 / (2 pi^2) of Sec. 4.4.
+enum SweepModel : int { kMprQ = 0, kMprQ1 = 1, kGmrf = 2 };
+
 template <typename P>
 struct SweepArgs {
   const GridDesc *grids;
@@ -54,6 +59,7 @@ struct SweepArgs {
   int32_t nsw;                     // sweeps in this pass
   int32_t lds_w, lds_h;            // LDS extent in sites (lds_w even)
   int32_t q_is_one;
+  int32_t gmrf;                    // 1: GMRF pair interaction (mpr_params.model)
   int32_t or_step;                 // 1: Algorithm 1, step 1 (over-relaxation); 0: Metropolis only
   uint32_t key0, key1;
   uint32_t sweep0;                 // global index of the pass's first sweep
@@ -107,7 +113,7 @@ hipError_t launch_init(const GridDesc *g, int n_grids, int64_t n_blocks, const d
                        const uint8_t *const *known, P *s0, P *s1, P q_unused, uint32_t k0, uint32_t k1,
                        hipStream_t s);
 template <typename P>
-hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q,
+hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q, int gmrf,
                          double *part, hipStream_t s);
 hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
                                double *out, hipStream_t s);

@@ -72,6 +72,7 @@ template <> struct Prec<float> {
   static constexpr float two_pi = 6.28318530717958647692f;  // rounds up: 6.2831855f
   static constexpr float below_two_pi = 6.2831850f;         // largest float < two_pi
   static constexpr float tiny_h2 = 1e-12f;
+  static constexpr float inv_2pi2 = 0.0506605918211688857f;  // 1 / (2 pi^2)
   __device__ static float sin_(float x) { return fm::sin(x); }
   __device__ static float sin_dh_(float x) { return fm::sin_hw(x); }
   __device__ static void sincos_(float x, float *s, float *c) { fm::sincos(x, s, c); }
@@ -86,6 +87,7 @@ template <> struct Prec<double> {
   static constexpr double two_pi = 6.28318530717958647692;
   static constexpr double below_two_pi = 6.2831853071795853;  // nextafter(2*pi, 0)
   static constexpr double tiny_h2 = 1e-24;
+  static constexpr double inv_2pi2 = 0.0506605918211688857;
   __device__ static double sin_(double x) { return ::sin(x); }
   __device__ static double sin_dh_(double x) { return ::sin(x); }
   __device__ static void sincos_(double x, double *s, double *c) { ::sincos(x, s, c); }
@@ -205,17 +207,68 @@ template <typename P> struct UpdateCtx {
   P *pc;               // this colour's angle plane
   V2 *cc;              // this colour's (cos, sin) plane
   const V2 *cn;        // the other colour's (cos, sin) plane
+  const P *pn;         // the other colour's angle plane
   int Ly, Lx, P2, pbase, npair;
   uint32_t sweep, cid, gid, k0, k1;
   P q, inv_q, alpha, beta;
   bool or_step;        // over-relaxation on
 };
 
+// Algorithm 1 with the GMRF pair interaction for the K plan entries fs[]
+// of one thread.  A site's energy is a parabola in its angle about the mean
+// m = S/n of its n in-grid neighbours (NaN in the angle plane marks none),
+// so over-relaxation reflects about m, kept inside [0, 2 pi), and
+// dH = ((p2 - p1) (n (p2 + p1) - 2 S)) / (2 pi^2).
+template <typename P, int K>
+__device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
+                                                      const bool (&cnt)[K]) {
+  int o[K];
+  P phi[K], sum[K], n[K], u[K], rr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t e = U.lc[fs[k]];
+    const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
+    const int j = lx >> 1, par = lx & 1;
+    o[k] = ly * U.P2 + j;
+    phi[k] = U.pc[o[k]];
+    const P nb[4] = {U.pn[o[k] - 1 + par], U.pn[o[k] + par], U.pn[o[k] - U.P2], U.pn[o[k] + U.P2]};
+    sum[k] = P(0);
+    n[k] = P(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bool in = !__builtin_isnan(nb[m]);
+      sum[k] += in ? fabs(nb[m]) : P(0);
+      n[k] += in ? P(1) : P(0);
+    }
+    uint32_t w[4];
+    philox4x32_10((uint32_t)(U.pbase + ly * U.npair + j), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
+    u[k] = unit<P>(par ? w[2] : w[0]);
+    rr[k] = unit<P>(par ? w[3] : w[1]);
+  }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    P p1 = phi[k];
+    if (U.or_step && n[k] > P(0)) {
+      const P star = P(2) * sum[k] / n[k] - phi[k];
+      if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+    }
+    const P p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
+    const P dH = (p2 - p1) * (n[k] * (p2 + p1) - P(2) * sum[k]) * Prec<P>::inv_2pi2;
+    const bool ok = (dH <= P(0)) || (rr[k] < Prec<P>::exp_(-U.beta * dH));
+    U.pc[o[k]] = ok ? p2 : p1;
+    acc += (ok && cnt[k]) ? 1u : 0u;
+  }
+  return acc;
+}
+
 // Algorithm 1 for the K plan entries fs[] of one thread, interleaved step
 // by step; returns the accepted updates among those with cnt[] set.
-template <typename P, bool QONE, int K>
+template <typename P, int MODEL, int K>
 __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
                                                  const bool (&cnt)[K]) {
+  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, K>(U, fs, cnt);
+  constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
   const P q = U.q;
   int o[K];
@@ -279,8 +332,9 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
 // 2*nsw + 1 sites covers hs = 0), so the interior is exact after the last
 // half-sweep.  When the energy of interior pairs is traced, every D is one
 // larger, so that the interior plus one ring is exact after each sweep.
-template <typename P, int NT, bool QONE>
+template <typename P, int NT, int MODEL>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
+  constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_d[NT / 64];
@@ -360,14 +414,19 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
         if (o[k] < 0) continue;
-        P s_ = P(0), c_ = P(0), val = -P(0);
-        if (in[k]) {
-          val = v[k];
-          if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
-          else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+        if constexpr (MODEL == kGmrf) {
+          // angles only; NaN marks a site outside the grid or the halo
+          ph[o[k]] = in[k] ? v[k] : P(__builtin_nan(""));
+        } else {
+          P s_ = P(0), c_ = P(0), val = -P(0);
+          if (in[k]) {
+            val = v[k];
+            if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
+            else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+          }
+          ph[o[k]] = val;
+          cs[o[k]] = V2{c_, s_};
         }
-        ph[o[k]] = val;
-        cs[o[k]] = V2{c_, s_};
       }
 #pragma unroll
       for (int k = 0; k < kPlanStage; ++k) {
@@ -406,8 +465,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       P *pc = ph + c * plane;
       V2 *cc = cs + c * plane;
       const V2 *cn = cs + (c ^ 1) * plane;
-      const UpdateCtx<P> U{lc,  pc,  cc,  cn, Ly, Lx,    P2,    pbase, npair,        sweep,
-                           cid, gid, k0, k1, q,  inv_q, alpha, beta,  A.or_step != 0};
+      const UpdateCtx<P> U{lc,  pc,    cc,    cn,   ph + (c ^ 1) * plane, Ly, Lx, P2, pbase, npair,
+                           sweep, cid, gid, k0, k1, q, inv_q, alpha, beta, A.or_step != 0};
       // In FP32, two independent updates per thread and iteration (items f
       // and f + NT) give the scheduler two dependency chains to interleave;
       // a lane without a second item repeats its first, whose identical
@@ -419,11 +478,11 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         if (kIlp == 2 && __any(f2 < n)) {
           const uint32_t fs[2] = {f, f2 < n ? f2 : f};
           const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
-          acc += update_sites<P, QONE, 2>(U, fs, cnt);
+          acc += update_sites<P, MODEL, 2>(U, fs, cnt);
         } else {
           const uint32_t fs[1] = {f};
           const bool cnt[1] = {f < n_inner};
-          acc += update_sites<P, QONE, 1>(U, fs, cnt);
+          acc += update_sites<P, MODEL, 1>(U, fs, cnt);
         }
       }
       __syncthreads();
@@ -444,16 +503,14 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         const int lx = gx - ox, ly = gy - oy;
         const int col = (gx + gy) & 1;
         const P v = fabs(ph[col * plane + ly * P2 + (lx >> 1)]);
-        if (gx + 1 < nx) {
-          const P d = v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]);
+        // 1 - H_ij: 2 sin^2(q d / 2) (MPR), d^2 / (2 pi^2) (GMRF)
+        auto pair = [&](P d) {
+          if constexpr (MODEL == kGmrf) return d * d * Prec<P>::inv_2pi2;
           const P sn = Prec<P>::sin_(q * d * P(0.5));
-          e += P(2) * sn * sn;
-        }
-        if (gy + 1 < ny) {
-          const P d = v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]);
-          const P sn = Prec<P>::sin_(q * d * P(0.5));
-          e += P(2) * sn * sn;
-        }
+          return P(2) * sn * sn;
+        };
+        if (gx + 1 < nx) e += pair(v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]));
+        if (gy + 1 < ny) e += pair(v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]));
       }
       const double et = block_sum<NT>((double)e, red_d);
       if (threadIdx.x == 0) atomicAdd(&A.energy[(int64_t)gchain * kMaxPass + s], et);
@@ -585,20 +642,21 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
   apply_pass_end(A, A.grids[lo], ch, true);
 }
 
-template <typename P, bool QONE>
+template <typename P, int MODEL>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   switch (threads) {
-    case 256: hipLaunchKernelGGL((k_sweep<P, 256, QONE>), dim3((unsigned)n_items), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_sweep<P, 512, QONE>), dim3((unsigned)n_items), dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_sweep<P, 1024, QONE>), dim3((unsigned)n_items), dim3(1024), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL>), dim3((unsigned)n_items), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL>), dim3((unsigned)n_items), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL>), dim3((unsigned)n_items), dim3(1024), lds, s, a); break;
   }
 }
 
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-  if (a.q_is_one) launch_sweep_q<P, true>(a, threads, n_items, lds, s);
-  else launch_sweep_q<P, false>(a, threads, n_items, lds, s);
+  if (a.gmrf) launch_sweep_q<P, kGmrf>(a, threads, n_items, lds, s);
+  else if (a.q_is_one) launch_sweep_q<P, kMprQ1>(a, threads, n_items, lds, s);
+  else launch_sweep_q<P, kMprQ>(a, threads, n_items, lds, s);
   return hipGetLastError();
 }
 
@@ -606,9 +664,9 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
-    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, false>)); break;
-    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, false>)); break;
-    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, false>)); break;
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ>)); break;
     default: break;
   }
   return e == hipSuccess ? at.maxThreadsPerBlock : 0;
@@ -774,9 +832,17 @@ template hipError_t launch_init<double>(const GridDesc *, int, int64_t, const do
 // what = 1: Eq. (5) per chain over all pairs.  Each site owns its right and
 // lower pair; terms 2 sin^2(q dphi / 2) are summed per thread in P and per
 // workgroup in FP64 -> part[b*2] = sum, part[b*2+1] = #pairs.
+// 1 - H_ij of one pair with angle difference d: 2 sin^2(q d / 2) for MPR,
+// d^2 / (2 pi^2) for the GMRF variant.
+template <typename P> __device__ __forceinline__ P pair_eps(P d, P q, int gmrf) {
+  if (gmrf) return d * d * Prec<P>::inv_2pi2;
+  const P sn = Prec<P>::sin_(q * d * P(0.5));
+  return P(2) * sn * sn;
+}
+
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
-    k_energy(const GridDesc *grids, int n_grids, int what, const P *state, P q, double *part) {
+    k_energy(const GridDesc *grids, int n_grids, int what, const P *state, P q, int gmrf, double *part) {
   __shared__ double red[kThreads / 64];
   const int64_t b = blockIdx.x;
   const int gi = find_by(grids, n_grids, b, what ? &GridDesc::cb_begin : &GridDesc::sb_begin);
@@ -797,16 +863,14 @@ __global__ void __launch_bounds__(kThreads)
     if (x + 1 < nx) {
       const P w = st[i + 1];
       if (what == 1 || signbit(w)) {
-        const P sn = Prec<P>::sin_(q * (fabs(v) - fabs(w)) * P(0.5));
-        e += P(2) * sn * sn;
+        e += pair_eps(fabs(v) - fabs(w), q, gmrf);
         cnt += 1.0;
       }
     }
     if (y + 1 < G.ny) {
       const P w = st[i + nx];
       if (what == 1 || signbit(w)) {
-        const P sn = Prec<P>::sin_(q * (fabs(v) - fabs(w)) * P(0.5));
-        e += P(2) * sn * sn;
+        e += pair_eps(fabs(v) - fabs(w), q, gmrf);
         cnt += 1.0;
       }
     }
@@ -854,14 +918,15 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 template <typename P>
-hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q,
+hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q, int gmrf,
                          double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, what, state, q, part);
+  hipLaunchKernelGGL(k_energy<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, what, state, q, gmrf,
+                     part);
   return hipGetLastError();
 }
-template hipError_t launch_energy<float>(const GridDesc *, int, int64_t, int, const float *, float, double *,
+template hipError_t launch_energy<float>(const GridDesc *, int, int64_t, int, const float *, float, int, double *,
                                          hipStream_t);
-template hipError_t launch_energy<double>(const GridDesc *, int, int64_t, int, const double *, double, double *,
+template hipError_t launch_energy<double>(const GridDesc *, int, int64_t, int, const double *, double, int, double *,
                                           hipStream_t);
 hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
                                double *out, hipStream_t s) {

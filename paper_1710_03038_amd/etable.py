@@ -8,6 +8,7 @@ set of temperatures, one grid of the batch per temperature, and writes the
 table that the benchmark and applications pass to mpr_match_T:
 
     python -m paper_1710_03038_amd.etable        # writes data/etable_L128.csv
+    python -m paper_1710_03038_amd.etable gmrf   # the GMRF variant: data/etable_gmrf_L128.csv
 
 Procedure (the paper leaves domain, resolution and run lengths open): every
 chain starts from a uniform field at a random angle (cold start, the
@@ -24,13 +25,14 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "data", "etable_L128.csv")
+GMRF_PATH = os.path.join(HERE, "data", "etable_gmrf_L128.csv")
 
 
 def default_temperatures():
     return np.logspace(-5.0, math.log10(3.0), 46)
 
 
-def build_table(L=128, temps=None, chains=4, n_eq=600, n_meas=2400, seed=20171003, dtype="fp64"):
+def build_table(L=128, temps=None, chains=4, n_eq=600, n_meas=2400, seed=20171003, dtype="fp64", model="mpr"):
     import torch
 
     from .mpr import Field, default_params
@@ -39,7 +41,7 @@ def build_table(L=128, temps=None, chains=4, n_eq=600, n_meas=2400, seed=2017100
     dev = torch.device("cuda:0")
     zero = torch.zeros((L, L), dtype=torch.float64, device=dev)
     none = torch.zeros((L, L), dtype=torch.uint8, device=dev)
-    f = Field([(zero, none, chains) for _ in temps], default_params(dtype=dtype, seed=seed))
+    f = Field([(zero, none, chains) for _ in temps], default_params(dtype=dtype, seed=seed, model=model))
     rng = np.random.Generator(np.random.PCG64(seed))
     for g in range(len(temps)):
         for c in range(chains):
@@ -52,13 +54,17 @@ def build_table(L=128, temps=None, chains=4, n_eq=600, n_meas=2400, seed=2017100
     e = per_chain.mean(axis=1)
     err = per_chain.std(axis=1, ddof=1) / math.sqrt(chains)
     f.close()
-    return temps, e, err, dict(L=L, chains=chains, n_eq=n_eq, n_meas=n_meas, seed=seed, dtype=dtype)
+    return temps, e, err, dict(L=L, chains=chains, n_eq=n_eq, n_meas=n_meas, seed=seed, dtype=dtype, model=model)
 
 
 def save_table(path, T, e, err, meta):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
-        f.write("# Equilibrium MPR specific energy e(T) = <H>/N_GP, q = 1/2, open boundaries,\n")
+        if meta.get("model") == "gmrf":
+            f.write("# Equilibrium GMRF specific energy e(T) = <H>/N_GP, H_ij = 1 - dphi^2/(2 pi^2), "
+                    "open boundaries,\n")
+        else:
+            f.write("# Equilibrium MPR specific energy e(T) = <H>/N_GP, q = 1/2, open boundaries,\n")
         f.write("# from unconditional hybrid Monte Carlo chains run with libmpr (paper_1710_03038_amd/etable.py): "
                 + ", ".join(f"{k}={v}" for k, v in meta.items()) + "\n")
         f.write(f"# strictly increasing in T: {bool(np.all(np.diff(e) > 0))}\n")
@@ -67,8 +73,10 @@ def save_table(path, T, e, err, meta):
             f.write(f"{t:.17g},{v:.17g},{s:.6g}\n")
 
 
-def load_table(path=DEFAULT_PATH):
-    """(T, e, e_stderr) arrays of a table file."""
+def load_table(path=None, model="mpr"):
+    """(T, e, e_stderr) arrays of a table file (default: the model's)."""
+    if path is None:
+        path = GMRF_PATH if model == "gmrf" else DEFAULT_PATH
     rows = []
     with open(path) as f:
         for line in f:
@@ -80,7 +88,8 @@ def load_table(path=DEFAULT_PATH):
 
 
 if __name__ == "__main__":
-    out = sys.argv[1] if len(sys.argv) > 1 else DEFAULT_PATH
-    T, e, err, meta = build_table()
+    model = sys.argv[1] if len(sys.argv) > 1 else "mpr"
+    out = sys.argv[2] if len(sys.argv) > 2 else (GMRF_PATH if model == "gmrf" else DEFAULT_PATH)
+    T, e, err, meta = build_table(model=model)
     save_table(out, T, e, err, meta)
     print("wrote", out, "monotone:", bool(np.all(np.diff(e) > 0)), flush=True)

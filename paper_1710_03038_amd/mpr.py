@@ -22,6 +22,7 @@ MPR_OK, MPR_E_ARG, MPR_E_SHAPE, MPR_E_DEGENERATE, MPR_E_NOPAIRS, MPR_E_RANGE, \
 STATUS_NAMES = ["MPR_OK", "MPR_E_ARG", "MPR_E_SHAPE", "MPR_E_DEGENERATE", "MPR_E_NOPAIRS",
                 "MPR_E_RANGE", "MPR_E_WORKSPACE", "MPR_E_HIP", "MPR_E_STATE"]
 FP32, FP64 = 0, 1
+MODEL_MPR, MODEL_GMRF = 0, 1
 ADAPT, TRACE_E, NO_OR = 1, 2, 4
 SAMPLE_PAIRS, STATE = 0, 1
 
@@ -36,7 +37,8 @@ class Params(ctypes.Structure):
     _fields_ = [("q", ctypes.c_double), ("a_targ", ctypes.c_double), ("k_a", ctypes.c_double),
                 ("adapt_every", ctypes.c_int32), ("a_sample_keep", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("sweeps_per_pass", ctypes.c_int32),
-                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -118,6 +120,8 @@ def default_params(**overrides):
     for k, v in overrides.items():
         if k == "dtype" and isinstance(v, str):
             v = {"fp32": FP32, "fp64": FP64}[v]
+        if k == "model" and isinstance(v, str):
+            v = {"mpr": MODEL_MPR, "gmrf": MODEL_GMRF}[v]
         setattr(p, k, v)
     return p
 

@@ -23,7 +23,8 @@ def test_library_exports_every_declared_symbol():
 def test_default_params_are_the_papers():
     p = M.default_params()
     assert (p.q, p.a_targ, p.k_a, p.adapt_every, p.a_sample_keep) == (0.5, 0.3, 3.0, 1, 0)
-    assert p.dtype == M.FP32 and p.seed == 0
+    assert p.dtype == M.FP32 and p.seed == 0 and p.model == M.MODEL_MPR
+    assert M.default_params(model="gmrf").model == M.MODEL_GMRF
 
 
 def test_match_T_matches_oracle_on_the_oracle_table():
@@ -86,7 +87,7 @@ def test_workspace_size_query_and_layout():
     ("q", 0.7, M.MPR_E_ARG), ("q", 0.0, M.MPR_E_ARG), ("a_targ", 1.5, M.MPR_E_ARG),
     ("k_a", 0.0, M.MPR_E_ARG), ("adapt_every", 0, M.MPR_E_ARG), ("dtype", 3, M.MPR_E_ARG),
     ("sweeps_per_pass", 17, M.MPR_E_ARG), ("tile_x", 7, M.MPR_E_ARG), ("tile_y", 194, M.MPR_E_ARG),
-    ("a_sample_keep", 2, M.MPR_E_ARG)])
+    ("a_sample_keep", 2, M.MPR_E_ARG), ("model", 2, M.MPR_E_ARG), ("reserved", 1, M.MPR_E_ARG)])
 def test_bad_params_rejected_before_any_launch(field, value, status):
     p = M.default_params(**{field: value})
     with pytest.raises(M.MPRError) as ei:

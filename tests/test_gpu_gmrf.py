@@ -1,0 +1,94 @@
+"""The GMRF variant (Sec. 4.4, mpr_params.model = MPR_MODEL_GMRF) on the
+GPU against the oracle: per-sweep parity, the exact single-site law,
+specific energies and equilibration."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import mpr as om
+from tests.gpu_util import TWO_PI, explained_mismatches, make_field, oracle_init, random_grid
+from tests.test_gpu_parity import _grids, _teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("tile,nsw", [((32, 32), 1), ((16, 24), 3)])
+def test_teacher_forced_sweep_fp64(tile, nsw):
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp64", tile, nsw, model="gmrf"):
+        assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
+        n_gap = int((~known.astype(bool)).sum())
+        for s in range(nsw):
+            if n_gap:
+                assert A[s] * n_gap == pytest.approx(acc[s], abs=1e-6), (T, a, g, c, s)
+
+
+def test_teacher_forced_sweep_fp32():
+    total_gap = total_bad = 0
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp32", (64, 64), 1, model="gmrf"):
+        n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+        assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
+        total_bad += n_bad
+        total_gap += int((~known.astype(bool)).sum())
+    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_exact_single_site_law(dtype):
+    # 3 x 3 grid, colour-0 sites frozen; z_min = 0 and z_max = 2 pi among
+    # them, so Eq. (2) is the identity.  Each edge site then follows the
+    # truncated normal law of its three frozen neighbours.
+    from tests.test_oracle_pins import chi2_pvalue
+    import torch
+    known = np.zeros((3, 3), np.uint8)
+    vals = np.zeros((3, 3))
+    for (y, x), v in {(0, 0): 0.0, (0, 2): 2.0, (1, 1): 3.5, (2, 0): 4.5, (2, 2): TWO_PI}.items():
+        known[y, x] = 1
+        vals[y, x] = v
+    C, T = 16384, 0.1
+    f = make_field([(vals, known, C)], dtype=dtype, seed=5, model="gmrf")
+    f.set_chain_state(0, np.full(C, 2.0))
+    f.sweep(100, [T])
+    phi = torch.stack([f.get_phi(0, c) for c in range(C)]).cpu().numpy()
+    for (y, x), nb in (((0, 1), ((0, 0), (0, 2), (1, 1))), ((1, 0), ((0, 0), (2, 0), (1, 1))),
+                       ((1, 2), ((0, 2), (2, 2), (1, 1))), ((2, 1), ((2, 0), (2, 2), (1, 1)))):
+        probs = exact.gmrf_single_site_bins([vals[k] for k in nb], 1.0 / T, nbins=8)
+        counts, _ = np.histogram(phi[:, y, x], bins=8, range=(0, TWO_PI))
+        assert chi2_pvalue(counts, probs) > 1e-3, ((y, x), counts, probs * C)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_specific_energies(dtype):
+    grids = _grids(5)
+    f = make_field(grids, dtype=dtype, seed=3, model="gmrf")
+    tol = 1e-12 if dtype == "fp64" else 2e-6
+    e, n = f.specific_energy(0)
+    for g, (z, known, chains) in enumerate(grids):
+        phi_s, _, _ = om.transform(z, known.astype(bool))
+        es, eps, ns = om.sample_specific_energy(phi_s, known.astype(bool), 0.5, om.GMRF)
+        assert n[g] == ns and abs((1 + e[g]) - eps) <= tol * eps + 1e-15, (g, e[g], es)
+    e, n = f.specific_energy(1)
+    k = 0
+    for g, (z, known, chains) in enumerate(grids):
+        for c in range(chains):
+            phi = oracle_init(z, known, 3, c, g, dtype)
+            _, eps = om.state_specific_energy(phi, 0.5, om.GMRF)
+            assert abs((1 + e[k]) - eps) <= tol * eps, (g, c)
+            k += 1
+
+
+def test_equilibrate_matches_oracle_fp64():
+    z, known = random_grid(24, 28, 0.7, 3, smooth=True)
+    C, seed, T = 3, 41, 0.02
+    f = make_field([(z, known, C)], dtype="fp64", seed=seed, model="gmrf")
+    n, at, tr = f.equilibrate([T], n_f=5, n_fit=20, i_max=150)
+    tr = tr.cpu().numpy()
+    phi0 = np.stack([oracle_init(z, known, seed, c, 0, "fp64") for c in range(C)])
+    phi, a, n_ref, at_ref, e_ref, _ = om.equilibrate(phi0, known.astype(bool), T, np.ones(C), 0.5, seed, 0,
+                                                     np.arange(C), 0, n_f=5, n_fit=20, i_max=150, model=om.GMRF)
+    assert np.abs(tr[:, :, 1] - e_ref[:n]).max() <= 1e-9
+    assert n == n_ref and np.array_equal(at, at_ref), (n, n_ref, at, at_ref)
+    for c in range(C):
+        assert np.abs(f.get_phi(0, c).cpu().numpy() - phi[c]).max() <= 1e-5
+    f.close()

@@ -73,9 +73,10 @@ def test_specific_energies(dtype):
 CASES = [(0.3, 1.0), (0.02, 5.0), (1e-3, 40.0), (math.inf, 1.0), (0.0, 3.0)]
 
 
-def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True):
+def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, model="mpr"):
     grids = _grids(21)
-    f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw)
+    om_model = om.GMRF if model == "gmrf" else om.MPR
+    f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw, model=model)
     C = f.total_chains
     results = []
     for T, a in CASES:
@@ -83,7 +84,8 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True):
         states = []
         for g, (z, known, chains) in enumerate(grids):
             phi = np.stack([oracle_init(z, known, seed, c, g, "fp64") for c in range(chains)])
-            phi, _, _, _ = om.run_sweeps(phi, known.astype(bool), 0.05, 2.0, 0.5, seed, 0, 2, np.arange(chains), g)
+            phi, _, _, _ = om.run_sweeps(phi, known.astype(bool), 0.05, 2.0, 0.5, seed, 0, 2, np.arange(chains), g,
+                                         model=om_model)
             if dtype == "fp32":
                 phi = np.stack([as_fp32_state(p, known) for p in phi])
             states.append(phi)
@@ -100,7 +102,7 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True):
             for s in range(nsw):
                 phi, acc = om.hybrid_sweep(phi, known.astype(bool), [beta] * chains, [TWO_PI / a] * chains, 0.5,
                                            seed, sweep_index + s, np.arange(chains), g, margins=margins,
-                                           or_step=or_step)
+                                           or_step=or_step, model=om_model)
                 accs.append(acc)
             for c in range(chains):
                 got = f.get_phi(g, c).cpu().numpy()

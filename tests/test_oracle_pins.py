@@ -18,15 +18,30 @@ TWO_PI = 2.0 * math.pi
 
 
 def chi2_pvalue(counts, probs):
+    """Pearson chi-square p-value of binned counts against bin
+    probabilities.  Adjacent bins are pooled, in order, until every cell
+    expects at least 5 counts (a remainder joins the last cell), the
+    condition for the chi-square approximation."""
     counts = np.asarray(counts, dtype=np.float64)
     exp = np.asarray(probs) * counts.sum()
-    keep = exp >= 5.0
-    c = np.append(counts[keep], counts[~keep].sum())
-    e = np.append(exp[keep], exp[~keep].sum())
-    if e[-1] == 0.0:
-        c, e = c[:-1], e[:-1]
+    c, e = [], []
+    cc = ee = 0.0
+    for ci, ei in zip(counts, exp):
+        cc += ci
+        ee += ei
+        if ee >= 5.0:
+            c.append(cc)
+            e.append(ee)
+            cc = ee = 0.0
+    if ee > 0.0 or cc > 0.0:
+        if e:
+            c[-1] += cc
+            e[-1] += ee
+        else:
+            c, e = [cc], [ee]
+    c, e = np.array(c), np.array(e)
     stat = ((c - e) ** 2 / e).sum()
-    return chi2.sf(stat, len(c) - 1)
+    return chi2.sf(stat, max(len(c) - 1, 1))
 
 
 def run_chains(known, phi0, T, a, q, seed, n_sweeps, grid=0):

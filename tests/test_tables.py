@@ -21,3 +21,22 @@ def test_table_shape_and_limits(loader, L):
     assert np.all(np.abs(ratio - 1.0) < 0.01), ratio
     assert np.all(e < -4.0 / math.pi ** 2)
     assert np.all(err < 5e-3 * eps + 1e-12)
+
+
+@pytest.mark.parametrize("which,L", [("oracle", 32), ("product", 128)])
+def test_gmrf_table_shape_and_limits(which, L):
+    # The GMRF energy is exactly quadratic: the same equipartition slope at
+    # low T, and at T = infinity 1 + e = E[dphi^2] / (2 pi^2) = 1/3 for
+    # independent uniform angles, so e < -2/3 throughout.
+    if which == "oracle":
+        from oracle import mpr as om
+        T, e, err = load_oracle_table(model=om.GMRF)
+    else:
+        T, e, err = load_product_table(model="gmrf")
+    assert np.all(np.diff(T) > 0) and np.all(np.diff(e) > 0)
+    eps = 1.0 + e
+    low = T < 3e-3
+    ratio = eps[low] / ((L + 1) * T[low] / (4 * L))
+    assert np.all(np.abs(ratio - 1.0) < 0.01), ratio
+    assert np.all(e < -2.0 / 3.0)
+    assert np.all(err < 5e-3 * eps + 1e-12)
