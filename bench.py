@@ -197,6 +197,65 @@ def validation_study(Ls, S):
                 print(json.dumps(out), flush=True)
 
 
+def gmrf_study(S, L=32):
+    """The paper's comparison of the MPR and GMRF pair interactions (Sec.
+    4.4): S configurations of L x L WM(kappa, nu) data, Gaussian
+    (mean 50, std 10) or lognormal (log Z with mean 5, std 1), case a: 33 %
+    random gaps, b: 66 %, c: one 20 x 20 block; each model with its own e(T)
+    table for SEM, Savitzky-Golay equilibration and M = 100 recorded sweeps.
+    All S configurations of a row run as one batch (one grid each).  One
+    JSON line per row, with the paper's values where printed."""
+    import torch
+
+    import mprgen
+    from paper_1710_03038_amd import mpr as M
+    from paper_1710_03038_amd.etable import load_table
+
+    paper = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_mpr_gmrf.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        dist, nu, kappa, model, case, *vals = line.split()
+        paper[(dist, float(nu), float(kappa), model, case)] = dict(
+            zip(("MAAE", "MARE", "MAARE", "MRASE", "MR"), map(float, vals)))
+    dev = torch.device("cuda:0")
+    for dist in ("gaussian", "lognormal"):
+        for nu in (0.5, 0.25):
+            for kappa in (0.5, 0.2):
+                for case in ("a", "b", "c"):
+                    grids = []
+                    for s in range(S):
+                        base = 700000 + 1000 * s + 100 * int(kappa * 10) + int(nu * 100) + ord(case)
+                        y = mprgen.matern_field(L, L, kappa, nu, base, mean=0.0, std=1.0)
+                        z = 50.0 + 10.0 * y if dist == "gaussian" else np.exp(5.0 + y)
+                        known = (mprgen.mask_block(L, L, 20, base + 1) if case == "c"
+                                 else mprgen.mask_random(L, L, {"a": 0.33, "b": 0.66}[case], base + 1))
+                        grids.append((torch.from_numpy(z).to(dev), torch.from_numpy(known).to(dev), 1))
+                    for model in ("mpr", "gmrf"):
+                        table = load_table(model=model)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        f = M.Field(grids, M.default_params(dtype="fp32", seed=991, model=model))
+                        e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
+                        T, _ = M.match_T(e_s, table[0], table[1])
+                        n, _, _ = f.equilibrate(T, n_f=5, n_fit=20, i_max=2000)
+                        zh, _, _ = f.fill(T, 0, 100, 1)
+                        ms = [f.validation_measures(g, grids[g][0], zh[g]) for g in range(S)]
+                        f.close()
+                        dt = time.perf_counter() - t0
+                        aae = np.array([m["AAE"] for m in ms])
+                        out = {"study": "gmrf", "distribution": dist, "nu": nu, "kappa": kappa, "model": model,
+                               "case": case, "L": L, "S": S,
+                               "MAAE": float(aae.mean()), "MARE_pct": 100 * float(np.mean([m["ARE"] for m in ms])),
+                               "MAARE_pct": 100 * float(np.mean([m["AARE"] for m in ms])),
+                               "MRASE": float(np.mean([m["RASE"] for m in ms])),
+                               "MR_pct": 100 * float(np.mean([m["R"] for m in ms])),
+                               "AAE_quartiles": [float(v) for v in np.percentile(aae, [25, 50, 75])],
+                               "eq_sweeps": n, "seconds_for_S": dt,
+                               "paper": paper.get((dist, nu, kappa, model, case))}
+                        print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=256 << 20, reps=10):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters of rocprofv3 to bytes."""
@@ -326,11 +385,12 @@ def main():
                     help="keep the library's default launch shape (for profiling runs, whose timing would sway "
                          "the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--study", choices=["relaxation", "validation"], default=None,
+    ap.add_argument("--study", choices=["relaxation", "validation", "gmrf"], default=None,
                     help="relaxation: energy relaxation of the hybrid, restricted and standard Metropolis updates "
                          "and their Savitzky-Golay equilibration points (L x L Whittle-Matern field, p gaps); "
                          "validation: the paper's MPR validation measures on WM(0.2, nu) data, one JSON line per "
-                         "(L, nu, case)")
+                         "(L, nu, case); gmrf: MPR against the GMRF pair interaction on Gaussian and lognormal "
+                         "WM data, L = 32")
     ap.add_argument("--Ls", type=int, nargs="+", default=[256, 512, 1024])
     ap.add_argument("--S", type=int, default=0, help="configurations per row (0: 100 at L <= 256, then fewer)")
     ap.add_argument("--L", type=int, default=512)
@@ -353,6 +413,9 @@ def main():
         return
     if args.study == "validation":
         validation_study(args.Ls, args.S)
+        return
+    if args.study == "gmrf":
+        gmrf_study(args.S or 100)
         return
 
     import torch
