@@ -42,6 +42,18 @@ Readings of points the paper leaves open (each also used by the library):
   i is a multiple of n_f.  Chains of a batch sweep in lock-step until every
   chain has passed a check.
 
+Replicate auxiliary nodes (Sec. 2.5), an option (``boundary=REPLICATE``):
+the grid is padded with a ring of auxiliary nodes holding copies of their
+nearest grid sites and the padded grid is swept with open boundaries, the
+ring frozen.  The ring is refreshed from the state at the start of every
+half-sweep, so an edge site's auxiliary neighbour holds that site's own
+value from before the half-sweep (a corner site has two such neighbours).
+Energies (Eqs. 4, 5, the e(T) table and the equilibration trace) stay on
+the grid's own 2 L (L - 1) pairs: an auxiliary pair would only add the
+constant -1.  The update then depends on the site's previous value, so it
+no longer satisfies detailed balance for Eq. (3); the open boundary is the
+default.
+
 The GMRF variant (Sec. 4.4) replaces the pair interaction by
 H_ij = 1 - dphi^2 / (2 pi^2) on the same non-periodic angles; its
 over-relaxation reflects phi about the mean of its neighbours, kept only
@@ -65,6 +77,8 @@ HOT_START_SWEEP = 0xFFFFFFFF
 # Pair interactions (Sec. 4.4): the MPR energy of Eq. (3), H_ij = cos(q dphi),
 # or the Gaussian (GMRF) one, H_ij = 1 - dphi^2 / (2 pi^2); H = -sum H_ij.
 MPR, GMRF = "mpr", "gmrf"
+# Boundary of the sweep (Sec. 2.1 open; Sec. 2.5 replicate auxiliary nodes).
+OPEN, REPLICATE = "open", "replicate"
 TWO_PI_SQ = 2.0 * math.pi * math.pi
 
 
@@ -89,12 +103,14 @@ def site_uniforms(seed, ny, nx, sweep, chains, grid, origin=(0, 0), npair=None):
     """
     k0, k1 = split_seed(seed)
     chains = np.asarray(chains, dtype=np.uint64).reshape(-1, 1, 1)
-    y = np.arange(origin[0], origin[0] + ny, dtype=np.uint64).reshape(1, ny, 1)
-    x = np.arange(origin[1], origin[1] + nx, dtype=np.uint64).reshape(1, 1, nx)
+    # int64 so that a window may start left of or above the grid (the ring of
+    # auxiliary nodes); the counter word is the pair index mod 2^32
+    y = np.arange(origin[0], origin[0] + ny, dtype=np.int64).reshape(1, ny, 1)
+    x = np.arange(origin[1], origin[1] + nx, dtype=np.int64).reshape(1, 1, nx)
     npair = (nx + 1) // 2 if npair is None else npair
-    pair = y * np.uint64(npair) + x // np.uint64(2)
-    w0, w1, w2, w3 = philox4x32(pair, sweep, chains, grid, k0, k1)
-    even = (x % np.uint64(2)) == 0
+    pair = (y * npair + x // 2) % (1 << 32)
+    w0, w1, w2, w3 = philox4x32(pair.astype(np.uint64), sweep, chains, grid, k0, k1)
+    even = (x % 2) == 0
     u = np.where(even, w0, w2)
     r = np.where(even, w1, w3)
     return unit_float(u), unit_float(r)
@@ -224,11 +240,16 @@ def wrap(x):
     return np.where(y >= TWO_PI, 0.0, y)
 
 
-def _neighbours(phi):
-    """Angles of the four neighbours of every site, NaN where off the grid."""
+def _neighbours(phi, boundary=OPEN):
+    """Angles of the four neighbours of every site, NaN where off the grid;
+    with REPLICATE the off-grid neighbours are auxiliary nodes that copy
+    their nearest grid site."""
     ny, nx = phi.shape[-2:]
-    pad = np.full(phi.shape[:-2] + (ny + 2, nx + 2), np.nan)
-    pad[..., 1:-1, 1:-1] = phi
+    if boundary == REPLICATE:
+        pad = np.pad(phi, [(0, 0)] * (phi.ndim - 2) + [(1, 1), (1, 1)], mode="edge")
+    else:
+        pad = np.full(phi.shape[:-2] + (ny + 2, nx + 2), np.nan)
+        pad[..., 1:-1, 1:-1] = phi
     return [pad[..., 1:-1, :-2], pad[..., 1:-1, 2:], pad[..., :-2, 1:-1], pad[..., 2:, 1:-1]]
 
 
@@ -263,7 +284,7 @@ def site_energy(phi, nbrs, q, model=MPR):
 
 
 def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), npair=None,
-                 or_step=True, model=MPR):
+                 or_step=True, model=MPR, boundary=OPEN):
     """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
 
     phi: (C, ny, nx) float64 current states (not modified).
@@ -282,6 +303,8 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     or_step: False skips step 1 (no over-relaxation): the restricted
       Metropolis update alone, or standard Metropolis with a = 1 (Sec. 2.4).
     model: MPR or GMRF pair interactions (Sec. 4.4).
+    boundary: OPEN, or REPLICATE auxiliary nodes (Sec. 2.5), refreshed at
+      the start of each half-sweep.
     Returns (new phi, accepted count per chain).
     """
     phi = np.array(phi, dtype=np.float64, copy=True)
@@ -296,7 +319,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
             margins[k] = np.full(phi.shape, np.inf)
     for colour in (0, 1):
         update = (((xx + yy) % 2) == colour) & ~known
-        nbrs = _neighbours(phi)
+        nbrs = _neighbours(phi, boundary)
         phi1 = over_relax(phi, nbrs, q, model) if or_step else phi  # step 1
         phi2 = wrap(phi1 + alpha * (u - 0.5))                # steps 2-3
         dH = site_energy(phi2, nbrs, q, model) - site_energy(phi1, nbrs, q, model)   # step 4
@@ -326,11 +349,14 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     return phi, accepted
 
 
-def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, or_step=True, model=MPR):
+def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, or_step=True, model=MPR,
+                         boundary=OPEN):
     """Algorithm 1 for one chain as a plain per-site loop (small grids only).
 
     Same checkerboard order and random stream as ``hybrid_sweep``; written
     with scalar ``math`` calls so the two can be checked against each other.
+    With REPLICATE, each missing neighbour of a site contributes the site's
+    own value at the start of its update (its value before the half-sweep).
     """
     phi = [list(map(float, row)) for row in np.asarray(phi, dtype=np.float64)]
     ny, nx = len(phi), len(phi[0])
@@ -346,9 +372,13 @@ def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, o
                 wu, wr = (w[0], w[1]) if x % 2 == 0 else (w[2], w[3])
                 u = float(unit_float(wu))
                 r = float(unit_float(wr))
-                nb = [phi[yy][xx] for yy, xx in ((y, x - 1), (y, x + 1), (y - 1, x), (y + 1, x))
-                      if 0 <= yy < ny and 0 <= xx < nx]
                 cur = phi[y][x]
+                nb = []
+                for yy, xx in ((y, x - 1), (y, x + 1), (y - 1, x), (y + 1, x)):
+                    if 0 <= yy < ny and 0 <= xx < nx:
+                        nb.append(phi[yy][xx])
+                    elif boundary == REPLICATE:
+                        nb.append(cur)
                 if model == GMRF:
                     p1 = cur
                     if or_step and nb:
@@ -391,7 +421,7 @@ def adapt_a(a, acceptance, i, a_targ=0.3, k_a=3.0):
 
 def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
                adapt=False, adapt_every=1, a_targ=0.3, k_a=3.0, trace_energy=False, or_step=True, window=None,
-               model=MPR):
+               model=MPR, boundary=OPEN):
     """Advance C chains of one grid by ``n_sweeps`` hybrid sweeps.
 
     Returns (phi, a, acceptance per sweep (n, C), specific energy per sweep
@@ -399,7 +429,8 @@ def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
     ``adapt_every`` sweeps using the mean acceptance of that window; the
     rule's counter i is the global sweep index.  ``window`` (C,), if given,
     carries the running window sum across calls and is updated in place.
-    ``or_step`` = False leaves out over-relaxation.
+    ``or_step`` = False leaves out over-relaxation; ``boundary`` as in
+    ``hybrid_sweep``.
     """
     C = phi.shape[0]
     T = np.broadcast_to(np.asarray(T, dtype=np.float64), (C,))
@@ -413,7 +444,8 @@ def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
         window = np.zeros(C)
     for s in range(n_sweeps):
         i = first_sweep + s
-        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid, or_step=or_step, model=model)
+        phi, acc = hybrid_sweep(phi, known, beta, TWO_PI / a, q, seed, i, chains, grid, or_step=or_step, model=model,
+                                boundary=boundary)
         A = acc / n_gap if n_gap > 0 else np.ones(C)
         acc_trace[s] = A
         if trace_energy:
@@ -427,7 +459,7 @@ def run_sweeps(phi, known, T, a, q, seed, first_sweep, n_sweeps, chains, grid,
 
 
 def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
-         a_targ=0.3, k_a=3.0, adapt_every=1, a_sample_keep=False, model=MPR):
+         a_targ=0.3, k_a=3.0, adapt_every=1, a_sample_keep=False, model=MPR, boundary=OPEN):
     """Algorithm 2 with fixed sweep counts (no Savitzky-Golay stop).
 
     Hot start, ``n_eq`` equilibration sweeps with the a-rule, then
@@ -442,7 +474,8 @@ def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
     phi = hot_start(phi_s, known, seed, chain_ids, grid)
     a = np.ones(chains)
     phi, a, acc_eq, _ = run_sweeps(phi, known, T, a, q, seed, 0, n_eq, chain_ids, grid,
-                                   adapt=True, adapt_every=adapt_every, a_targ=a_targ, k_a=k_a, model=model)
+                                   adapt=True, adapt_every=adapt_every, a_targ=a_targ, k_a=k_a, model=model,
+                                   boundary=boundary)
     a_eq = a.copy()
     if not a_sample_keep:
         a = np.ones(chains)
@@ -451,7 +484,8 @@ def fill(z, known, T, n_eq, n_samp, stride, q=0.5, seed=0, chains=1, grid=0,
     m = 0
     acc_samp = []
     for j in range(n_samp):
-        phi, a, acc, _ = run_sweeps(phi, known, T, a, q, seed, n_eq + j, 1, chain_ids, grid, model=model)
+        phi, a, acc, _ = run_sweeps(phi, known, T, a, q, seed, n_eq + j, 1, chain_ids, grid, model=model,
+                                    boundary=boundary)
         acc_samp.append(acc[0])
         if (j + 1) % stride == 0:
             s1 += phi.sum(axis=0)
@@ -506,7 +540,7 @@ def sg_stop_index(e_after, n_f, n_fit, i_max):
 
 
 def equilibrate(phi, known, T, a, q, seed, first_sweep, chains, grid, n_f=5, n_fit=20, i_max=1000,
-                adapt=True, or_step=True, adapt_every=1, a_targ=0.3, k_a=3.0, model=MPR):
+                adapt=True, or_step=True, adapt_every=1, a_targ=0.3, k_a=3.0, model=MPR, boundary=OPEN):
     """Algorithm 2, step 4, for C chains of one grid swept in lock-step:
     hybrid sweeps (4.1), the a-rule (4.2, with ``adapt``), the specific
     energy after every sweep (4.3) and the Savitzky-Golay slope check of
@@ -526,7 +560,7 @@ def equilibrate(phi, known, T, a, q, seed, first_sweep, chains, grid, n_f=5, n_f
     while i <= i_max and np.any(eq_at < 0):
         phi, a, acc, e = run_sweeps(phi, known, T, a, q, seed, first_sweep + i, 1, chains, grid, adapt=adapt,
                                     adapt_every=adapt_every, a_targ=a_targ, k_a=k_a, trace_energy=True,
-                                    or_step=or_step, window=window, model=model)
+                                    or_step=or_step, window=window, model=model, boundary=boundary)
         e_hist.append(e[0])
         acc_hist.append(acc[0])
         if i >= n_fit and i % n_f == 0:
