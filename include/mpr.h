@@ -59,6 +59,19 @@ typedef enum { MPR_FP32 = 0, MPR_FP64 = 1 } mpr_dtype;
  * chosen interaction; the e(T) table must be that model's. */
 typedef enum { MPR_MODEL_MPR = 0, MPR_MODEL_GMRF = 1 } mpr_model;
 
+/* Boundary of the sweeps.  MPR_BC_OPEN: open boundaries, edge sites have
+ * fewer neighbours (Sec. 2.1).  MPR_BC_REPLICATE: the auxiliary nodes of
+ * Sec. 2.5, a ring around the grid whose nodes copy their nearest grid
+ * site; the augmented grid is swept with open boundaries and the ring is
+ * refreshed at the start of every half-sweep, so each off-grid neighbour
+ * of an edge site holds that site's own value from before the half-sweep
+ * (two for a corner).  Only the updates change: the specific energies and
+ * the equilibration trace stay on the grid's own pairs.  The replicate
+ * update depends on the site's previous value and so does not satisfy
+ * detailed balance for Eq. (3); the e(T) tables are those of the open
+ * boundary. */
+typedef enum { MPR_BC_OPEN = 0, MPR_BC_REPLICATE = 1 } mpr_boundary;
+
 /* mpr_sweep flags */
 #define MPR_ADAPT   1u /* apply the a-rule of Algorithm 2, step 4.2 */
 #define MPR_TRACE_E 2u /* record the specific energy e of Eq. (5) after every sweep */
@@ -92,7 +105,7 @@ typedef struct {
   int32_t tile_x, tile_y; /* interior tile of one workgroup (even, 8..192); 0 = library choice */
   uint64_t seed;          /* Philox4x32-10 key: (seed mod 2^32, seed >> 32) */
   int32_t model;          /* pair interaction: MPR_MODEL_MPR (Eq. 3) or MPR_MODEL_GMRF (Sec. 4.4) */
-  int32_t reserved;       /* must be 0 */
+  int32_t boundary;       /* mpr_boundary: MPR_BC_OPEN (default) or MPR_BC_REPLICATE */
 } mpr_params;
 
 typedef struct {
@@ -105,7 +118,7 @@ typedef struct {
 
 /* Fill *p with the paper's defaults (Sec. 2.5): q = 0.5, A_targ = 0.3,
  * k_a = 3, adapt_every = 1, a_sample_keep = 0, FP32, library-chosen tiles,
- * seed 0, the MPR interaction. */
+ * seed 0, the MPR interaction, open boundaries. */
 void mpr_default_params(mpr_params *p);
 
 /*

@@ -144,7 +144,8 @@ mpr_status check_params(const mpr_params *p) {
       return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 192]");
   if (p->model != MPR_MODEL_MPR && p->model != MPR_MODEL_GMRF)
     return fail(nullptr, MPR_E_ARG, "model must be MPR_MODEL_MPR or MPR_MODEL_GMRF");
-  if (p->reserved != 0) return fail(nullptr, MPR_E_ARG, "params.reserved must be 0");
+  if (p->boundary != MPR_BC_OPEN && p->boundary != MPR_BC_REPLICATE)
+    return fail(nullptr, MPR_E_ARG, "boundary must be MPR_BC_OPEN or MPR_BC_REPLICATE");
   return MPR_OK;
 }
 
@@ -330,6 +331,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.lds_h = h;
   A.q_is_one = c->p.q == 1.0;
   A.gmrf = c->p.model == MPR_MODEL_GMRF ? 1 : 0;
+  A.rep = c->p.boundary == MPR_BC_REPLICATE ? 1 : 0;
   A.or_step = or_step ? 1 : 0;
   A.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
   A.key1 = (uint32_t)(c->p.seed >> 32);
@@ -601,6 +603,7 @@ void mpr_default_params(mpr_params *p) {
   p->tile_y = 0;
   p->seed = 0;
   p->model = MPR_MODEL_MPR;
+  p->boundary = MPR_BC_OPEN;
 }
 
 const char *mpr_last_error(const mpr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_thread_err.c_str(); }

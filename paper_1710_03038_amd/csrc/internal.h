@@ -61,6 +61,7 @@ struct SweepArgs {
   int32_t q_is_one;
   int32_t gmrf;                    // 1: GMRF pair interaction (mpr_params.model)
   int32_t or_step;                 // 1: Algorithm 1, step 1 (over-relaxation); 0: Metropolis only
+  int32_t rep;                     // 1: replicate auxiliary nodes around the grid (mpr_params.boundary)
   uint32_t key0, key1;
   uint32_t sweep0;                 // global index of the pass's first sweep
   uint32_t record_mask, first_mask;

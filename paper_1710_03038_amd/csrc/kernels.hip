@@ -212,14 +212,26 @@ template <typename P> struct UpdateCtx {
   uint32_t sweep, cid, gid, k0, k1;
   P q, inv_q, alpha, beta;
   bool or_step;        // over-relaxation on
+  // LDS column of grid x = 0 and x = nx - 1, row of y = 0 and y = ny - 1
+  // (outside the LDS range when the tile is away from that edge).
+  int ex0, ex1, ey0, ey1;
 };
+
+// Replicate auxiliary nodes (Sec. 2.5): the number of a site's neighbours
+// that lie off the grid, each an auxiliary node that holds the site's own
+// value from before the half-sweep.
+template <typename P>
+__device__ __forceinline__ int aux_count(const UpdateCtx<P> &U, int ly, int lx) {
+  return (lx == U.ex0 ? 1 : 0) + (lx == U.ex1 ? 1 : 0) + (ly == U.ey0 ? 1 : 0) + (ly == U.ey1 ? 1 : 0);
+}
 
 // Algorithm 1 with the GMRF pair interaction for the K plan entries fs[]
 // of one thread.  A site's energy is a parabola in its angle about the mean
 // m = S/n of its n in-grid neighbours (NaN in the angle plane marks none),
 // so over-relaxation reflects about m, kept inside [0, 2 pi), and
-// dH = ((p2 - p1) (n (p2 + p1) - 2 S)) / (2 pi^2).
-template <typename P, int K>
+// dH = ((p2 - p1) (n (p2 + p1) - 2 S)) / (2 pi^2).  With REP, g auxiliary
+// neighbours add g copies of the site's own angle to S and g to n.
+template <typename P, bool REP, int K>
 __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
                                                       const bool (&cnt)[K]) {
   int o[K];
@@ -239,6 +251,11 @@ __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, con
       const bool in = !__builtin_isnan(nb[m]);
       sum[k] += in ? fabs(nb[m]) : P(0);
       n[k] += in ? P(1) : P(0);
+    }
+    if constexpr (REP) {
+      const P g = (P)aux_count(U, ly, lx);
+      sum[k] = fma(g, phi[k], sum[k]);
+      n[k] += g;
     }
     uint32_t w[4];
     philox4x32_10((uint32_t)(U.pbase + ly * U.npair + j), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
@@ -264,10 +281,10 @@ __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, con
 
 // Algorithm 1 for the K plan entries fs[] of one thread, interleaved step
 // by step; returns the accepted updates among those with cnt[] set.
-template <typename P, int MODEL, int K>
+template <typename P, int MODEL, bool REP, int K>
 __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
                                                  const bool (&cnt)[K]) {
-  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, K>(U, fs, cnt);
+  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, REP, K>(U, fs, cnt);
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
   const P q = U.q;
@@ -285,6 +302,13 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
     const V2 nu = U.cn[o[k] - U.P2], nd = U.cn[o[k] + U.P2];
     hx[k] = nl.x + nr.x + nu.x + nd.x;
     hy[k] = nl.y + nr.y + nu.y + nd.y;
+    if constexpr (REP) {
+      // off-grid neighbours read (0, 0); each auxiliary one adds the site's own (cos, sin)
+      const P g = (P)aux_count(U, ly, lx);
+      const V2 own = U.cc[o[k]];
+      hx[k] = fma(g, own.x, hx[k]);
+      hy[k] = fma(g, own.y, hy[k]);
+    }
     // Philox pair of the site: its LDS pair index offset by the tile origin.
     uint32_t w[4];
     philox4x32_10((uint32_t)(U.pbase + ly * U.npair + j), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
@@ -332,7 +356,7 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
 // 2*nsw + 1 sites covers hs = 0), so the interior is exact after the last
 // half-sweep.  When the energy of interior pairs is traced, every D is one
 // larger, so that the interior plus one ring is exact after each sweep.
-template <typename P, int NT, int MODEL>
+template <typename P, int NT, int MODEL, bool REP>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
@@ -465,8 +489,11 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       P *pc = ph + c * plane;
       V2 *cc = cs + c * plane;
       const V2 *cn = cs + (c ^ 1) * plane;
-      const UpdateCtx<P> U{lc,  pc,    cc,    cn,   ph + (c ^ 1) * plane, Ly, Lx, P2, pbase, npair,
-                           sweep, cid, gid, k0, k1, q, inv_q, alpha, beta, A.or_step != 0};
+      const UpdateCtx<P> U{lc,    pc,  cc,  cn,    ph + (c ^ 1) * plane,
+                           Ly,    Lx,  P2,  pbase, npair,
+                           sweep, cid, gid, k0,    k1,
+                           q,     inv_q, alpha, beta, A.or_step != 0,
+                           -ox,   nx - 1 - ox, -oy, ny - 1 - oy};
       // In FP32, two independent updates per thread and iteration (items f
       // and f + NT) give the scheduler two dependency chains to interleave;
       // a lane without a second item repeats its first, whose identical
@@ -478,11 +505,11 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         if (kIlp == 2 && __any(f2 < n)) {
           const uint32_t fs[2] = {f, f2 < n ? f2 : f};
           const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
-          acc += update_sites<P, MODEL, 2>(U, fs, cnt);
+          acc += update_sites<P, MODEL, REP, 2>(U, fs, cnt);
         } else {
           const uint32_t fs[1] = {f};
           const bool cnt[1] = {f < n_inner};
-          acc += update_sites<P, MODEL, 1>(U, fs, cnt);
+          acc += update_sites<P, MODEL, REP, 1>(U, fs, cnt);
         }
       }
       __syncthreads();
@@ -642,21 +669,28 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
   apply_pass_end(A, A.grids[lo], ch, true);
 }
 
-template <typename P, int MODEL>
+template <typename P, int MODEL, bool REP>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
+  const dim3 grid((unsigned)n_items);
   switch (threads) {
-    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL>), dim3((unsigned)n_items), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL>), dim3((unsigned)n_items), dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL>), dim3((unsigned)n_items), dim3(1024), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP>), grid, dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP>), grid, dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP>), grid, dim3(1024), lds, s, a); break;
   }
+}
+
+template <typename P, bool REP>
+static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
+  if (a.gmrf) launch_sweep_q<P, kGmrf, REP>(a, threads, n_items, lds, s);
+  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP>(a, threads, n_items, lds, s);
+  else launch_sweep_q<P, kMprQ, REP>(a, threads, n_items, lds, s);
 }
 
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-  if (a.gmrf) launch_sweep_q<P, kGmrf>(a, threads, n_items, lds, s);
-  else if (a.q_is_one) launch_sweep_q<P, kMprQ1>(a, threads, n_items, lds, s);
-  else launch_sweep_q<P, kMprQ>(a, threads, n_items, lds, s);
+  if (a.rep) launch_sweep_m<P, true>(a, threads, n_items, lds, s);
+  else launch_sweep_m<P, false>(a, threads, n_items, lds, s);
   return hipGetLastError();
 }
 
@@ -664,9 +698,9 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
-    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ>)); break;
-    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ>)); break;
-    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ>)); break;
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false>)); break;
     default: break;
   }
   return e == hipSuccess ? at.maxThreadsPerBlock : 0;

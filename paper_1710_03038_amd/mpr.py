@@ -23,6 +23,7 @@ STATUS_NAMES = ["MPR_OK", "MPR_E_ARG", "MPR_E_SHAPE", "MPR_E_DEGENERATE", "MPR_E
                 "MPR_E_RANGE", "MPR_E_WORKSPACE", "MPR_E_HIP", "MPR_E_STATE"]
 FP32, FP64 = 0, 1
 MODEL_MPR, MODEL_GMRF = 0, 1
+BC_OPEN, BC_REPLICATE = 0, 1
 ADAPT, TRACE_E, NO_OR = 1, 2, 4
 SAMPLE_PAIRS, STATE = 0, 1
 
@@ -38,7 +39,7 @@ class Params(ctypes.Structure):
                 ("adapt_every", ctypes.c_int32), ("a_sample_keep", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("sweeps_per_pass", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("model", ctypes.c_int32), ("boundary", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -122,6 +123,8 @@ def default_params(**overrides):
             v = {"fp32": FP32, "fp64": FP64}[v]
         if k == "model" and isinstance(v, str):
             v = {"mpr": MODEL_MPR, "gmrf": MODEL_GMRF}[v]
+        if k == "boundary" and isinstance(v, str):
+            v = {"open": BC_OPEN, "replicate": BC_REPLICATE}[v]
         setattr(p, k, v)
     return p
 

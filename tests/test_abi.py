@@ -87,7 +87,8 @@ def test_workspace_size_query_and_layout():
     ("q", 0.7, M.MPR_E_ARG), ("q", 0.0, M.MPR_E_ARG), ("a_targ", 1.5, M.MPR_E_ARG),
     ("k_a", 0.0, M.MPR_E_ARG), ("adapt_every", 0, M.MPR_E_ARG), ("dtype", 3, M.MPR_E_ARG),
     ("sweeps_per_pass", 17, M.MPR_E_ARG), ("tile_x", 7, M.MPR_E_ARG), ("tile_y", 194, M.MPR_E_ARG),
-    ("a_sample_keep", 2, M.MPR_E_ARG), ("model", 2, M.MPR_E_ARG), ("reserved", 1, M.MPR_E_ARG)])
+    ("a_sample_keep", 2, M.MPR_E_ARG), ("model", 2, M.MPR_E_ARG), ("boundary", 2, M.MPR_E_ARG),
+    ("boundary", -1, M.MPR_E_ARG)])
 def test_bad_params_rejected_before_any_launch(field, value, status):
     p = M.default_params(**{field: value})
     with pytest.raises(M.MPRError) as ei:

@@ -73,10 +73,11 @@ def test_specific_energies(dtype):
 CASES = [(0.3, 1.0), (0.02, 5.0), (1e-3, 40.0), (math.inf, 1.0), (0.0, 3.0)]
 
 
-def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, model="mpr"):
+def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, model="mpr", boundary="open"):
     grids = _grids(21)
     om_model = om.GMRF if model == "gmrf" else om.MPR
-    f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw, model=model)
+    f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw, model=model,
+                   boundary=boundary)
     C = f.total_chains
     results = []
     for T, a in CASES:
@@ -102,7 +103,7 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, mod
             for s in range(nsw):
                 phi, acc = om.hybrid_sweep(phi, known.astype(bool), [beta] * chains, [TWO_PI / a] * chains, 0.5,
                                            seed, sweep_index + s, np.arange(chains), g, margins=margins,
-                                           or_step=or_step, model=om_model)
+                                           or_step=or_step, model=om_model, boundary=boundary)
                 accs.append(acc)
             for c in range(chains):
                 got = f.get_phi(g, c).cpu().numpy()
@@ -152,6 +153,54 @@ def test_teacher_forced_sweep_without_over_relaxation(dtype):
             total_bad += int(((np.abs(got - ref) > 1e-3) & ~known.astype(bool)).sum())
             total_gap += int((~known.astype(bool)).sum())
     assert total_bad <= max(3, 1e-3 * max(total_gap, 1)), (total_bad, total_gap)
+
+
+@pytest.mark.parametrize("model", ["mpr", "gmrf"])
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_teacher_forced_sweep_replicate_boundary(dtype, model):
+    # auxiliary nodes copying the edge sites (MPR_BC_REPLICATE); tiles of
+    # 32 x 24 put grid edges in the halo of inner tiles as well as in the
+    # interior of edge tiles
+    total_gap = total_bad = 0
+    nsw = 2 if dtype == "fp64" else 1
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced(dtype, (32, 24), nsw, model=model,
+                                                                        boundary="replicate"):
+        if dtype == "fp64":
+            assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
+            n_gap = int((~known.astype(bool)).sum())
+            for s in range(nsw):
+                if n_gap:
+                    assert A[s] * n_gap == pytest.approx(acc[s], abs=1e-6), (T, a, g, c, s)
+        else:
+            n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+            assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
+            total_bad += n_bad
+            total_gap += int((~known.astype(bool)).sum())
+    assert total_bad <= max(3, 1e-3 * max(total_gap, 1)), (total_bad, total_gap)
+
+
+def test_replicate_boundary_changes_only_edge_updates():
+    # one sweep from the same state: sites whose four neighbours are all on
+    # the grid update identically under both boundaries (same stream, same
+    # field); edge gap sites see their auxiliary neighbours
+    grids = _grids(23)
+    out = {}
+    for bc in ("open", "replicate"):
+        f = make_field(grids, dtype="fp64", seed=5, tile_x=16, tile_y=16, sweeps_per_pass=1, boundary=bc)
+        f.sweep(1, np.full(len(grids), 0.05))
+        out[bc] = [f.get_phi(g, 0).cpu().numpy() for g in range(len(grids))]
+    changed = 0
+    for g, (z, known, _) in enumerate(grids):
+        o, r = out["open"][g], out["replicate"][g]
+        ny, nx = o.shape
+        # colour 1 reads colour 0's new values, so an edge change can move
+        # colour-1 neighbours of edge sites one site in: compare two rings in
+        inner = np.zeros((ny, nx), dtype=bool)
+        inner[2:-2, 2:-2] = True
+        np.testing.assert_array_equal(o[inner], r[inner])
+        edge = ~known.astype(bool) & ~inner
+        changed += int((np.abs(o - r)[edge] > 0).sum())
+    assert changed > 0
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
