@@ -256,6 +256,60 @@ def gmrf_study(S, L=32):
                         print(json.dumps(out), flush=True)
 
 
+def boundary_study(S, Ls, kappa=0.2, band=4, inner=8):
+    """Replicate auxiliary nodes (Sec. 2.5) against open boundaries.  S
+    configurations of L x L WM(kappa, nu) data (mean 50, std 10), case a:
+    33 % random gaps, b: 66 %; all S as one batch (one grid each), run once
+    with each boundary from the same seed: e_s, T-hat by SEM (open-boundary
+    table), Savitzky-Golay equilibration (n_f = 5, n_fit = 20), M = 100
+    recorded sweeps.  Errors (GPU validation measures) over all gaps, the
+    gaps on the grid's edge, those within ``band`` sites of it, and those
+    more than ``inner`` sites in.  One JSON line per (L, nu, case, boundary)."""
+    import torch
+
+    import mprgen
+    from paper_1710_03038_amd import mpr as M
+    from paper_1710_03038_amd.etable import load_table
+
+    table = load_table()
+    dev = torch.device("cuda:0")
+    for L in Ls:
+        yy, xx = np.mgrid[0:L, 0:L]
+        dist = np.minimum(np.minimum(yy, L - 1 - yy), np.minimum(xx, L - 1 - xx))
+        regions = {"all": np.ones((L, L), bool), "edge": dist == 0, "band": dist < band, "interior": dist >= inner}
+        for nu in (0.5, 0.25):
+            for case in ("a", "b"):
+                grids, zs = [], []
+                for s in range(S):
+                    base = 400000 + 1000 * s + int(nu * 100) + ord(case) + 7 * L
+                    z = mprgen.matern_field(L, L, kappa, nu, base, mean=50.0, std=10.0)
+                    known = mprgen.mask_random(L, L, {"a": 0.33, "b": 0.66}[case], base + 1)
+                    grids.append((torch.from_numpy(z).to(dev), torch.from_numpy(known).to(dev), 1))
+                    zs.append(z)
+                zsub = {r: [torch.from_numpy(np.where(m, z, np.nan)).to(dev) for z in zs]
+                        for r, m in regions.items()}
+                for bc in ("open", "replicate"):
+                    f = M.Field(grids, M.default_params(dtype="fp32", seed=4242, boundary=bc))
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
+                    T, _ = M.match_T(e_s, table[0], table[1])
+                    n, _, _ = f.equilibrate(T, n_f=5, n_fit=20, i_max=2000)
+                    zh, _, _ = f.fill(T, 0, 100, 1)
+                    torch.cuda.synchronize()
+                    secs = time.perf_counter() - t0
+                    out = {"study": "boundary", "L": L, "kappa": kappa, "nu": nu, "case": case, "S": S,
+                           "boundary": bc, "eq_sweeps": int(n), "ms_per_batch": 1e3 * secs}
+                    for r in regions:
+                        ms = [f.validation_measures(g, zsub[r][g], zh[g]) for g in range(S)]
+                        out[r] = {"MAAE": float(np.mean([m["AAE"] for m in ms])),
+                                  "MRASE": float(np.mean([m["RASE"] for m in ms])),
+                                  "MR_pct": 100 * float(np.mean([m["R"] for m in ms])),
+                                  "sites": int(np.mean([m["P"] for m in ms]))}
+                    f.close()
+                    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=256 << 20, reps=10):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters of rocprofv3 to bytes."""
@@ -344,7 +398,7 @@ def fill_mae(W, zh):
     return err / n
 
 
-def cpu_baseline(W, T, budget_s=10.0, max_side=1024):
+def cpu_baseline(W, T, budget_s=10.0, max_side=1024, boundary="open"):
     """The FP64 NumPy oracle timed on this host on a bounded sample of the
     same workload: hybrid sweeps (with the a-rule) of its grids in order,
     each cut to at most max_side x max_side, until budget_s has elapsed."""
@@ -361,7 +415,8 @@ def cpu_baseline(W, T, budget_s=10.0, max_side=1024):
         s = 0
         t0 = time.perf_counter()
         while s < 2 or (time.perf_counter() - t0 < budget_s - spent and s < 1000):
-            phi, _, _, _ = om.run_sweeps(phi, kc, T[g], 1.0, 0.5, W["seed"], s, 1, [0], g, adapt=True)
+            phi, _, _, _ = om.run_sweeps(phi, kc, T[g], 1.0, 0.5, W["seed"], s, 1, [0], g, adapt=True,
+                                         boundary=boundary)
             s += 1
         spent += time.perf_counter() - t0
         done += s * P
@@ -385,12 +440,15 @@ def main():
                     help="keep the library's default launch shape (for profiling runs, whose timing would sway "
                          "the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--study", choices=["relaxation", "validation", "gmrf"], default=None,
+    ap.add_argument("--boundary", choices=["open", "replicate"], default="open",
+                    help="sweep boundary: open, or the replicate auxiliary nodes of Sec. 2.5")
+    ap.add_argument("--study", choices=["relaxation", "validation", "gmrf", "boundary"], default=None,
                     help="relaxation: energy relaxation of the hybrid, restricted and standard Metropolis updates "
                          "and their Savitzky-Golay equilibration points (L x L Whittle-Matern field, p gaps); "
                          "validation: the paper's MPR validation measures on WM(0.2, nu) data, one JSON line per "
                          "(L, nu, case); gmrf: MPR against the GMRF pair interaction on Gaussian and lognormal "
-                         "WM data, L = 32")
+                         "WM data, L = 32; boundary: replicate auxiliary nodes against open boundaries, "
+                         "errors at the edge and in the interior")
     ap.add_argument("--Ls", type=int, nargs="+", default=[256, 512, 1024])
     ap.add_argument("--S", type=int, default=0, help="configurations per row (0: 100 at L <= 256, then fewer)")
     ap.add_argument("--L", type=int, default=512)
@@ -417,6 +475,9 @@ def main():
     if args.study == "gmrf":
         gmrf_study(args.S or 100)
         return
+    if args.study == "boundary":
+        boundary_study(args.S or 100, args.Ls)
+        return
 
     import torch
 
@@ -437,7 +498,7 @@ def main():
     updates = sweeps * P
 
     prm32 = M.default_params(dtype="fp32", seed=W["seed"], sweeps_per_pass=args.sweeps_per_pass,
-                             tile_x=args.tile[0], tile_y=args.tile[1])
+                             tile_x=args.tile[0], tile_y=args.tile[1], boundary=args.boundary)
     dt32, out32, (kms, kl, kss) = run_arm(M, dev_grids, W, table, prm32, args.steps, args.warmup, graph=True,
                                           tune=not args.no_autotune)
     mae32 = fill_mae(W, out32[0])
@@ -448,7 +509,7 @@ def main():
     fp64 = None
     if args.fp64_steps > 0:
         torch.cuda.empty_cache()
-        prm64 = M.default_params(dtype="fp64", seed=W["seed"], sweeps_per_pass=1)
+        prm64 = M.default_params(dtype="fp64", seed=W["seed"], sweeps_per_pass=1, boundary=args.boundary)
         dt64, out64, _ = run_arm(M, dev_grids, W, table, prm64, args.fp64_steps, 0, graph=False)
         mae64 = fill_mae(W, out64[0])
         fp64 = {"spin_updates_per_s": updates / dt64, "realisations_per_s": records / dt64,
@@ -462,9 +523,10 @@ def main():
     useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
     achieved = useful_updates * VALU_INST_PER_UPDATE / ksec / 1e12 if kms > 0 else None
     default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
+                      and args.boundary == "open"
                       and "MPR_SWEEP_THREADS" not in os.environ and tuple(out32[5]) in ((8, 1024), (0, None)))
     cfg = dict(W["config"])
-    cfg.update({"workload": args.workload, "gap_fraction": p, "n_eq": W["n_eq"], "n_samp": W["n_samp"],
+    cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"], "n_samp": W["n_samp"],
                 "stride": W["stride"], "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
                 "sweeps_per_pass_max": prm32.sweeps_per_pass or 8,
                 "autotuned_sweeps_per_pass_threads": list(out32[5]), "fill_graph": True,
@@ -500,7 +562,7 @@ def main():
     }
     if not args.no_cpu:
         os.environ.setdefault("OMP_NUM_THREADS", "1")
-        v, dt, used = cpu_baseline(W, T_hat, budget_s=args.cpu_seconds)
+        v, dt, used = cpu_baseline(W, T_hat, budget_s=args.cpu_seconds, boundary=args.boundary)
         desc = ", ".join(f"{s} sweeps of {sh[0]}x{sh[1]}" for sh, s in used[:4]) + (" ..." if len(used) > 4 else "")
         res["cpu_baseline"] = {"value": v, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
                                "sample": f"{desc} (1 chain each, from the hot start, a-rule on), FP64 NumPy oracle, "

@@ -230,9 +230,11 @@ mpr_status mpr_fill(mpr_ctx *ctx, const double *T, int32_t n_eq, int32_t n_samp,
  * |eps|/Z), RASE (sqrt of mean eps^2), R (linear correlation coefficient
  * of Z and Z_hat), P (number of prediction sites), mean Z, mean Z_hat.
  * z_true: device [ny*nx], the complete field (the values the gaps hide);
+ * a gap site whose z_true is NaN is left out, which scores a subset of the
+ * gaps (an edge band, or held-out samples in a cross-validation).
  * zhat: device [ny*nx], e.g. this grid's part of mpr_fill's output.
  * FP64, deterministic order.  Synchronises the stream.  Errors: MPR_E_ARG,
- * MPR_E_DEGENERATE (no prediction sites), MPR_E_HIP.
+ * MPR_E_DEGENERATE (no prediction site left; out[5] = 0), MPR_E_HIP.
  */
 mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_true, const double *zhat,
                                    double *out);

@@ -986,6 +986,8 @@ mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_t
                                ctx->v.out, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(out, ctx->v.out, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (out[5] == 0.0)
+    return fail(ctx, MPR_E_DEGENERATE, "grid " + std::to_string(grid) + ": no prediction site with a finite z_true");
   return MPR_OK;
 }
 

@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   double s[kMeasureSums] = {};
   for (int64_t i = base + threadIdx.x; i < min(base + (int64_t)kChunk, n); i += kThreads) {
-    if (known[i]) continue;
+    if (known[i] || __builtin_isnan(z[i])) continue;  // a NaN in z_true leaves the site out
     const double zt = z[i], zp = zh[i], e = zt - zp, a = zt - shift, b = zp - shift;
     s[0] += 1.0;
     s[1] += fabs(e);

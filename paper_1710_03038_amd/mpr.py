@@ -284,7 +284,8 @@ class Field:
 
     def validation_measures(self, grid, z_true, zhat):
         """mpr_validation_measures: AAE, ARE, AARE, RASE, R (Sec. 3.3) of
-        zhat against the complete field z_true over the grid's gaps."""
+        zhat against the complete field z_true over the grid's gaps (gap
+        sites where z_true is NaN are left out)."""
         torch = self._torch
         ny, nx, _ = self.shapes[grid]
         zt = torch.as_tensor(z_true, dtype=torch.float64).to(self.device).contiguous()

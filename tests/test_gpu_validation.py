@@ -37,6 +37,19 @@ def test_measures_match_oracle():
     assert got["P"] == ref["P"]
     for k in ("AAE", "ARE", "AARE", "RASE", "R"):
         assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-15), k
+    # a subset of the gaps: NaN in z_true leaves a site out
+    sub = np.zeros(z.shape, dtype=bool)
+    sub[:3, :] = sub[-3:, :] = sub[:, :3] = sub[:, -3:] = True
+    zt = np.where(sub, z, np.nan)
+    got = f.validation_measures(0, zt, zhat)
+    ref = om.validation_measures(z, zhat, (known == 0) & sub)
+    assert got["P"] == ref["P"] < int((known == 0).sum())
+    for k in ("AAE", "ARE", "AARE", "RASE", "R"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-15), k
+    from paper_1710_03038_amd import mpr as M
+    with pytest.raises(M.MPRError) as ei:
+        f.validation_measures(0, np.full(z.shape, np.nan), zhat)
+    assert ei.value.status == M.MPR_E_DEGENERATE
     f.close()
 
 
