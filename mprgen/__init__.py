@@ -131,6 +131,22 @@ def mask_blocks(ny, nx, p, seed, block=16):
     return known
 
 
+def cv_folds(known, n_folds, seed):
+    """Fold ids for K-fold cross-validation: the sample sites (known != 0)
+    in a seeded random order, dealt round-robin into n_folds folds (sizes
+    differ by at most one).  Returns uint8 (ny, nx): the fold id at sample
+    sites, 255 at gaps."""
+    if not 2 <= n_folds <= 254:
+        raise ValueError("n_folds must be in [2, 254]")
+    known = np.asarray(known) != 0
+    idx = np.flatnonzero(known)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = rng.permutation(idx.size)
+    fold = np.full(known.size, 255, dtype=np.uint8)
+    fold[idx[order]] = (np.arange(idx.size) % n_folds).astype(np.uint8)
+    return fold.reshape(known.shape)
+
+
 def mask_clouds(ny, nx, p, seed, a_min=16.0, a_max=512.0):
     """Elliptical clouds (log-uniform semi-axes, uniform orientation and
     centre) added until the gap fraction reaches p."""

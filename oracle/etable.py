@@ -30,6 +30,13 @@ DEFAULT_PATH = os.path.join(HERE, "etable_L32.csv")
 GMRF_PATH = os.path.join(HERE, "etable_gmrf_L32.csv")
 
 
+def table_path(model=mpr.MPR, q=0.5):
+    """File of the oracle's table for a model (and, for MPR, q)."""
+    if model == mpr.GMRF:
+        return GMRF_PATH
+    return DEFAULT_PATH if q == 0.5 else os.path.join(HERE, f"etable_q{q:g}_L32.csv")
+
+
 def default_temperatures():
     return np.logspace(-5.0, math.log10(3.0), 46)
 
@@ -76,10 +83,11 @@ def save_table(path, T, e, err, header):
             f.write(f"{t:.17g},{v:.17g},{s:.6g}\n")
 
 
-def load_table(path=None, model=mpr.MPR):
-    """Return (T, e, e_stderr) arrays of a table file (default: the model's)."""
+def load_table(path=None, model=mpr.MPR, q=0.5):
+    """Return (T, e, e_stderr) arrays of a table file (default: the model's
+    at q)."""
     if path is None:
-        path = GMRF_PATH if model == mpr.GMRF else DEFAULT_PATH
+        path = table_path(model, q)
     rows = []
     with open(path) as f:
         for line in f:
@@ -91,16 +99,18 @@ def load_table(path=None, model=mpr.MPR):
 
 
 if __name__ == "__main__":
-    # python -m oracle.etable [processes] [mpr|gmrf]
+    # python -m oracle.etable [processes] [mpr|gmrf] [q]
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     procs = int(sys.argv[1]) if len(sys.argv) > 1 else 8
     model = sys.argv[2] if len(sys.argv) > 2 else mpr.MPR
-    kw = dict(L=32, chains=8, n_eq=300, n_meas=2400 if model == mpr.GMRF else 900, q=0.5, seed=7, model=model)
+    q = float(sys.argv[3]) if len(sys.argv) > 3 else 0.5
+    n_meas = 2400 if (model == mpr.GMRF or q != 0.5) else 900
+    kw = dict(L=32, chains=8, n_eq=300, n_meas=n_meas, q=q, seed=7, model=model)
     T, e, err = build_table(processes=procs, **kw)
     order_ok = bool(np.all(np.diff(e) > 0))
-    path = GMRF_PATH if model == mpr.GMRF else DEFAULT_PATH
+    path = table_path(model, q)
     what = ("Equilibrium GMRF specific energy e(T) = <H>/N_GP, H_ij = 1 - dphi^2/(2 pi^2), open boundaries,"
-            if model == mpr.GMRF else "Equilibrium MPR specific energy e(T) = <H>/N_GP, q = 1/2, open boundaries,")
+            if model == mpr.GMRF else f"Equilibrium MPR specific energy e(T) = <H>/N_GP, q = {q:g}, open boundaries,")
     save_table(path, T, e, err, [
         what,
         "from unconditional CPU-oracle chains (oracle/etable.py): "

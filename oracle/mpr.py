@@ -54,6 +54,14 @@ constant -1.  The update then depends on the site's previous value, so it
 no longer satisfies detailed balance for Eq. (3); the open boundary is the
 default.
 
+Cross-validation of q (Sec. 6 proposes choosing q in [0, 1/2] this way;
+the procedure is this project's reading): the samples are split into K
+folds; for each candidate q and fold, the method runs with that fold's
+samples hidden, each candidate with its own e(T) table, and the candidate
+with the least pooled absolute error on the held-out samples wins (ties:
+the larger q).  q = 0 is left out: it makes every state equally likely.
+The equilibration of each fit is a fixed sweep count with the a-rule.
+
 The GMRF variant (Sec. 4.4) replaces the pair interaction by
 H_ij = 1 - dphi^2 / (2 pi^2) on the same non-periodic angles; its
 over-relaxation reflects phi about the mean of its neighbours, kept only
@@ -635,3 +643,75 @@ def mae(z_true, z_hat, gaps):
     """Average absolute error over the prediction sites (Sec. 3, AAE)."""
     gaps = np.asarray(gaps, dtype=bool)
     return float(np.abs(np.asarray(z_true)[gaps] - np.asarray(z_hat)[gaps]).mean())
+
+
+# --------------------------------------------------------------------------
+# Selection of q by cross-validation (Sec. 6)
+# --------------------------------------------------------------------------
+def cv_masks(known, fold, k):
+    """Masks of fold k: the training samples (every sample whose fold id is
+    not k) and the held-out ones (fold id k), which become gaps and are
+    scored."""
+    known = np.asarray(known, dtype=bool)
+    held = known & (np.asarray(fold) == k)
+    return known & ~held, held
+
+
+def cv_pool(parts):
+    """Pool held-out errors over the folds.  parts: per fold (sum |eps|,
+    sum eps^2, count).  Returns (AAE, RASE) over all held-out samples: each
+    sample is held out once, so this is the K-fold estimate of the
+    prediction error."""
+    s_abs = sum(p[0] for p in parts)
+    s_sq = sum(p[1] for p in parts)
+    n = sum(p[2] for p in parts)
+    if n == 0:
+        raise OracleError("no held-out samples")
+    return s_abs / n, math.sqrt(s_sq / n)
+
+
+def cv_best(qs, scores):
+    """Index of the candidate with the least score; among equal scores the
+    largest q (nearest the paper's q = 1/2)."""
+    qs = np.asarray(qs, dtype=np.float64)
+    scores = np.asarray(scores, dtype=np.float64)
+    low = scores == scores.min()
+    return int(np.flatnonzero(low)[np.argmax(qs[low])])
+
+
+def cv_select_q(z, known, fold, n_folds, qs, tables, n_eq, n_samp, stride, seed=0, chains=1, a_targ=0.3, k_a=3.0,
+                boundary=OPEN):
+    """Choose q in (0, 1/2] by K-fold cross-validation (the extension
+    proposed in Sec. 6).  For candidate i and fold k the fold's samples are
+    hidden and the method runs on the rest: Eq. (2) on the training
+    samples, e_s (Eq. 4) at q_i, T-hat by SEM on candidate i's own e(T)
+    table, then ``fill`` (hot start, n_eq sweeps with the a-rule, n_samp
+    sampling sweeps, every stride-th recorded) on grid id i * n_folds + k.
+    The score of a candidate is the pooled AAE (and RASE) over the
+    held-out samples.
+
+    fold: integer fold id in [0, n_folds) at every sample site (ignored at
+    gaps).  tables: per candidate (tab_T, tab_e).
+    Returns dict(aae (n_q,), rase (n_q,), T (n_q, n_folds), best index).
+    """
+    z = np.asarray(z, dtype=np.float64)
+    known = np.asarray(known, dtype=bool)
+    aae, rase, Ts = [], [], []
+    for i, q in enumerate(qs):
+        tab_T, tab_e = tables[i]
+        parts, Tq = [], []
+        for k in range(n_folds):
+            train, held = cv_masks(known, fold, k)
+            phi_s, _, _ = transform(z, train)
+            e_s, _, _ = sample_specific_energy(phi_s, train, q)
+            T, _ = match_T(e_s, tab_T, tab_e)
+            out = fill(z, train, T[0], n_eq, n_samp, stride, q=q, seed=seed, chains=chains, grid=i * n_folds + k,
+                       a_targ=a_targ, k_a=k_a, boundary=boundary)
+            eps = z[held] - out["z_hat"][held]
+            parts.append((float(np.abs(eps).sum()), float((eps * eps).sum()), int(held.sum())))
+            Tq.append(float(T[0]))
+        a, r = cv_pool(parts)
+        aae.append(a)
+        rase.append(r)
+        Ts.append(Tq)
+    return dict(aae=np.array(aae), rase=np.array(rase), T=np.array(Ts), best=cv_best(qs, aae))
