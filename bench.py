@@ -310,6 +310,66 @@ def boundary_study(S, Ls, kappa=0.2, band=4, inner=8):
                     print(json.dumps(out), flush=True)
 
 
+def qcv_study(S, L=64, qs=(0.125, 0.25, 0.375, 0.5), n_folds=5):
+    """Choice of q by cross-validation (the extension proposed in Sec. 6).
+    Data: L x L fields, S configurations each, case a (33 % random gaps):
+    Gaussian 50 + 10 WM(0.2, 0.5), rough Gaussian 50 + 10 WM(0.5, 0.25),
+    and lognormal exp(5 + WM(0.5, 0.5)).  Per configuration: mpr_cv_select_q
+    over the candidates with n_folds folds of the samples (FP32, 100 + 100
+    sweeps per fit, every sweep recorded), timed; then the method at every
+    candidate on the true gaps, all S x n_q fits as one batch with per-grid
+    q (e_s, SEM on each q's table, Savitzky-Golay equilibration, M = 100).
+    One JSON line per data kind: mean CV score and true AAE per q, how often
+    CV picked each q, and the true AAE at the CV choice, at q = 1/2 and at
+    the best q in hindsight."""
+    import torch
+
+    import mprgen
+    from paper_1710_03038_amd import mpr as M
+    from paper_1710_03038_amd.etable import load_table
+
+    dev = torch.device("cuda:0")
+    tables = [load_table(q=q)[:2] for q in qs]
+    nq = len(qs)
+    kinds = {"gaussian": (0.2, 0.5, lambda y: 50.0 + 10.0 * y), "rough": (0.5, 0.25, lambda y: 50.0 + 10.0 * y),
+             "lognormal": (0.5, 0.5, lambda y: np.exp(5.0 + y))}
+    for kind, (kappa, nu, tr) in kinds.items():
+        data = []
+        for s in range(S):
+            base = 810000 + 1000 * s + 7 * len(kind)
+            z = tr(mprgen.matern_field(L, L, kappa, nu, base, mean=0.0, std=1.0))
+            known = mprgen.mask_random(L, L, 0.33, base + 1)
+            fold = mprgen.cv_folds(known, n_folds, base + 2)
+            data.append((torch.from_numpy(z).to(dev), torch.from_numpy(known).to(dev), torch.from_numpy(fold).to(dev)))
+        cv, secs = [], []
+        for s, (zt, kt, ft) in enumerate(data):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cv.append(M.cv_select_q(zt, kt, ft, n_folds, qs, tables, 100, 100, 1,
+                                    params=M.default_params(dtype="fp32", seed=77 + s)))
+            secs.append(time.perf_counter() - t0)
+        grids = [(zt, kt, 1) for zt, kt, _ in data for _ in qs]
+        f = M.Field(grids, M.default_params(dtype="fp32", seed=991))
+        f.set_grid_q(np.tile(np.asarray(qs, dtype=np.float64), S))
+        e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
+        T = np.array([M.match_T(e_s[g:g + 1], *tables[g % nq])[0][0] for g in range(S * nq)])
+        n, _, _ = f.equilibrate(T, n_f=5, n_fit=20, i_max=2000)
+        zh, _, _ = f.fill(T, 0, 100, 1)
+        true = np.array([f.validation_measures(g, data[g // nq][0], zh[g])["AAE"] for g in range(S * nq)]).reshape(S, nq)
+        f.close()
+        pick = np.array([c["best"] for c in cv])
+        out = {"study": "qcv", "data": kind, "kappa": kappa, "nu": nu, "L": L, "S": S, "folds": n_folds,
+               "q": list(qs), "cv_aae_mean": [float(np.mean([c["aae"][i] for c in cv])) for i in range(nq)],
+               "picked": [int((pick == i).sum()) for i in range(nq)],
+               "true_aae_mean": [float(v) for v in true.mean(axis=0)],
+               "true_aae_at_cv_choice": float(true[np.arange(S), pick].mean()),
+               "true_aae_at_q_half": float(true[:, qs.index(0.5)].mean()),
+               "true_aae_at_best_q": float(true.min(axis=1).mean()),
+               "T_hat_over_q2": [float(np.mean([c["T_mean"][i] for c in cv]) / qs[i] ** 2) for i in range(nq)],
+               "eq_sweeps": int(n), "ms_per_cv": 1e3 * float(np.mean(secs)), "fits_per_cv": nq * n_folds}
+        print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=256 << 20, reps=10):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters of rocprofv3 to bytes."""
@@ -442,13 +502,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--boundary", choices=["open", "replicate"], default="open",
                     help="sweep boundary: open, or the replicate auxiliary nodes of Sec. 2.5")
-    ap.add_argument("--study", choices=["relaxation", "validation", "gmrf", "boundary"], default=None,
+    ap.add_argument("--study", choices=["relaxation", "validation", "gmrf", "boundary", "qcv"], default=None,
                     help="relaxation: energy relaxation of the hybrid, restricted and standard Metropolis updates "
                          "and their Savitzky-Golay equilibration points (L x L Whittle-Matern field, p gaps); "
                          "validation: the paper's MPR validation measures on WM(0.2, nu) data, one JSON line per "
                          "(L, nu, case); gmrf: MPR against the GMRF pair interaction on Gaussian and lognormal "
                          "WM data, L = 32; boundary: replicate auxiliary nodes against open boundaries, "
-                         "errors at the edge and in the interior")
+                         "errors at the edge and in the interior; qcv: the choice of q by cross-validation on "
+                         "Gaussian, rough and lognormal data")
     ap.add_argument("--Ls", type=int, nargs="+", default=[256, 512, 1024])
     ap.add_argument("--S", type=int, default=0, help="configurations per row (0: 100 at L <= 256, then fewer)")
     ap.add_argument("--L", type=int, default=512)
@@ -477,6 +538,9 @@ def main():
         return
     if args.study == "boundary":
         boundary_study(args.S or 100, args.Ls)
+        return
+    if args.study == "qcv":
+        qcv_study(args.S or 40)
         return
 
     import torch

@@ -240,6 +240,52 @@ mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_t
                                    double *out);
 
 /*
+ * Give every grid of the context its own modification factor q of Eq. (3)
+ * (q: host [n_grids], each in (0, 0.5]), in place of mpr_params.q.  The
+ * sample and state specific energies and the sweeps of each grid then use
+ * its q; a batch can hold fits of several q, as the q selection of Sec. 6
+ * needs.  Kept by mpr_reinit.  Errors: MPR_E_ARG, MPR_E_STATE (GMRF
+ * interaction, or a context created with q = 1), MPR_E_HIP.  Synchronises
+ * the stream.
+ */
+mpr_status mpr_set_grid_q(mpr_ctx *ctx, const double *q);
+
+/*
+ * Choose q in (0, 1/2] by K-fold cross-validation, the extension proposed
+ * in Sec. 6.  The sample sites are split into n_folds folds by `fold`; for
+ * candidate i and fold k, the fold's samples are hidden and the method runs
+ * on the rest: Eq. (2) on the training samples, e_s (Eq. 4) at q[i], T-hat
+ * by specific energy matching on candidate i's own table (as mpr_match_T; a
+ * clamped T-hat is used as it is), then mpr_fill(n_eq, n_samp, stride).
+ * All n_q * n_folds fits run as one batch (fit (i, k) is grid
+ * i * n_folds + k of the batch, which keys its random stream).  The score
+ * of a candidate is the AAE over all held-out samples (each is held out
+ * once); the least score wins, and among equal scores the larger q.
+ *
+ * grid: the data (device z and known, as for mpr_init_field); chains =
+ *   chains per fit.  p: the fits' parameters (p->q is ignored; the MPR
+ *   interaction is required).
+ * fold: device [ny*nx] uint8: the fold of each sample site; a sample whose
+ *   id is >= n_folds is never held out; ignored at gaps.  2 <= n_folds <= 254.
+ * q: host [n_q], the candidates.  tab_T, tab_e: host [n_q] pointers to each
+ *   candidate's e(T) table (host arrays of n_tab[i] >= 2 values, as for
+ *   mpr_match_T).
+ * workspace, ws_bytes: device memory for the batch and its fold masks,
+ *   256-byte aligned; with workspace == NULL only *ws_bytes is set.
+ * score: host [n_q * 3] or NULL: pooled AAE, pooled RASE over the held-out
+ *   samples, and the mean T-hat over the folds.  best: host, the chosen
+ *   candidate's index.
+ * Errors: MPR_E_ARG, MPR_E_SHAPE, MPR_E_WORKSPACE, MPR_E_DEGENERATE (a fold
+ * with no held-out sample, or training samples of one value),
+ * MPR_E_NOPAIRS, MPR_E_HIP; the message is mpr_last_error(NULL).
+ * Synchronises the stream.
+ */
+mpr_status mpr_cv_select_q(const mpr_grid *grid, const mpr_params *p, const uint8_t *fold, int32_t n_folds,
+                           const double *q, int32_t n_q, const double *const *tab_T, const double *const *tab_e,
+                           const int32_t *n_tab, int32_t n_eq, int32_t n_samp, int32_t stride, void *workspace,
+                           size_t *ws_bytes, void *hip_stream, double *score, int32_t *best);
+
+/*
  * Set the context up again from the caller's z and known buffers given to
  * mpr_init_field (same shapes; the values and the gap pattern may have
  * changed): Eq. (2) bounds, the hot start of Algorithm 2, steps 1.8 and

@@ -190,6 +190,8 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
     d.site_off = pl.sites;
     d.n_pairs = (int64_t)G.ny * (G.nx - 1) + (int64_t)G.nx * (G.ny - 1);
     d.zmin = d.zmax = NAN;
+    d.q = p->q;
+    d.inv_q = 1.0 / p->q;
     pl.n_items += (int64_t)G.chains * d.tiles_x * d.tiles_y;
     pl.n_tiles += (int64_t)d.tiles_x * d.tiles_y;
     pl.plan_entries += (int64_t)d.tiles_x * d.tiles_y * d.plan_cap;
@@ -342,8 +344,6 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.adapt_every = c->p.adapt_every;
   A.a_targ = c->p.a_targ;
   A.k_a = c->p.k_a;
-  A.q = (P)c->p.q;
-  A.inv_q = (P)(1.0 / c->p.q);
   A.src = (const P *)c->v.st[c->cur];
   A.dst = (P *)c->v.st[c->cur ^ 1];
   A.beta = c->v.beta;
@@ -469,11 +469,11 @@ mpr_status reduce_energy(mpr_ctx *c, int what, std::vector<double> &out) {
   const int units = what ? c->plan.total_chains : c->n_grids;
   const int64_t blocks = what ? c->plan.n_cblocks : c->plan.n_sblocks;
   if (c->p.dtype == MPR_FP64) {
-    HIP_TRY(c, launch_energy<double>(c->v.gd, c->n_grids, blocks, what, (const double *)c->v.st[c->cur], c->p.q,
+    HIP_TRY(c, launch_energy<double>(c->v.gd, c->n_grids, blocks, what, (const double *)c->v.st[c->cur],
                                      c->p.model, c->v.part, c->stream));
   } else {
     HIP_TRY(c, launch_energy<float>(c->v.gd, c->n_grids, blocks, what, (const float *)c->v.st[c->cur],
-                                    (float)c->p.q, c->p.model, c->v.part, c->stream));
+                                    c->p.model, c->v.part, c->stream));
   }
   HIP_TRY(c, launch_energy_final(c->v.gd, c->n_grids, what, units, c->v.part, c->v.out, c->stream));
   out.resize((size_t)units * 2);
@@ -989,6 +989,121 @@ mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_t
   if (out[5] == 0.0)
     return fail(ctx, MPR_E_DEGENERATE, "grid " + std::to_string(grid) + ": no prediction site with a finite z_true");
   return MPR_OK;
+}
+
+mpr_status mpr_set_grid_q(mpr_ctx *ctx, const double *q) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (!q) return fail(ctx, MPR_E_ARG, "q is NULL");
+  if (ctx->p.model != MPR_MODEL_MPR) return fail(ctx, MPR_E_STATE, "q has no role in the GMRF interaction");
+  if (ctx->p.q == 1.0) return fail(ctx, MPR_E_STATE, "the context was created with q = 1 (test mode)");
+  for (int g = 0; g < ctx->n_grids; ++g)
+    if (!(q[g] > 0.0 && q[g] <= 0.5)) return fail(ctx, MPR_E_ARG, "grid " + std::to_string(g) + ": q must be in (0, 0.5]");
+  const mpr_status st = close_pending(ctx);
+  if (st != MPR_OK) return st;
+  for (int g = 0; g < ctx->n_grids; ++g) {
+    ctx->plan.gd[g].q = q[g];
+    ctx->plan.gd[g].inv_q = 1.0 / q[g];
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->v.gd, ctx->plan.gd.data(), sizeof(GridDesc) * ctx->n_grids,
+                              hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPR_OK;
+}
+
+mpr_status mpr_cv_select_q(const mpr_grid *grid, const mpr_params *p, const uint8_t *fold, int32_t n_folds,
+                           const double *q, int32_t n_q, const double *const *tab_T, const double *const *tab_e,
+                           const int32_t *n_tab, int32_t n_eq, int32_t n_samp, int32_t stride, void *workspace,
+                           size_t *ws_bytes, void *hip_stream, double *score, int32_t *best) {
+  g_thread_err.clear();
+  if (!grid || !p || !ws_bytes) return fail(nullptr, MPR_E_ARG, "grid, p and ws_bytes are required");
+  if (n_folds < 2 || n_folds > 254) return fail(nullptr, MPR_E_ARG, "n_folds must be in [2, 254]");
+  if (n_q < 1 || !q) return fail(nullptr, MPR_E_ARG, "need at least one candidate q");
+  for (int i = 0; i < n_q; ++i)
+    if (!(q[i] > 0.0 && q[i] <= 0.5)) return fail(nullptr, MPR_E_ARG, "candidate q must be in (0, 0.5]");
+  if (p->model != MPR_MODEL_MPR) return fail(nullptr, MPR_E_ARG, "q selection needs the MPR interaction");
+  if (n_eq < 0 || n_samp < 1 || stride < 1 || n_samp / stride < 1)
+    return fail(nullptr, MPR_E_ARG, "need n_eq >= 0 and n_samp / stride >= 1");
+  const int nb = n_q * n_folds;
+  if ((int64_t)nb * grid->chains > 0x7fffffff) return fail(nullptr, MPR_E_SHAPE, "too many fits");
+  mpr_params pq = *p;
+  pq.q = q[0];
+  // One batch of n_q * n_folds copies of the grid: fit (i, k) = grid i * n_folds + k.
+  std::vector<mpr_grid> batch((size_t)nb, *grid);
+  size_t ctx_bytes = 0;
+  mpr_status st = mpr_init_field(nullptr, batch.data(), nb, &pq, nullptr, &ctx_bytes, nullptr);
+  if (st != MPR_OK) return st;
+  const int64_t n = (int64_t)grid->nx * grid->ny;
+  const size_t off_mask = align_up(ctx_bytes, 256);
+  const size_t off_zt = align_up(off_mask + (size_t)n_folds * n, 256);
+  const size_t off_zh = align_up(off_zt + sizeof(double) * n_folds * n, 256);
+  const size_t total = align_up(off_zh + sizeof(double) * nb * n, 256);
+  if (!workspace) {
+    *ws_bytes = total;
+    return MPR_OK;
+  }
+  if (*ws_bytes < total)
+    return fail(nullptr, MPR_E_WORKSPACE, "workspace of " + std::to_string(*ws_bytes) + " bytes, need " +
+                                              std::to_string(total));
+  if (((uintptr_t)workspace) & 255) return fail(nullptr, MPR_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!fold || !grid->z || !grid->known) return fail(nullptr, MPR_E_ARG, "z, known and fold must be device pointers");
+  if (!tab_T || !tab_e || !n_tab) return fail(nullptr, MPR_E_ARG, "tables are required");
+  for (int i = 0; i < n_q; ++i)
+    if (!tab_T[i] || !tab_e[i] || n_tab[i] < 2) return fail(nullptr, MPR_E_ARG, "candidate table missing or short");
+  if (!best) return fail(nullptr, MPR_E_ARG, "best is NULL");
+  unsigned char *base = (unsigned char *)workspace;
+  uint8_t *masks = base + off_mask;
+  double *zt = (double *)(base + off_zt), *zh = (double *)(base + off_zh);
+  const hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t he = launch_cv_prepare(grid->z, grid->known, fold, n_folds, n, masks, zt, s);
+  if (he != hipSuccess) return hip_fail(nullptr, he, "cross-validation fold masks");
+  for (int g = 0; g < nb; ++g) batch[g].known = masks + (int64_t)(g % n_folds) * n;
+
+  mpr_ctx *c = nullptr;
+  st = mpr_init_field(&c, batch.data(), nb, &pq, workspace, &ctx_bytes, hip_stream);
+  if (st != MPR_OK) return st;
+  auto done = [&](mpr_status r) {
+    if (r != MPR_OK) g_thread_err = c->err;
+    mpr_destroy(c);
+    return r;
+  };
+  std::vector<double> qg((size_t)nb), e((size_t)nb), T((size_t)nb);
+  for (int g = 0; g < nb; ++g) qg[g] = q[g / n_folds];
+  if ((st = mpr_set_grid_q(c, qg.data())) != MPR_OK) return done(st);
+  if ((st = mpr_specific_energy(c, MPR_SAMPLE_PAIRS, e.data(), nullptr)) != MPR_OK) return done(st);
+  for (int g = 0; g < nb; ++g) {
+    const int i = g / n_folds;
+    mpr_status item = MPR_OK;
+    st = mpr_match_T(&e[g], 1, tab_T[i], tab_e[i], n_tab[i], &T[g], &item);
+    if (st != MPR_OK && st != MPR_E_RANGE) {  // a clamped T-hat is used as it is, as in a fill
+      c->err = "fit " + std::to_string(g) + ": " + g_thread_err;
+      return done(st);
+    }
+  }
+  if ((st = mpr_fill(c, T.data(), n_eq, n_samp, stride, zh, nullptr, nullptr)) != MPR_OK) return done(st);
+  std::vector<double> aae((size_t)n_q, 0.0), sq((size_t)n_q, 0.0), cnt((size_t)n_q, 0.0), tm((size_t)n_q, 0.0);
+  for (int g = 0; g < nb; ++g) {
+    const int i = g / n_folds, k = g % n_folds;
+    double m[8];
+    if ((st = mpr_validation_measures(c, g, zt + (int64_t)k * n, zh + (int64_t)g * n, m)) != MPR_OK) return done(st);
+    aae[i] += m[0] * m[5];         // sum |eps| of the fold
+    sq[i] += m[3] * m[3] * m[5];   // sum eps^2
+    cnt[i] += m[5];
+    tm[i] += T[g] / n_folds;
+  }
+  int b = 0;
+  for (int i = 0; i < n_q; ++i) {
+    aae[i] /= cnt[i];
+    sq[i] = std::sqrt(sq[i] / cnt[i]);
+    if (score) {
+      score[i * 3] = aae[i];
+      score[i * 3 + 1] = sq[i];
+      score[i * 3 + 2] = tm[i];
+    }
+    // least pooled AAE; among equal ones the larger q
+    if (aae[i] < aae[b] || (aae[i] == aae[b] && q[i] > q[b])) b = i;
+  }
+  *best = b;
+  return done(MPR_OK);
 }
 
 mpr_status mpr_reinit(mpr_ctx *ctx) {

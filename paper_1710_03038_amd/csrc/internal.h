@@ -30,6 +30,7 @@ struct GridDesc {
   int64_t n_gap;                   // gap sites per chain
   int64_t n_pairs;                 // N_GP of Eq. (5)
   double zmin, zmax;               // Eq. (2) over the samples; NaN without samples
+  double q, inv_q;                 // modification factor of Eq. (3) for this grid, and 1/q
 };
 
 // The end of a pass whose per-chain acceptance and energy sums are complete
@@ -67,7 +68,6 @@ struct SweepArgs {
   uint32_t record_mask, first_mask;
   int32_t adapt, adapt_every;      // a-rule (Algorithm 2, step 4.2)
   double a_targ, k_a;
-  P q, inv_q;
   const P *src;
   P *dst;
   const double *beta;              // per chain
@@ -114,7 +114,7 @@ hipError_t launch_init(const GridDesc *g, int n_grids, int64_t n_blocks, const d
                        const uint8_t *const *known, P *s0, P *s1, P q_unused, uint32_t k0, uint32_t k1,
                        hipStream_t s);
 template <typename P>
-hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q, int gmrf,
+hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, int gmrf,
                          double *part, hipStream_t s);
 hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
                                double *out, hipStream_t s);
@@ -129,6 +129,8 @@ hipError_t launch_set_phi(P *s0, P *s1, int64_t n, const double *in, hipStream_t
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
+hipError_t launch_cv_prepare(const double *z, const uint8_t *known, const uint8_t *fold, int n_folds, int64_t n,
+                             uint8_t *masks, double *zt, hipStream_t s);
 // Validation measures of one grid (kMeasureSums partial sums per chunk of
 // kChunk sites in part; eight results in out).
 constexpr int kMeasureSums = 10;

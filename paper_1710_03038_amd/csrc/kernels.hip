@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 
   V2 *cs = reinterpret_cast<V2 *>(smem);                         // (cos q phi, sin q phi)
   P *ph = reinterpret_cast<P *>(smem + 2 * plane * sizeof(V2));  // encoded angle
-  const P q = A.q, inv_q = A.inv_q;
+  const P q = (P)G.q, inv_q = (P)G.inv_q;
   const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
   const P *src = A.src + cbase;
 
@@ -876,11 +876,12 @@ template <typename P> __device__ __forceinline__ P pair_eps(P d, P q, int gmrf) 
 
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
-    k_energy(const GridDesc *grids, int n_grids, int what, const P *state, P q, int gmrf, double *part) {
+    k_energy(const GridDesc *grids, int n_grids, int what, const P *state, int gmrf, double *part) {
   __shared__ double red[kThreads / 64];
   const int64_t b = blockIdx.x;
   const int gi = find_by(grids, n_grids, b, what ? &GridDesc::cb_begin : &GridDesc::sb_begin);
   const GridDesc &G = grids[gi];
+  const P q = (P)G.q;
   const int nx = G.nx;
   const int64_t n = (int64_t)nx * G.ny;
   const int64_t per_chain = (n + kChunk - 1) / kChunk;
@@ -952,15 +953,15 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 template <typename P>
-hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, P q, int gmrf,
+hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, int gmrf,
                          double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, what, state, q, gmrf,
+  hipLaunchKernelGGL(k_energy<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, what, state, gmrf,
                      part);
   return hipGetLastError();
 }
-template hipError_t launch_energy<float>(const GridDesc *, int, int64_t, int, const float *, float, int, double *,
+template hipError_t launch_energy<float>(const GridDesc *, int, int64_t, int, const float *, int, double *,
                                          hipStream_t);
-template hipError_t launch_energy<double>(const GridDesc *, int, int64_t, int, const double *, double, int, double *,
+template hipError_t launch_energy<double>(const GridDesc *, int, int64_t, int, const double *, int, double *,
                                           hipStream_t);
 hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
                                double *out, hipStream_t s) {
@@ -1146,6 +1147,31 @@ __global__ void k_copy_f64(double *dst, const double *src, int64_t n) {
 hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------- cross-validation folds
+// Per site and fold k: the training mask (a sample whose fold id is not k)
+// and the scoring field (z at the samples of fold k, NaN elsewhere, so that
+// the validation measures see only the held-out samples).
+__global__ void k_cv_prepare(const double *z, const uint8_t *known, const uint8_t *fold, int n_folds, int64_t n,
+                             uint8_t *masks, double *zt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool smp = known[i] != 0;
+  const int f = fold[i];
+  const double v = z[i];
+  for (int k = 0; k < n_folds; ++k) {
+    const bool held = smp && f == k;
+    masks[(int64_t)k * n + i] = (smp && !held) ? 1 : 0;
+    zt[(int64_t)k * n + i] = held ? v : __builtin_nan("");
+  }
+}
+hipError_t launch_cv_prepare(const double *z, const uint8_t *known, const uint8_t *fold, int n_folds, int64_t n,
+                             uint8_t *masks, double *zt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cv_prepare, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z, known,
+                     fold, n_folds, n, masks, zt);
   return hipGetLastError();
 }
 

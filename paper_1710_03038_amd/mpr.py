@@ -84,6 +84,10 @@ def lib():
         L.mpr_validation_measures.argtypes = [vp, i32, vp, vp, dp]
         L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_set_graph.argtypes = [vp, i32]
+        L.mpr_set_grid_q.argtypes = [vp, dp]
+        L.mpr_cv_select_q.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, i32, dp, i32,
+                                      ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(i32), i32, i32, i32,
+                                      vp, ctypes.POINTER(ctypes.c_size_t), vp, dp, ctypes.POINTER(i32)]
         L.mpr_set_timing.argtypes = [vp, i32]
         L.mpr_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.mpr_destroy.argtypes = [vp]
@@ -151,6 +155,54 @@ def workspace_bytes(shapes, params):
     n = ctypes.c_size_t(0)
     _check(lib().mpr_init_field(None, gs, len(shapes), ctypes.byref(params), None, ctypes.byref(n), None))
     return n.value
+
+
+def cv_select_q(z, known, fold, n_folds, qs, tables, n_eq, n_samp, stride, params=None, chains=1, stream=None):
+    """mpr_cv_select_q: choose q by K-fold cross-validation.
+
+    z (float64), known (uint8), fold (uint8): CUDA tensors (ny, nx); fold
+    holds each sample site's fold id.  qs: candidates in (0, 0.5]; tables:
+    per candidate (tab_T, tab_e).  Returns dict(aae, rase, T_mean (arrays
+    per candidate), best (index), q (the chosen q))."""
+    import torch
+
+    params = params if params is not None else default_params()
+    z = z.contiguous().to(torch.float64)
+    known = known.contiguous().to(torch.uint8)
+    fold = fold.contiguous().to(torch.uint8)
+    if not (z.is_cuda and known.is_cuda and fold.is_cuda):
+        raise ValueError("z, known and fold must be CUDA tensors")
+    if z.shape != known.shape or z.shape != fold.shape or z.dim() != 2:
+        raise ValueError("z, known and fold must be 2-D tensors of one shape")
+    g = Grid()
+    g.ny, g.nx = z.shape
+    g.chains, g.reserved = int(chains), 0
+    g.z, g.known = z.data_ptr(), known.data_ptr()
+    nq = len(qs)
+    q = np.ascontiguousarray(qs, dtype=np.float64)
+    tabs = [(np.ascontiguousarray(t, dtype=np.float64), np.ascontiguousarray(e, dtype=np.float64)) for t, e in tables]
+    if len(tabs) != nq:
+        raise ValueError("one table per candidate")
+    dp = ctypes.POINTER(ctypes.c_double)
+    tT = (dp * nq)(*[_dptr(t) for t, _ in tabs])
+    tE = (dp * nq)(*[_dptr(e) for _, e in tabs])
+    nT = (ctypes.c_int32 * nq)(*[len(t) for t, _ in tabs])
+    stream = stream if stream is not None else torch.cuda.current_stream(z.device)
+    L = lib()
+    n = ctypes.c_size_t(0)
+    best = ctypes.c_int32(-1)
+    args = (tT, tE, nT, int(n_eq), int(n_samp), int(stride))
+    _check(L.mpr_cv_select_q(ctypes.byref(g), ctypes.byref(params), ctypes.c_void_p(fold.data_ptr()), int(n_folds),
+                             _dptr(q), nq, *args, None, ctypes.byref(n), None, None, ctypes.byref(best)))
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device=z.device)
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    score = np.empty(3 * nq)
+    _check(L.mpr_cv_select_q(ctypes.byref(g), ctypes.byref(params), ctypes.c_void_p(fold.data_ptr()), int(n_folds),
+                             _dptr(q), nq, *args, ctypes.c_void_p(aligned), ctypes.byref(n),
+                             ctypes.c_void_p(stream.cuda_stream), _dptr(score), ctypes.byref(best)))
+    sc = score.reshape(nq, 3)
+    return dict(aae=sc[:, 0].copy(), rase=sc[:, 1].copy(), T_mean=sc[:, 2].copy(), best=int(best.value),
+                q=float(q[best.value]))
 
 
 class Field:
@@ -281,6 +333,11 @@ class Field:
             off += ny * nx
         return out_h, (out_s if zstd is not None else None), dict(
             records=rep.records, a_eq=a_eq, acc_eq=acc_eq, acc_samp=acc_samp)
+
+    def set_grid_q(self, q):
+        """mpr_set_grid_q: one modification factor per grid."""
+        q = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.float64), (self.n_grids,)))
+        _check(lib().mpr_set_grid_q(self.ctx, _dptr(q)), self.ctx)
 
     def validation_measures(self, grid, z_true, zhat):
         """mpr_validation_measures: AAE, ARE, AARE, RASE, R (Sec. 3.3) of

@@ -15,7 +15,7 @@ from paper_1710_03038_amd import mpr as M
 def test_library_exports_every_declared_symbol():
     L = M.lib()
     names = M.header_functions()
-    assert len(names) == 19
+    assert len(names) == 21
     for n in names:
         assert hasattr(L, n), n
 
@@ -120,5 +120,36 @@ def test_null_context_calls_fail_cleanly():
     assert L.mpr_set_graph(None, 1) == M.MPR_E_STATE
     assert L.mpr_validation_measures(None, 0, None, None, M._dptr(e)) == M.MPR_E_STATE
     assert L.mpr_equilibrate(None, M._dptr(T), 5, 20, 10, 0, None, None, None) == M.MPR_E_STATE
+    assert L.mpr_set_grid_q(None, M._dptr(T)) == M.MPR_E_STATE
     L.mpr_destroy(None)
     assert b"NULL" in L.mpr_last_error(None)
+
+
+def _cv_query(n_folds=4, qs=(0.25, 0.5), model=0, n_samp=10, stride=2, shape=(32, 40), chains=1):
+    L = M.lib()
+    g = M.Grid()
+    g.ny, g.nx = shape
+    g.chains, g.reserved = chains, 0
+    p = M.default_params(model=model)
+    q = np.array(qs, dtype=np.float64)
+    n = ctypes.c_size_t(0)
+    best = ctypes.c_int32(-1)
+    dp = ctypes.POINTER(ctypes.c_double)
+    nq = len(qs)
+    rc = L.mpr_cv_select_q(ctypes.byref(g), ctypes.byref(p), None, n_folds, M._dptr(q), nq, (dp * max(nq, 1))(),
+                           (dp * max(nq, 1))(), (ctypes.c_int32 * max(nq, 1))(), 20, n_samp, stride, None,
+                           ctypes.byref(n), None, None, ctypes.byref(best))
+    return rc, n.value
+
+
+def test_cv_select_q_workspace_query_and_validation():
+    rc, n = _cv_query()
+    assert rc == M.MPR_OK
+    one = M.workspace_bytes([(32, 40, 1)], M.default_params())
+    # eight fits, four fold masks and scoring fields, eight predictions
+    assert n >= 8 * 32 * 40 * 8 + 4 * 32 * 40 * 9 + one
+    assert _cv_query(qs=(0.25, 0.5, 0.125))[1] > n
+    for kw in (dict(n_folds=1), dict(n_folds=255), dict(qs=(0.0, 0.5)), dict(qs=(0.6,)), dict(qs=()),
+               dict(model=M.MODEL_GMRF), dict(n_samp=1, stride=2)):
+        assert _cv_query(**kw)[0] == M.MPR_E_ARG, kw
+    assert _cv_query(shape=(1, 1))[0] == M.MPR_E_SHAPE

@@ -40,3 +40,24 @@ def test_gmrf_table_shape_and_limits(which, L):
     assert np.all(np.abs(ratio - 1.0) < 0.01), ratio
     assert np.all(e < -2.0 / 3.0)
     assert np.all(err < 5e-3 * eps + 1e-12)
+
+
+@pytest.mark.parametrize("q", [0.125, 0.25, 0.375])
+def test_product_tables_of_other_q(q):
+    # the same closed forms as for q = 1/2: the equipartition slope
+    # (L + 1) T / (4 L) does not depend on q, and e stays below the
+    # infinite-temperature value -(sin(pi q) / (pi q))^2
+    T, e, err = load_product_table(q=q)
+    L = 128
+    assert np.all(np.diff(T) > 0) and np.all(np.diff(e) > 0)
+    eps = 1.0 + e
+    low = T < 3e-3
+    ratio = eps[low] / ((L + 1) * T[low] / (4 * L))
+    assert np.all(np.abs(ratio - 1.0) < 0.01), ratio
+    e_inf = -(math.sin(math.pi * q) / (math.pi * q)) ** 2
+    assert np.all(e < e_inf)
+    assert np.all(err < 5e-3 * eps + 1e-12)
+    # and it agrees with the oracle's L = 32 table where e depends little on L
+    To, eo, _ = load_oracle_table(q=q)
+    mid = (T > 1e-2) & (T < 0.3)
+    np.testing.assert_allclose(1 + e[mid], 1 + eo[mid], rtol=0.05)
