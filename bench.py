@@ -42,11 +42,32 @@ HBM_PEAK_GBS = 8000.0
 # probes; the published 157.3 TFLOP/s FP32 is this peak times 2 flops per FMA.
 VALU_PEAK_TINST = 256 * 4 * 32 * 2.4e9 / 1e12
 # Issue slots (2-cycle units) of one FP32 gap-site update in the compiled
-# sweep kernel for q = 1/2: the two-update iteration of k_sweep<float> has
-# 347 VALU instructions for two updates, of which 2 x 20 v_mad_u64_u32 for
-# Philox and 2 x 5 transcendentals at 4 slots each: (337 + 40) / 2 = 188.5
-# (the one-update iteration: 165 + 5 * 4 = 185).
+# sweep kernel for q = 1/2 when the update draws its own random words: the
+# two-update iteration of k_sweep<float> has 347 VALU instructions for two
+# updates, of which 2 x 20 v_mad_u64_u32 for Philox and 2 x 5
+# transcendentals at 4 slots each: (337 + 40) / 2 = 188.5 (the one-update
+# iteration: 165 + 5 * 4 = 185).  One Philox4x32-10 call is 58 of them
+# (20 v_mad_u64_u32 and 38 v_xor_b32); an update whose words come from the
+# previous sweep's call (odd sweeps of a multi-sweep pass) skips it.
 VALU_INST_PER_UPDATE = 188
+VALU_INST_PHILOX = 58
+
+
+def stash_fraction(n_eq, n_samp, nsw):
+    """Share of a fill's site updates whose random words come from the
+    previous sweep's Philox call: the equilibration runs one sweep per pass
+    (the a-rule needs every sweep's acceptance), the sampling runs passes of
+    nsw sweeps from sweep n_eq, and the odd sweeps after a pass's first
+    sweep reuse the words.  (Items past a thread's first two per colour
+    draw their own; below 2 * 1024 per colour for the 64 x 64 tiles of the
+    default workload, so none there.)"""
+    served, s0, left = 0, n_eq, n_samp
+    while left > 0:
+        k = min(nsw, left)
+        served += sum(1 for s in range(1, k) if (s0 + s) % 2 == 1)
+        s0 += k
+        left -= k
+    return served / (n_eq + n_samp)
 KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
                   "paper_1710_03038_amd/csrc/internal.h")
 PROFILE = "profiles/k_sweep_fp32_grid1024.md"
@@ -585,7 +606,9 @@ def main():
     ksec = kms * 1e-3
     hbm_gbs = kss * b_site / ksec / 1e9 if kms > 0 else None
     useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
-    achieved = useful_updates * VALU_INST_PER_UPDATE / ksec / 1e12 if kms > 0 else None
+    nsw_run = out32[5][0] or (prm32.sweeps_per_pass or 8)
+    inst = VALU_INST_PER_UPDATE - VALU_INST_PHILOX * stash_fraction(W["n_eq"], W["n_samp"], nsw_run)
+    achieved = useful_updates * inst / ksec / 1e12 if kms > 0 else None
     default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
                       and args.boundary == "open"
                       and "MPR_SWEEP_THREADS" not in os.environ and tuple(out32[5]) in ((8, 1024), (0, None)))
@@ -617,7 +640,7 @@ def main():
                      "achieved": achieved, "peak": VALU_PEAK_TINST, "unit": "T VALU issue slots/s (lane-instructions, transcendentals x4)",
                      "frac": (achieved / VALU_PEAK_TINST) if achieved else None,
                      "traffic": profiled_traffic() if default_config else None,
-                     "inst_per_update": VALU_INST_PER_UPDATE,
+                     "inst_per_update": inst,
                      "avg_launch_us": kms * 1e3 / kl if kl else None, "launches": kl,
                      "site_sweeps_per_launch": kss / kl if kl else None,
                      "hbm_one_pass": {"achieved_GBps": hbm_gbs, "peak_GBps": HBM_PEAK_GBS,

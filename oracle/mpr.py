@@ -68,10 +68,11 @@ over-relaxation reflects phi about the mean of its neighbours, kept only
 inside [0, 2 pi), and everything else is unchanged.
 
 Random stream (a definition of this project): key = (seed mod 2^32,
-seed >> 32); counter = (pair, sweep, chain, grid) with
-pair = y * ceil(nx/2) + x//2.  A site with even x uses words (w0 -> u,
-w1 -> r), odd x uses (w2 -> u, w3 -> r).  The hot start uses
-sweep = 0xFFFFFFFF and the u word only.
+seed >> 32); counter = (site, sweep >> 1, chain, grid) with
+site = y * nx + x.  One call serves a site for two sweeps: words (w0 -> u,
+w1 -> r) in the even sweep, (w2 -> u, w3 -> r) in the odd one.  The hot
+start uses counter word 0xFFFFFFFF in place of sweep >> 1 (which never
+reaches it) and the u word w0.
 """
 import math
 
@@ -102,26 +103,29 @@ def split_seed(seed):
     return seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
 
 
-def site_uniforms(seed, ny, nx, sweep, chains, grid, origin=(0, 0), npair=None):
+def site_uniforms(seed, ny, nx, sweep, chains, grid, origin=(0, 0), gnx=None):
     """Uniforms (u, r) of every site for one sweep; arrays (C, ny, nx).
 
-    ``origin`` and ``npair`` place the array as a window at (y0, x0) of a
-    larger grid with ``npair`` Philox pairs per row: the stream is keyed by
-    the sites' coordinates in that grid.
+    ``origin`` and ``gnx`` place the array as a window at (y0, x0) of a
+    larger grid of width ``gnx``: the stream is keyed by the sites'
+    coordinates in that grid.
     """
     k0, k1 = split_seed(seed)
     chains = np.asarray(chains, dtype=np.uint64).reshape(-1, 1, 1)
     # int64 so that a window may start left of or above the grid (the ring of
-    # auxiliary nodes); the counter word is the pair index mod 2^32
+    # auxiliary nodes); the counter word is the site index mod 2^32
     y = np.arange(origin[0], origin[0] + ny, dtype=np.int64).reshape(1, ny, 1)
     x = np.arange(origin[1], origin[1] + nx, dtype=np.int64).reshape(1, 1, nx)
-    npair = (nx + 1) // 2 if npair is None else npair
-    pair = (y * npair + x // 2) % (1 << 32)
-    w0, w1, w2, w3 = philox4x32(pair.astype(np.uint64), sweep, chains, grid, k0, k1)
-    even = (x % 2) == 0
-    u = np.where(even, w0, w2)
-    r = np.where(even, w1, w3)
-    return unit_float(u), unit_float(r)
+    gnx = nx if gnx is None else gnx
+    site = ((y * gnx + x) % (1 << 32)).astype(np.uint64)
+    sweep = int(sweep)
+    if sweep == HOT_START_SWEEP:
+        w0, w1, _, _ = philox4x32(site, HOT_START_SWEEP, chains, grid, k0, k1)
+        return unit_float(w0), unit_float(w1)
+    w0, w1, w2, w3 = philox4x32(site, sweep >> 1, chains, grid, k0, k1)
+    if sweep % 2 == 0:
+        return unit_float(w0), unit_float(w1)
+    return unit_float(w2), unit_float(w3)
 
 
 # --------------------------------------------------------------------------
@@ -157,12 +161,12 @@ def inverse_transform(phi, zmin, zmax):
     return zmin + (zmax - zmin) * (np.asarray(phi, dtype=np.float64) / TWO_PI)
 
 
-def hot_start(phi_s, known, seed, chains, grid, origin=(0, 0), npair=None):
+def hot_start(phi_s, known, seed, chains, grid, origin=(0, 0), gnx=None):
     """Paramagnetic start: every gap gets 2*pi*U (Algorithm 2, step 1.8).
-    origin, npair: a window of a larger grid (see site_uniforms)."""
+    origin, gnx: a window of a larger grid (see site_uniforms)."""
     ny, nx = phi_s.shape
     chains = np.atleast_1d(np.asarray(chains))
-    u, _ = site_uniforms(seed, ny, nx, HOT_START_SWEEP, chains, grid, origin, npair)
+    u, _ = site_uniforms(seed, ny, nx, HOT_START_SWEEP, chains, grid, origin, gnx)
     phi = np.where(known[None], phi_s[None], TWO_PI * u)
     return phi
 
@@ -291,7 +295,7 @@ def site_energy(phi, nbrs, q, model=MPR):
     return -sum(np.where(np.isnan(n), 0.0, np.cos(q * (phi - np.nan_to_num(n)))) for n in nbrs)
 
 
-def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), npair=None,
+def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=None, origin=(0, 0), gnx=None,
                  or_step=True, model=MPR, boundary=OPEN):
     """One sweep of Algorithm 1 over all gap sites, colour 0 then colour 1.
 
@@ -305,7 +309,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
       "or_edge" = distance of the reflected angle from 0 and 2*pi, "wrap" =
       distance of the unwrapped proposal from 0 and 2*pi.  inf at sites not
       updated.
-    origin, npair: run on a window of a larger grid (see site_uniforms);
+    origin, gnx: run on a window of a larger grid (see site_uniforms);
       the window's edges are then open boundaries, which is exact only for
       sites far enough from them.
     or_step: False skips step 1 (no over-relaxation): the restricted
@@ -319,7 +323,7 @@ def hybrid_sweep(phi, known, beta, alpha, q, seed, sweep, chains, grid, margins=
     C, ny, nx = phi.shape
     beta = np.broadcast_to(np.asarray(beta, dtype=np.float64), (C,)).reshape(C, 1, 1)
     alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (C,)).reshape(C, 1, 1)
-    u, r = site_uniforms(seed, ny, nx, sweep, chains, grid, origin, npair)
+    u, r = site_uniforms(seed, ny, nx, sweep, chains, grid, origin, gnx)
     yy, xx = np.mgrid[origin[0]:origin[0] + ny, origin[1]:origin[1] + nx]
     accepted = np.zeros(C, dtype=np.int64)
     if margins is not None:
@@ -369,15 +373,14 @@ def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, o
     phi = [list(map(float, row)) for row in np.asarray(phi, dtype=np.float64)]
     ny, nx = len(phi), len(phi[0])
     k0, k1 = split_seed(seed)
-    npair = (nx + 1) // 2
     accepted = 0
     for colour in (0, 1):
         for y in range(ny):
             for x in range(nx):
                 if (x + y) % 2 != colour or known[y][x]:
                     continue
-                w = philox4x32(y * npair + x // 2, sweep, chain, grid, k0, k1)
-                wu, wr = (w[0], w[1]) if x % 2 == 0 else (w[2], w[3])
+                w = philox4x32(y * nx + x, sweep >> 1, chain, grid, k0, k1)
+                wu, wr = (w[0], w[1]) if sweep % 2 == 0 else (w[2], w[3])
                 u = float(unit_float(wu))
                 r = float(unit_float(wr))
                 cur = phi[y][x]

@@ -173,7 +173,6 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
     d.nx = G.nx;
     d.ny = G.ny;
     d.chains = G.chains;
-    d.npair = (G.nx + 1) / 2;
     d.tiles_x = (G.nx + pl.tile_x - 1) / pl.tile_x;
     d.tiles_y = (G.ny + pl.tile_y - 1) / pl.tile_y;
     d.chain_base = (int32_t)chains;

@@ -16,7 +16,7 @@ constexpr int kChunk = 4096;        // sites per workgroup in the streaming kern
 // site_off + y*nx + x.  A sample (frozen) site is stored with its sign bit
 // set: the angle is |v|, and gap angles are >= +0.
 struct GridDesc {
-  int32_t nx, ny, chains, npair;   // npair = ceil(nx/2): Philox pairs per row
+  int32_t nx, ny, chains, reserved0;
   int32_t tiles_x, tiles_y;        // sweep tiles of one chain
   int32_t chain_base;              // global index of chain 0
   int32_t grid_id;                 // index of the grid in the batch

@@ -208,7 +208,9 @@ template <typename P> struct UpdateCtx {
   V2 *cc;              // this colour's (cos, sin) plane
   const V2 *cn;        // the other colour's (cos, sin) plane
   const P *pn;         // the other colour's angle plane
-  int Ly, Lx, P2, pbase, npair;
+  int Ly, Lx, P2;
+  uint32_t sbase;      // Philox site index of LDS site (0, 0), mod 2^32
+  int gnx;             // grid width: LDS site (ly, lx) has index sbase + ly * gnx + lx
   uint32_t sweep, cid, gid, k0, k1;
   P q, inv_q, alpha, beta;
   bool or_step;        // over-relaxation on
@@ -225,6 +227,28 @@ __device__ __forceinline__ int aux_count(const UpdateCtx<P> &U, int ly, int lx) 
   return (lx == U.ex0 ? 1 : 0) + (lx == U.ex1 ? 1 : 0) + (ly == U.ey0 ? 1 : 0) + (ly == U.ey1 ? 1 : 0);
 }
 
+// Random words (u, r) of a site for this sweep.  One Philox call keyed by
+// (site, sweep >> 1, chain, grid) serves two sweeps: words (w0, w1) in the
+// even one, (w2, w3) in the odd one.  On an even sweep the odd sweep's
+// words go to the thread's stash; with use_stash (an odd sweep whose even
+// predecessor ran in this pass, for the same item) they come from it.
+template <typename P>
+__device__ __forceinline__ void site_words(const UpdateCtx<P> &U, int ly, int lx, bool use_stash, uint32_t (&st)[2],
+                                           uint32_t &wu, uint32_t &wr) {
+  if (use_stash) {
+    wu = st[0];
+    wr = st[1];
+    return;
+  }
+  uint32_t w[4];
+  philox4x32_10(U.sbase + (uint32_t)(ly * U.gnx + lx), U.sweep >> 1, U.cid, U.gid, U.k0, U.k1, w);
+  const bool odd = (U.sweep & 1u) != 0;
+  wu = odd ? w[2] : w[0];
+  wr = odd ? w[3] : w[1];
+  st[0] = w[2];
+  st[1] = w[3];
+}
+
 // Algorithm 1 with the GMRF pair interaction for the K plan entries fs[]
 // of one thread.  A site's energy is a parabola in its angle about the mean
 // m = S/n of its n in-grid neighbours (NaN in the angle plane marks none),
@@ -233,7 +257,7 @@ __device__ __forceinline__ int aux_count(const UpdateCtx<P> &U, int ly, int lx) 
 // neighbours add g copies of the site's own angle to S and g to n.
 template <typename P, bool REP, int K>
 __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
-                                                      const bool (&cnt)[K]) {
+                                                      const bool (&cnt)[K], bool use_stash, uint32_t (&stash)[K][2]) {
   int o[K];
   P phi[K], sum[K], n[K], u[K], rr[K];
 #pragma unroll
@@ -257,10 +281,10 @@ __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, con
       sum[k] = fma(g, phi[k], sum[k]);
       n[k] += g;
     }
-    uint32_t w[4];
-    philox4x32_10((uint32_t)(U.pbase + ly * U.npair + j), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
-    u[k] = unit<P>(par ? w[2] : w[0]);
-    rr[k] = unit<P>(par ? w[3] : w[1]);
+    uint32_t wu, wr;
+    site_words(U, ly, lx, use_stash, stash[k], wu, wr);
+    u[k] = unit<P>(wu);
+    rr[k] = unit<P>(wr);
   }
   uint32_t acc = 0;
 #pragma unroll
@@ -283,8 +307,8 @@ __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, con
 // by step; returns the accepted updates among those with cnt[] set.
 template <typename P, int MODEL, bool REP, int K>
 __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
-                                                 const bool (&cnt)[K]) {
-  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, REP, K>(U, fs, cnt);
+                                                 const bool (&cnt)[K], bool use_stash, uint32_t (&stash)[K][2]) {
+  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, REP, K>(U, fs, cnt, use_stash, stash);
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
   const P q = U.q;
@@ -309,11 +333,10 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
       hx[k] = fma(g, own.x, hx[k]);
       hy[k] = fma(g, own.y, hy[k]);
     }
-    // Philox pair of the site: its LDS pair index offset by the tile origin.
-    uint32_t w[4];
-    philox4x32_10((uint32_t)(U.pbase + ly * U.npair + j), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
-    u[k] = unit<P>(par ? w[2] : w[0]);
-    rr[k] = unit<P>(par ? w[3] : w[1]);
+    uint32_t wu, wr;
+    site_words(U, ly, lx, use_stash, stash[k], wu, wr);
+    u[k] = unit<P>(wu);
+    rr[k] = unit<P>(wr);
   }
   uint32_t acc = 0;
 #pragma unroll
@@ -472,16 +495,22 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
   const int iw = ix1 - x0, ih = iy1 - y0;
   const float inv_iw = 1.0f / (float)iw;
-  const int npair = G.npair;
-  // Plan entries are decoded relative to these LDS offsets; the Philox pair
-  // of LDS site (ly, lx) is pbase + ly * npair + (lx >> 1).
+  // Plan entries are decoded relative to these LDS offsets; LDS site
+  // (ly, lx) is grid site (oy + ly, ox + lx), Philox site index
+  // sbase + ly * nx + lx (mod 2^32).
   const int Ly = y0 - oy - kPlanOffset, Lx = x0 - ox - kPlanOffset;
-  const int pbase = oy * npair + (ox >> 1);
+  const uint32_t sbase = (uint32_t)((int64_t)oy * nx + ox);
+  // Odd-sweep random words of each thread's first two plan items per
+  // colour (the same items in every sweep of the pass).
+  uint32_t stash0[2][2] = {}, stash1[2][2] = {};
 
   for (int s = 0; s < A.nsw; ++s) {
     const uint32_t sweep = A.sweep0 + (uint32_t)s;
+    const bool from_stash = (sweep & 1u) != 0 && s > 0;
     uint32_t acc = 0;
-    for (int c = 0; c < 2; ++c) {
+    // One colour phase (half-sweep); called once per colour with that
+    // colour's stash, so that every register array is indexed statically.
+    auto phase = [&](const int c, uint32_t(&stash)[2][2]) __attribute__((always_inline)) {
       const int D = 2 * A.nsw - (2 * s + c) - (A.energy ? 0 : 1);
       const uint32_t n = cum[c * cstride + D + 1];      // entries within ring D
       const uint32_t n_inner = cum[c * cstride + 1];    // ring 0: the interior
@@ -490,30 +519,43 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       V2 *cc = cs + c * plane;
       const V2 *cn = cs + (c ^ 1) * plane;
       const UpdateCtx<P> U{lc,    pc,  cc,  cn,    ph + (c ^ 1) * plane,
-                           Ly,    Lx,  P2,  pbase, npair,
+                           Ly,    Lx,  P2,  sbase, nx,
                            sweep, cid, gid, k0,    k1,
                            q,     inv_q, alpha, beta, A.or_step != 0,
                            -ox,   nx - 1 - ox, -oy, ny - 1 - oy};
       // In FP32, two independent updates per thread and iteration (items f
       // and f + NT) give the scheduler two dependency chains to interleave;
-      // a lane without a second item repeats its first, whose identical
-      // write is harmless, and counts it once.  FP64 keeps one per iteration
-      // (its registers would cost occupancy).
+      // a lane without a second item repeats its first, with the first's
+      // random words, whose identical write is harmless, and counts it once.
+      // FP64 keeps one per iteration (its registers would cost occupancy).
+      // The first iteration's items keep their odd-sweep words in `stash`;
+      // later ones draw their own.
       constexpr uint32_t kIlp = sizeof(P) == 4 ? 2 : 1;
-      for (uint32_t f = threadIdx.x; f < n; f += kIlp * NT) {
+      auto step = [&](uint32_t f, bool use, uint32_t(&st)[2][2]) __attribute__((always_inline)) {
         const uint32_t f2 = f + NT;
         if (kIlp == 2 && __any(f2 < n)) {
           const uint32_t fs[2] = {f, f2 < n ? f2 : f};
           const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
-          acc += update_sites<P, MODEL, REP, 2>(U, fs, cnt);
+          if (f2 >= n) {  // the repeated item takes the first item's words
+            st[1][0] = st[0][0];
+            st[1][1] = st[0][1];
+          }
+          acc += update_sites<P, MODEL, REP, 2>(U, fs, cnt, use, st);
         } else {
           const uint32_t fs[1] = {f};
           const bool cnt[1] = {f < n_inner};
-          acc += update_sites<P, MODEL, REP, 1>(U, fs, cnt);
+          acc += update_sites<P, MODEL, REP, 1>(U, fs, cnt, use, reinterpret_cast<uint32_t(&)[1][2]>(st[0]));
         }
+      };
+      if (threadIdx.x < n) step(threadIdx.x, from_stash, stash);
+      for (uint32_t f = threadIdx.x + kIlp * NT; f < n; f += kIlp * NT) {
+        uint32_t spare[2][2];
+        step(f, false, spare);
       }
       __syncthreads();
-    }
+    };
+    phase(0, stash0);
+    phase(1, stash1);
 
     {
       const uint32_t wsum = wave_sum(acc);
@@ -835,12 +877,11 @@ __global__ void __launch_bounds__(kThreads)
     if (kn[i]) {
       v = -(P)((z[i] - zmin) / span * 6.28318530717958647692);
     } else {
-      const int y = (int)(i / G.nx), x = (int)(i - (int64_t)y * G.nx);
+      // the site's counter with word 0xFFFFFFFF (sweep >> 1 never reaches it); word w0
       uint32_t w[4];
-      philox4x32_10((uint32_t)y * (uint32_t)G.npair + (uint32_t)(x >> 1), 0xFFFFFFFFu, (uint32_t)chain,
-                    (uint32_t)G.grid_id, k0, k1, w);
+      philox4x32_10((uint32_t)i, 0xFFFFFFFFu, (uint32_t)chain, (uint32_t)G.grid_id, k0, k1, w);
       // Float angles are rounded to the nearest float; keep gaps below 2*pi.
-      v = (P)(6.28318530717958647692 * unit<double>((x & 1) ? w[2] : w[0]));
+      v = (P)(6.28318530717958647692 * unit<double>(w[0]));
       if (v >= Prec<P>::two_pi) v = Prec<P>::below_two_pi;
     }
     const int64_t k = G.state_off + (int64_t)chain * n + i;

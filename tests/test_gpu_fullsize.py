@@ -32,14 +32,13 @@ def _oracle_window(z, known, bounds, seed, chain, grid, T, a, sweep0, nsw, win, 
     ey0, ey1, ex0, ex1 = max(y0 - H, 0), min(y1 + H, ny), max(x0 - H, 0), min(x1 + H, nx)
     kw = known[ey0:ey1, ex0:ex1].astype(bool)
     ws, _, _ = om.transform(z[ey0:ey1, ex0:ex1], kw, bounds=bounds)
-    npair = (nx + 1) // 2
-    phi = om.hot_start(ws, kw, seed, [chain], grid, origin=(ey0, ex0), npair=npair)
+    phi = om.hot_start(ws, kw, seed, [chain], grid, origin=(ey0, ex0), gnx=nx)
     if dtype == "fp32":
         phi = as_fp32_state(phi[0], kw)[None]
     margins = {}
     for s in range(nsw):
         phi, _ = om.hybrid_sweep(phi, kw, [beta_of(T)], [TWO_PI / a], 0.5, seed, sweep0 + s, [chain], grid,
-                                 margins=margins, origin=(ey0, ex0), npair=npair)
+                                 margins=margins, origin=(ey0, ex0), gnx=nx)
     cut = (slice(y0 - ey0, y1 - ey0), slice(x0 - ex0, x1 - ex0))
     return phi[0][cut], {k: v[0][cut] for k, v in margins.items()}, kw[cut]
 

@@ -37,7 +37,7 @@ def _augmented_sweep(phi, known, beta, alpha, q, seed, sweep, chains, or_step, m
     pad = np.pad(phi, [(0, 0), (1, 1), (1, 1)], mode="edge")
     kpad = np.pad(known, 1, mode="constant", constant_values=True)
     out, acc = mpr.hybrid_sweep(pad, kpad, beta, alpha, q, seed, sweep, chains, 0, origin=(-1, -1),
-                                npair=(nx + 1) // 2, or_step=or_step, model=model)
+                                gnx=nx, or_step=or_step, model=model)
     return out[:, 1:-1, 1:-1], acc
 
 

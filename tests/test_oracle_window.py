@@ -24,12 +24,11 @@ def test_window_matches_full_grid_away_from_edges():
     H = 2 * k + 1
     ey0, ey1, ex0, ex1 = y0 - H, y1 + H, x0 - H, x1 + H
     ws, _, _ = om.transform(z[ey0:ey1, ex0:ex1], known[ey0:ey1, ex0:ex1], bounds=(zmin, zmax))
-    npair = (nx + 1) // 2
-    w = om.hot_start(ws, known[ey0:ey1, ex0:ex1], seed, [chain], grid, origin=(ey0, ex0), npair=npair)
+    w = om.hot_start(ws, known[ey0:ey1, ex0:ex1], seed, [chain], grid, origin=(ey0, ex0), gnx=nx)
     assert np.array_equal(w[0], phi[0, ey0:ey1, ex0:ex1])
     for s in range(k):
         w, _ = om.hybrid_sweep(w, known[ey0:ey1, ex0:ex1], [1 / 0.05], [2 * math.pi / 2], 0.5, seed, 5 + s,
-                               [chain], grid, origin=(ey0, ex0), npair=npair)
+                               [chain], grid, origin=(ey0, ex0), gnx=nx)
     inner = w[0, y0 - ey0:y1 - ey0, x0 - ex0:x1 - ex0]
     assert np.array_equal(inner, full[0, y0:y1, x0:x1])
     # and the edge rings really do differ (the test has teeth)
