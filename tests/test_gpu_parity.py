@@ -410,3 +410,33 @@ def test_autotune_leaves_state_and_results_unchanged():
     for g, gr in enumerate(grids):
         for c in range(gr[2]):
             assert np.array_equal(f1.get_phi(g, c).cpu().numpy(), f2.get_phi(g, c).cpu().numpy())
+
+
+@pytest.mark.parametrize("shape", [(2, 65536), (65536, 3), (1, 65536)])
+@pytest.mark.parametrize("dtype,nsw", [("fp64", 2), ("fp32", 1)])
+def test_extreme_shapes(shape, dtype, nsw):
+    # the largest width and height the ABI accepts (65536): Philox site
+    # indices up to 2^18, 1024 tiles in a row or column, both colours at
+    # the far edges
+    ny, nx = shape
+    rng = np.random.default_rng(ny + nx)
+    z = rng.normal(50.0, 10.0, shape)
+    known = (rng.random(shape) < 0.4).astype(np.uint8)
+    seed, T, a = 13, 0.05, 2.0
+    f = make_field([(z, known, 1)], dtype=dtype, seed=seed, sweeps_per_pass=nsw)
+    phi = oracle_init(z, known, seed, 0, 0, dtype)
+    assert np.array_equal(f.get_phi(0, 0).cpu().numpy(), phi)
+    f.set_chain_state(4, np.full(1, a))
+    f.sweep(nsw, np.array([T]))
+    got = f.get_phi(0, 0).cpu().numpy()
+    ref, margins = phi[None], {}
+    for s in range(nsw):
+        ref, _ = om.hybrid_sweep(ref, known.astype(bool), [beta_of(T)], [TWO_PI / a], 0.5, seed, 4 + s, [0], 0,
+                                 margins=margins)
+    if dtype == "fp64":
+        assert np.abs(got - ref[0]).max() <= 1e-5
+    else:
+        n_bad, _, unexpl = explained_mismatches(got, ref[0], margins, known, 1e-3)
+        assert len(unexpl) == 0, unexpl[:5]
+        assert n_bad <= max(3, 1e-3 * int((known == 0).sum()))
+    f.close()
