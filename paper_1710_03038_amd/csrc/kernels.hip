@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int x0 = (t % G.tiles_x) * A.tile_x, y0 = (t / G.tiles_x) * A.tile_y;
   const int ix1 = min(x0 + A.tile_x, nx), iy1 = min(y0 + A.tile_y, ny);
   const int H = 2 * A.nsw + 1;
-  const int ox = max(x0 - H - 1, -2);  // even, so LDS pairs are Philox pairs
+  const int ox = max(x0 - H - 1, -2);  // even: LDS x has the parity of grid x, so both colour planes pair sites lx / 2
   const int oy = max(y0 - H - 1, -1);
   const int lxs = max(x0 - H, 0), lxe = min(ix1 + H, nx);
   const int lys = max(y0 - H, 0), lye = min(iy1 + H, ny);
