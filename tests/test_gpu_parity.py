@@ -440,3 +440,25 @@ def test_extreme_shapes(shape, dtype, nsw):
         assert len(unexpl) == 0, unexpl[:5]
         assert n_bad <= max(3, 1e-3 * int((known == 0).sum()))
     f.close()
+
+
+@pytest.mark.parametrize("dtype,nsw", [("fp32", 8), ("fp64", 4)])
+def test_fused_pass_equals_single_sweeps_dense_gaps(dtype, nsw):
+    # 95 % gaps: a colour of a 64 x 64 tile has more plan entries than two
+    # per thread, so within one pass some items reuse the previous sweep's
+    # random words and the rest draw their own; the result must equal
+    # single-sweep passes (which draw every word) bit for bit, from an even
+    # and from an odd first sweep
+    rng = np.random.default_rng(17)
+    z = rng.normal(50.0, 10.0, (200, 190))
+    known = (rng.random(z.shape) < 0.05).astype(np.uint8)
+    for first in (0, 5):
+        outs = []
+        for k in (nsw, 1):
+            f = make_field([(z, known, 2)], dtype=dtype, seed=3, sweeps_per_pass=k)
+            f.set_chain_state(first, np.full(2, 3.0))
+            f.sweep(nsw, [0.05])
+            outs.append([f.get_phi(0, c).cpu().numpy() for c in range(2)])
+            f.close()
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
