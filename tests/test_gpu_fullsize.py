@@ -138,3 +138,48 @@ def test_fill_grid1024_fp32_vs_fp64_equal_mae():
     m32, m64 = np.mean(maes["fp32"]), np.mean(maes["fp64"])
     s = math.hypot(np.std(maes["fp32"], ddof=1), np.std(maes["fp64"], ddof=1)) / math.sqrt(4)
     assert abs(m32 - m64) <= 3 * s + 1e-4, (maes, s)
+
+
+def _uneven_inputs():
+    import multiprocessing as mp
+    import os
+
+    import mprgen
+    specs = mprgen.uneven_batch(2000, seed=401)
+    # fresh interpreters (spawn): the workers import numpy and the generators only
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        return pool.map(mprgen.batch_grid, specs, chunksize=8)
+
+
+def test_uneven2000_fp32_one_sweep():
+    # The 2000-grid batch (sides log-uniform in [32, 2048], 1.0e9 sites) in
+    # one launch of the library's default shape, each grid at its own
+    # temperature; the oracle checks windows of the smallest grid, the
+    # largest and four others.
+    grids = _uneven_inputs()
+    n = len(grids)
+    rng = np.random.default_rng(5)
+    T = 10.0 ** rng.uniform(-4.0, -1.0, n)
+    seed, a, sweep0 = 403, 2.0, 3
+    f = make_field([(z, k, 1) for z, k in grids], dtype="fp32", seed=seed)
+    f.set_chain_state(sweep0, np.full(n, a))
+    f.sweep(1, T)
+    sizes = [z.size for z, _ in grids]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))} | set(rng.choice(n, 4, replace=False).tolist()))
+    total_bad = total_gap = 0
+    for g in pick:
+        z, known = grids[g]
+        kn = known.astype(bool)
+        bounds = (float(z[kn].min()), float(z[kn].max()))
+        ny, nx = z.shape
+        got_full = f.get_phi(g, 0).cpu().numpy()
+        wins = _windows(ny, nx) if min(ny, nx) > 64 else [(0, ny, 0, nx)]
+        for win in wins:
+            ref, margins, kw = _oracle_window(z, known, bounds, seed, 0, g, T[g], a, sweep0, 1, win, "fp32")
+            got = got_full[win[0]:win[1], win[2]:win[3]]
+            n_bad, _, unexpl = explained_mismatches(got, ref, margins, kw, 1e-3)
+            assert len(unexpl) == 0, (g, win, unexpl[:4])
+            total_bad += n_bad
+            total_gap += int((~kw).sum())
+    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+    f.close()
