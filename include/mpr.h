@@ -337,9 +337,11 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
  * temperatures T[n_grids].  The angles, the sweep counter and every chain's
  * a are restored exactly afterwards, so the call has no effect on results;
  * neither choice changes results either (tiling and fusion are bitwise
- * invariant).  Choices are cached per batch shape for the process, so a
- * later context of the same shape reuses them without timing.  nsw_out,
- * threads_out (nullable) receive the choice.  Uses the fill accumulators as
+ * invariant).  The workgroup size of single-sweep passes (the a-rule runs
+ * one sweep per pass) is chosen apart, as the fastest at one sweep per
+ * pass.  Choices are cached per batch shape for the process, so a later
+ * context of the same shape reuses them without timing.  nsw_out,
+ * threads_out (nullable) receive the choice for multi-sweep passes.  Uses the fill accumulators as
  * scratch: do not call during a fill.  Synchronises the stream.
  */
 mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out);

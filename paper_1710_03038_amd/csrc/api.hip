@@ -65,6 +65,7 @@ struct mpr_ctx {
   int nsw_max = 1;             // the most sweeps per pass the plan supports
   int nsw_run = 1;             // sweeps per pass used (autotuned, <= nsw_max)
   int threads = 256;           // workgroup size of the sweep kernel
+  int threads1 = 256;          // ... for single-sweep passes (the a-rule's); tuned apart
   size_t lds_limit = 65536;
   std::vector<double> beta_h;  // staging for per-chain inverse temperatures
   std::string err;
@@ -82,12 +83,13 @@ struct mpr_ctx {
   bool capturing = false;
   struct GraphState {
     int64_t sweep_index, pass_no;
-    int cur, nsw_run, threads;
+    int cur, nsw_run, threads, threads1;
     int32_t n_eq, n_samp, stride;
     bool keep_a;
     bool operator==(const GraphState &o) const {
       return sweep_index == o.sweep_index && pass_no == o.pass_no && cur == o.cur && nsw_run == o.nsw_run &&
-             threads == o.threads && n_eq == o.n_eq && n_samp == o.n_samp && stride == o.stride && keep_a == o.keep_a;
+             threads == o.threads && threads1 == o.threads1 && n_eq == o.n_eq && n_samp == o.n_samp &&
+             stride == o.stride && keep_a == o.keep_a;
     }
   };
   GraphState g_key{}, g_post{};
@@ -361,7 +363,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.plan = c->v.plan;
   A.plan_cum = c->v.plan_cum;
   A.plan_dmax = c->plan.dmax;
-  HIP_TRY(c, launch_sweep<P>(A, c->threads, c->plan.n_items, lds, c->stream));
+  HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
   if (c->capturing) {
     c->g_launches += 1;
     c->g_site_sweeps += (int64_t)nsw * c->sites_all_chains;
@@ -641,6 +643,7 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
     const int t = std::atoi(env);
     if (t == 256 || t == 512 || t == 1024) c->threads = t;
   }
+  c->threads1 = c->threads;
   c->sites_all_chains = plan.state_elems;
   auto bail = [&](mpr_status s) {
     g_thread_err = c->err;
@@ -855,7 +858,7 @@ static mpr_status fill_sweeps(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_
 // Clears use fill kernels, never memset nodes.
 static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_t stride) {
   const mpr_ctx::GraphState key{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
-                                n_eq,             n_samp,       stride,    ctx->p.a_sample_keep != 0};
+                                ctx->threads1,    n_eq,         n_samp,    stride,       ctx->p.a_sample_keep != 0};
   if (!ctx->graph_exec || !(key == ctx->g_key)) {
     ctx->drop_graph();
     if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -875,7 +878,7 @@ static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, 
     ctx->capturing = false;
     ctx->stream = user;
     const mpr_ctx::GraphState post{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
-                                   n_eq,             n_samp,       stride,    key.keep_a};
+                                   ctx->threads1,    n_eq,         n_samp,    stride,       key.keep_a};
     // nothing has run yet: the host state goes back until the graph launches
     ctx->sweep_index = sweep0;
     ctx->pass_no = pass0;
@@ -1172,7 +1175,10 @@ static std::string tune_key(const mpr_ctx *c) {
 }
 
 static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<int, int>> g_tune_cache;
+struct TuneChoice {
+  int nsw, threads, threads1;  // sweeps per pass and workgroup size; workgroup size of single-sweep passes
+};
+static std::map<std::string, TuneChoice> g_tune_cache;
 
 
 mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out) {
@@ -1183,8 +1189,9 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      ctx->nsw_run = it->second.first;
-      ctx->threads = it->second.second;
+      ctx->nsw_run = it->second.nsw;
+      ctx->threads = it->second.threads;
+      ctx->threads1 = it->second.threads1;
       if (nsw_out) *nsw_out = ctx->nsw_run;
       if (threads_out) *threads_out = ctx->threads;
       return MPR_OK;
@@ -1208,8 +1215,8 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   hipEvent_t e0, e1;
   HIP_TRY(ctx, hipEventCreate(&e0));
   HIP_TRY(ctx, hipEventCreate(&e1));
-  double best = 1e300;
-  int best_nsw = ctx->nsw_run, best_thr = ctx->threads;
+  double best = 1e300, best1 = 1e300;
+  int best_nsw = ctx->nsw_run, best_thr = ctx->threads, best_thr1 = ctx->threads1;
   const int nsws[] = {1, 2, 3, 4, 6, 8, 12, 16};
   for (int thr : {256, 512, 1024}) {
     const bool ok = (ctx->p.dtype == MPR_FP64 ? sweep_max_threads<double>(thr) : sweep_max_threads<float>(thr)) >= thr;
@@ -1221,6 +1228,7 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
       lds_extent(ctx, nsw, w, h, lds);
       if (lds > ctx->lds_limit) break;
       ctx->threads = thr;
+      ctx->threads1 = thr;
       ctx->nsw_run = nsw;
       const int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
       st = run_sweeps(ctx, nsw, false, false, nullptr, 0);  // warm-up pass
@@ -1238,6 +1246,10 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
         best = per_sweep;
         best_nsw = nsw;
         best_thr = thr;
+      }
+      if (nsw == 1 && per_sweep < best1) {  // the a-rule runs one sweep per pass
+        best1 = per_sweep;
+        best_thr1 = thr;
       }
     }
   }
@@ -1258,9 +1270,10 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   if (st != MPR_OK) return st;
   ctx->nsw_run = best_nsw;
   ctx->threads = best_thr;
+  ctx->threads1 = best_thr1;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_nsw, best_thr};
+    g_tune_cache[key] = {best_nsw, best_thr, best_thr1};
   }
   if (nsw_out) *nsw_out = best_nsw;
   if (threads_out) *threads_out = best_thr;

@@ -379,7 +379,7 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
 // 2*nsw + 1 sites covers hs = 0), so the interior is exact after the last
 // half-sweep.  When the energy of interior pairs is traced, every D is one
 // larger, so that the interior plus one ring is exact after each sweep.
-template <typename P, int NT, int MODEL, bool REP>
+template <typename P, int NT, int MODEL, bool REP, bool STASH>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
@@ -501,12 +501,14 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int Ly = y0 - oy - kPlanOffset, Lx = x0 - ox - kPlanOffset;
   const uint32_t sbase = (uint32_t)((int64_t)oy * nx + ox);
   // Odd-sweep random words of each thread's first two plan items per
-  // colour (the same items in every sweep of the pass).
+  // colour (the same items in every sweep of the pass).  Without STASH
+  // every sweep draws its own: the kernel then holds 8 registers fewer,
+  // which lets two workgroups share a CU where the LDS would allow it.
   uint32_t stash0[2][2] = {}, stash1[2][2] = {};
 
   for (int s = 0; s < A.nsw; ++s) {
     const uint32_t sweep = A.sweep0 + (uint32_t)s;
-    const bool from_stash = (sweep & 1u) != 0 && s > 0;
+    const bool from_stash = STASH && (sweep & 1u) != 0 && s > 0;
     uint32_t acc = 0;
     // One colour phase (half-sweep); called once per colour with that
     // colour's stash, so that every register array is indexed statically.
@@ -554,8 +556,12 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       }
       __syncthreads();
     };
-    phase(0, stash0);
-    phase(1, stash1);
+    if constexpr (STASH) {
+      phase(0, stash0);
+      phase(1, stash1);
+    } else {
+      for (int c = 0; c < 2; ++c) phase(c, stash0);  // no stash to index: one copy of the code
+    }
 
     {
       const uint32_t wsum = wave_sum(acc);
@@ -711,28 +717,32 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
   apply_pass_end(A, A.grids[lo], ch, true);
 }
 
-template <typename P, int MODEL, bool REP>
+template <typename P, int MODEL, bool REP, bool STASH>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   const dim3 grid((unsigned)n_items);
   switch (threads) {
-    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP>), grid, dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP>), grid, dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP>), grid, dim3(1024), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, STASH>), grid, dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, STASH>), grid, dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP, STASH>), grid, dim3(1024), lds, s, a); break;
   }
 }
 
-template <typename P, bool REP>
+template <typename P, bool REP, bool STASH>
 static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  if (a.gmrf) launch_sweep_q<P, kGmrf, REP>(a, threads, n_items, lds, s);
-  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP>(a, threads, n_items, lds, s);
-  else launch_sweep_q<P, kMprQ, REP>(a, threads, n_items, lds, s);
+  if (a.gmrf) launch_sweep_q<P, kGmrf, REP, STASH>(a, threads, n_items, lds, s);
+  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP, STASH>(a, threads, n_items, lds, s);
+  else launch_sweep_q<P, kMprQ, REP, STASH>(a, threads, n_items, lds, s);
 }
 
+// Passes of 3 or more sweeps keep random words between the sweeps of a pair
+// (their LDS already limits a CU to one workgroup); shorter passes use the
+// leaner kernel.  The replicate boundary, a rarely used option, always does.
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-  if (a.rep) launch_sweep_m<P, true>(a, threads, n_items, lds, s);
-  else launch_sweep_m<P, false>(a, threads, n_items, lds, s);
+  if (a.rep) launch_sweep_m<P, true, true>(a, threads, n_items, lds, s);
+  else if (a.nsw >= 3) launch_sweep_m<P, false, true>(a, threads, n_items, lds, s);
+  else launch_sweep_m<P, false, false>(a, threads, n_items, lds, s);
   return hipGetLastError();
 }
 
@@ -740,9 +750,9 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
-    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false>)); break;
-    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false>)); break;
-    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false>)); break;
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false, true>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false, true>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false, true>)); break;
     default: break;
   }
   return e == hipSuccess ? at.maxThreadsPerBlock : 0;
