@@ -440,7 +440,7 @@ def one_step(M, f, W, table, tune, timing=False):
         f.set_timing(True)
     e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
     T, _ = M.match_T(e_s, table[0], table[1])
-    tuned = f.autotune(T, 16) if tune else (f.params.sweeps_per_pass, None)
+    tuned = f.autotune(T, 16) if tune else (f.params.sweeps_per_pass, None, None)
     zh, zs, rep = f.fill(T, W["n_eq"], W["n_samp"], W["stride"])
     kt = f.timing() if timing else (0.0, 0, 0)
     return zh, rep, T, e_s, kt, tuned
@@ -611,12 +611,13 @@ def main():
     achieved = useful_updates * inst / ksec / 1e12 if kms > 0 else None
     default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
                       and args.boundary == "open"
-                      and "MPR_SWEEP_THREADS" not in os.environ and tuple(out32[5]) in ((8, 1024), (0, None)))
+                      and "MPR_SWEEP_THREADS" not in os.environ and tuple(out32[5]) in ((8, 1024, 1024), (0, None, None)))
     cfg = dict(W["config"])
     cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"], "n_samp": W["n_samp"],
                 "stride": W["stride"], "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
                 "sweeps_per_pass_max": prm32.sweeps_per_pass or 8,
-                "autotuned_sweeps_per_pass_threads": list(out32[5]), "fill_graph": True,
+                "autotuned_shape": {"sweeps_per_pass": out32[5][0], "threads": out32[5][1],
+                                    "threads_single_sweep_passes": out32[5][2]}, "fill_graph": True,
                 "T_hat": float(T_hat[0]) if len(T_hat) == 1 else [float(T_hat.min()), float(T_hat.max())],
                 "e_s": float(out32[3][0]) if len(T_hat) == 1 else None})
     res = {

@@ -341,10 +341,12 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
  * one sweep per pass) is chosen apart, as the fastest at one sweep per
  * pass.  Choices are cached per batch shape for the process, so a later
  * context of the same shape reuses them without timing.  nsw_out,
- * threads_out (nullable) receive the choice for multi-sweep passes.  Uses the fill accumulators as
+ * threads_out (nullable) receive the choice for multi-sweep passes,
+ * threads1_out (nullable) the workgroup size of single-sweep passes.  Uses the fill accumulators as
  * scratch: do not call during a fill.  Synchronises the stream.
  */
-mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out);
+mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out,
+                        int32_t *threads1_out);
 
 /*
  * Kernel timing, for measurement.  With enable != 0 every later run of

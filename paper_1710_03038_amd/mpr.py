@@ -79,7 +79,7 @@ def lib():
         L.mpr_set_phi.argtypes = [vp, i32, i32, vp]
         L.mpr_get_chain_state.argtypes = [vp, ctypes.POINTER(i64), dp]
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
-        L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_reinit.argtypes = [vp]
         L.mpr_validation_measures.argtypes = [vp, i32, vp, vp, dp]
         L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -373,12 +373,15 @@ class Field:
         self.stream.synchronize()
 
     def autotune(self, T, trial_sweeps=16):
-        """mpr_autotune: returns (sweeps per pass, workgroup size) chosen."""
+        """mpr_autotune: returns (sweeps per pass, workgroup size, workgroup
+        size of single-sweep passes) chosen."""
         T = self._T(T)
         nsw = ctypes.c_int32(0)
         thr = ctypes.c_int32(0)
-        _check(lib().mpr_autotune(self.ctx, _dptr(T), trial_sweeps, ctypes.byref(nsw), ctypes.byref(thr)), self.ctx)
-        return nsw.value, thr.value
+        thr1 = ctypes.c_int32(0)
+        _check(lib().mpr_autotune(self.ctx, _dptr(T), trial_sweeps, ctypes.byref(nsw), ctypes.byref(thr),
+                                  ctypes.byref(thr1)), self.ctx)
+        return nsw.value, thr.value, thr1.value
 
     def reinit(self):
         """mpr_reinit: hot start again from the z and known tensors given at

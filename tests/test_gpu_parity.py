@@ -399,8 +399,8 @@ def test_autotune_leaves_state_and_results_unchanged():
     f2.sweep(3, T, adapt=True)
     before = [f2.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
     idx, a = f2.chain_state()
-    nsw, thr = f2.autotune(T, 8)
-    assert 1 <= nsw <= 8 and thr in (256, 512, 1024)
+    nsw, thr, thr1 = f2.autotune(T, 8)
+    assert 1 <= nsw <= 8 and thr in (256, 512, 1024) and thr1 in (256, 512, 1024)
     idx2, a2 = f2.chain_state()
     assert idx2 == idx and np.array_equal(a2, a)
     after = [f2.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
