@@ -1232,12 +1232,21 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
       ctx->threads = thr;
       ctx->threads1 = thr;
       ctx->nsw_run = nsw;
-      const int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
+      int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
       st = run_sweeps(ctx, nsw, false, false, nullptr, 0);  // warm-up pass
-      // two timed runs, the faster kept: close candidates are otherwise
-      // decided by one-off delays
+      // Timed runs of at least ~2 ms each (a short run is lengthened after
+      // the first), the fastest kept: close candidates are otherwise
+      // decided by one-off delays.
       float ms = 1e30f;
-      for (int rep = 0; rep < 2 && st == MPR_OK; ++rep) {
+      bool lengthened = false;
+      for (int rep = 0; rep < 3 && st == MPR_OK; ++rep) {
+        if (rep == 1 && ms < 2.0f) {
+          const int64_t want = (int64_t)std::ceil(n * 2.0 / std::max(ms, 0.01f));
+          n = ((std::min<int64_t>(want, 64 * n) + nsw - 1) / nsw) * nsw;
+          ms = 1e30f;  // compare runs of the new length only
+          lengthened = true;
+        }
+        if (rep == 2 && !lengthened) break;  // two long runs suffice
         HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
         st = run_sweeps(ctx, n, false, false, nullptr, 0);
         HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
