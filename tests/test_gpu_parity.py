@@ -365,6 +365,29 @@ def test_fill_fp64_statistics_match_oracle():
     assert abs(mg - mo) <= 3 * math.hypot(sg, so) + 1e-12, (mg, mo, sg, so)
 
 
+@pytest.mark.parametrize("stride,keep", [(1, False), (3, True)])
+def test_fill_fp64_equals_oracle_site_by_site(stride, keep):
+    # A short FP64 fill (a-rule equilibration, sampling, records, the
+    # pooled mean and standard deviation of Algorithm 2, steps 4-6) of a
+    # mixed batch follows the oracle's chains state for state, so z_hat and
+    # z_std agree site by site; samples are copied through with std 0.
+    grids = _grids(41, chains=3)
+    T = [0.02, 0.1, 0.005, 0.3, 0.05]
+    f = make_field(grids, dtype="fp64", seed=71, a_sample_keep=int(keep))
+    zh, zs, rep = f.fill(T, 12, 18, stride)
+    assert rep["records"] == 18 // stride
+    for g, (z, known, chains) in enumerate(grids):
+        kn = known.astype(bool)
+        if kn.all() or not kn.any():
+            continue
+        out = om.fill(z, kn, T[g], 12, 18, stride, seed=71, chains=chains, grid=g, a_sample_keep=keep)
+        got_h, got_s = zh[g].cpu().numpy(), zs[g].cpu().numpy()
+        span = float(z[kn].max() - z[kn].min())
+        np.testing.assert_allclose(got_h, out["z_hat"], rtol=0, atol=1e-9 * span)
+        np.testing.assert_allclose(got_s, out["z_std"], rtol=0, atol=1e-7 * span)
+        assert np.array_equal(got_h[kn], z[kn]) and np.all(got_s[kn] == 0)
+
+
 # ---------------------------------------------------------------- errors
 def test_error_paths_on_device():
     from paper_1710_03038_amd import mpr as M
