@@ -376,16 +376,21 @@ def test_fill_fp64_equals_oracle_site_by_site(stride, keep):
     f = make_field(grids, dtype="fp64", seed=71, a_sample_keep=int(keep))
     zh, zs, rep = f.fill(T, 12, 18, stride)
     assert rep["records"] == 18 // stride
+    c0 = 0
     for g, (z, known, chains) in enumerate(grids):
         kn = known.astype(bool)
-        if kn.all() or not kn.any():
-            continue
         out = om.fill(z, kn, T[g], 12, 18, stride, seed=71, chains=chains, grid=g, a_sample_keep=keep)
         got_h, got_s = zh[g].cpu().numpy(), zs[g].cpu().numpy()
         span = float(z[kn].max() - z[kn].min())
         np.testing.assert_allclose(got_h, out["z_hat"], rtol=0, atol=1e-9 * span)
         np.testing.assert_allclose(got_s, out["z_std"], rtol=0, atol=1e-7 * span)
         assert np.array_equal(got_h[kn], z[kn]) and np.all(got_s[kn] == 0)
+        # the report: a after equilibration, mean acceptance of both phases
+        sl = slice(c0, c0 + chains)
+        assert np.array_equal(rep["a_eq"][sl], out["a_eq"])
+        np.testing.assert_allclose(rep["acc_eq"][sl], out["acc_eq"].mean(axis=0), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(rep["acc_samp"][sl], out["acc_samp"].mean(axis=0), rtol=0, atol=1e-12)
+        c0 += chains
 
 
 # ---------------------------------------------------------------- errors
