@@ -27,8 +27,9 @@ def test_default_params_are_the_papers():
     assert M.default_params(model="gmrf").model == M.MODEL_GMRF
 
 
-def test_match_T_matches_oracle_on_the_oracle_table():
-    T, e, _ = load_table()
+@pytest.mark.parametrize("model,q", [("mpr", 0.5), ("mpr", 0.125), ("mpr", 0.25), ("mpr", 0.375), ("gmrf", 0.5)])
+def test_match_T_matches_oracle_on_the_oracle_table(model, q):
+    T, e, _ = load_table(model=model, q=q)
     es = np.concatenate([np.linspace(e[0], e[-1], 700), e, [e[0] - 1e-3, e[-1] + 1e-3, -1.0, -1.5]])
     a, sa = M.match_T(es, T, e)
     b, sb = om.match_T(es, T, e)
