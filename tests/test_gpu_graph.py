@@ -62,8 +62,10 @@ def test_graph_replays_equal_the_plain_fill(dtype):
     g.set_timing(True)
     for rep in range(3):                          # record, then two replays
         _assert_same(_host(g.fill(T, 17, 40, 4)), ref)
-        ms, launches, _ = g.timing()
+        ms, launches, site_sweeps = g.timing()
         assert launches > 0 and ms > 0
+        # every sweep of the fill covers every site of every chain once
+        assert site_sweeps == (17 + 40) * sum(z.size * ch for z, _, ch in _grids())
         # eager work between replays
         g.specific_energy()
         x = torch.ones(1 << 16, device="cuda").cumsum(0)
