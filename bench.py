@@ -7,7 +7,9 @@ HBM: mpr_reinit (Eq. 2 bounds, gap-site plan, hot start), mpr_specific_energy
 mpr_autotune (a cached lookup after the first step) and mpr_fill
 (Algorithm 2 with fixed counts: equilibration with the a-rule, sampling,
 conditional mean and std; in the FP32 arm replayed from a hipGraph).  The
-context and its workspace are set up once per arm, outside the timed steps.
+context and its workspace are set up once per arm, outside the timed steps;
+before the FP32 arm's context is built, mpr_autotune_tile picks its tile
+shape (set-up, untimed, skipped with --no-autotune or an explicit --tile).
 
 Prints one JSON line.  value = spin-updates/s (hybrid updates of gap sites,
 whole job); realisations/s is reported beside it.  The default workload is
@@ -584,6 +586,17 @@ def main():
 
     prm32 = M.default_params(dtype="fp32", seed=W["seed"], sweeps_per_pass=args.sweeps_per_pass,
                              tile_x=args.tile[0], tile_y=args.tile[1], boundary=args.boundary)
+    tile_tuned = None
+    if not args.no_autotune and tuple(args.tile) == (0, 0):
+        # Set-up, untimed: the tile shape (and the depth its LDS allows) at
+        # the workload's own T, chosen before the context is built.
+        f0 = M.Field(dev_grids, prm32)
+        T0, _ = M.match_T(f0.specific_energy(M.SAMPLE_PAIRS)[0], table[0], table[1])
+        f0.close()
+        del f0
+        tile_tuned = M.autotune_tile(dev_grids, T0, W["n_eq"], W["n_samp"], params=prm32, trial_sweeps=16)
+        prm32.tile_x, prm32.tile_y, prm32.sweeps_per_pass = tile_tuned
+        torch.cuda.empty_cache()
     dt32, out32, (kms, kl, kss) = run_arm(M, dev_grids, W, table, prm32, args.steps, args.warmup, graph=True,
                                           tune=not args.no_autotune)
     mae32 = fill_mae(W, out32[0])
@@ -613,11 +626,12 @@ def main():
     # multi-sweep shape; the bytes a pass moves do not depend on the
     # workgroup size the single-sweep passes run with.
     default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
-                      and args.boundary == "open"
+                      and tile_tuned in (None, (64, 64, 8)) and args.boundary == "open"
                       and "MPR_SWEEP_THREADS" not in os.environ and tuple(out32[5])[:2] in ((8, 1024), (0, None)))
     cfg = dict(W["config"])
     cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"], "n_samp": W["n_samp"],
                 "stride": W["stride"], "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
+                "tile_autotuned": tile_tuned is not None,
                 "sweeps_per_pass_max": prm32.sweeps_per_pass or 8,
                 "autotuned_shape": {"sweeps_per_pass": out32[5][0], "threads": out32[5][1],
                                     "threads_single_sweep_passes": out32[5][2]}, "fill_graph": True,

@@ -349,6 +349,37 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
                         int32_t *threads1_out);
 
 /*
+ * Tile autotuner: choose the tile shape (mpr_params.tile_x, tile_y) and the
+ * most sweeps per pass (sweeps_per_pass) for mpr_init_field of these grids
+ * and params, before any context exists.  Each candidate tile (FP32: 64x64,
+ * 32x32, 64x32, 128x32, 128x64, 96x96; FP64: 32x32, 16x16, 32x16, 64x32,
+ * 64x64), at the largest sweeps_per_pass up to p->sweeps_per_pass (or the
+ * default, 8 in FP32 and 1 in FP64) whose LDS the device holds, is set up
+ * as a context in the workspace and its launch shape tuned as by
+ * mpr_autotune at the host temperatures T[n_grids]; the tile whose fill
+ * would take the least time wins, a fill costed as n_eq sweeps at one sweep
+ * per pass (the a-rule's pace when adapt_every == 1, else the tuned pace)
+ * plus n_samp sweeps at the tuned pace.  The library default wins ties.
+ * Tiling and fusion do not change results (every tile keeps the
+ * checkerboard order of Sec. 5.2), so the choice affects speed only.  p's own tile is
+ * ignored.  Choices, and each candidate's launch shape, are cached per
+ * batch shape for the process; mpr_autotune on a context initialised with
+ * the chosen tile and sweeps_per_pass then reuses the cached shape.
+ *
+ * workspace: device memory, 256-byte aligned, of at least *ws_bytes bytes
+ *   (the largest candidate's mpr_init_field need); with workspace == NULL
+ *   the call only writes that size to *ws_bytes.  Its contents are scratch.
+ * tile_x, tile_y, sweeps_per_pass (nullable) receive the choice.
+ * Errors: those of mpr_init_field for the grids and params; MPR_E_ARG for
+ *   n_eq < 0, n_samp < 0, n_eq + n_samp < 1, trial_sweeps < 1 or no
+ *   candidate that fits the LDS at a requested sweeps_per_pass.
+ * Synchronises the stream.
+ */
+mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_params *p, const double *T,
+                             int32_t n_eq, int32_t n_samp, int32_t trial_sweeps, void *workspace, size_t *ws_bytes,
+                             void *hip_stream, int32_t *tile_x, int32_t *tile_y, int32_t *sweeps_per_pass);
+
+/*
  * Kernel timing, for measurement.  With enable != 0 every later run of
  * back-to-back sweep-kernel launches (one mpr_sweep call, or one phase of
  * mpr_fill) is bracketed by two HIP events on the context's stream, with no

@@ -265,18 +265,20 @@ void bind(Views &v, const Views &o, void *ws) {
 
 // LDS extent of a pass with nsw sweeps: tile + 2*(2*nsw + 1) halo + a ring,
 // or the whole grid plus its ring when that is smaller.
-void lds_extent(const mpr_ctx *c, int nsw, int &w, int &h, size_t &bytes) {
+void lds_extent(const Plan &pl, int nsw, int &w, int &h, size_t &bytes) {
   const int H = 2 * nsw + 1;
   w = 0;
   h = 0;
-  for (const GridDesc &d : c->plan.gd) {
-    w = std::max(w, std::min(c->plan.tile_x + 2 * H + 2, d.nx + 3));
-    h = std::max(h, std::min(c->plan.tile_y + 2 * H + 2, d.ny + 2));
+  for (const GridDesc &d : pl.gd) {
+    w = std::max(w, std::min(pl.tile_x + 2 * H + 2, d.nx + 3));
+    h = std::max(h, std::min(pl.tile_y + 2 * H + 2, d.ny + 2));
   }
   w = (w + 1) & ~1;
   // angle + (cos, sin) of both colours, and the staged gap-site list
-  bytes = (size_t)w * h * 3 * c->plan.elem + (size_t)w * h * 2;
+  bytes = (size_t)w * h * 3 * pl.elem + (size_t)w * h * 2;
 }
+
+void lds_extent(const mpr_ctx *c, int nsw, int &w, int &h, size_t &bytes) { lds_extent(c->plan, nsw, w, h, bytes); }
 
 double *a_buf(mpr_ctx *c, int64_t pass) { return c->v.a + (pass & 1) * c->plan.total_chains; }
 double *win_buf(mpr_ctx *c, int64_t pass) { return c->v.window + (pass & 1) * c->plan.total_chains; }
@@ -1160,45 +1162,39 @@ mpr_status mpr_set_phi(mpr_ctx *ctx, int32_t grid, int32_t chain, const double *
   return MPR_OK;
 }
 
-// Key of a batch shape for the autotuner's process-wide cache.
-static std::string tune_key(const mpr_ctx *c) {
-  std::string k = std::to_string(c->p.dtype) + ":" + std::to_string(c->plan.tile_x) + "x" +
-                  std::to_string(c->plan.tile_y) + ":" + std::to_string(c->nsw_max) + ":" +
-                  std::to_string(c->p.q == 1.0);
-  uint64_t h = 1469598103934665603ull;  // FNV-1a over the grid shapes and gap counts
-  for (const GridDesc &d : c->plan.gd)
+// FNV-1a over the grid shapes and gap counts of a batch.
+static uint64_t shape_hash(const std::vector<GridDesc> &gd) {
+  uint64_t h = 1469598103934665603ull;
+  for (const GridDesc &d : gd)
     for (int64_t v : {(int64_t)d.nx, (int64_t)d.ny, (int64_t)d.chains, d.n_gap}) {
       h ^= (uint64_t)v;
       h *= 1099511628211ull;
     }
-  return k + ":" + std::to_string(c->n_grids) + ":" + std::to_string(h);
+  return h;
+}
+
+// Key of a batch shape for the autotuners' process-wide caches: what
+// selects the kernel (precision, interaction, boundary) and the grids.
+static std::string batch_key(const mpr_params &p, const std::vector<GridDesc> &gd) {
+  return std::to_string(p.dtype) + ":" + std::to_string(p.model) + ":" + std::to_string(p.boundary) + ":" +
+         std::to_string(p.q == 1.0) + ":" + std::to_string(gd.size()) + ":" + std::to_string(shape_hash(gd));
+}
+
+static std::string tune_key(const mpr_ctx *c) {
+  return batch_key(c->p, c->plan.gd) + ":" + std::to_string(c->plan.tile_x) + "x" + std::to_string(c->plan.tile_y) +
+         ":" + std::to_string(c->nsw_max);
 }
 
 static std::mutex g_tune_mu;
 struct TuneChoice {
   int nsw, threads, threads1;  // sweeps per pass and workgroup size; workgroup size of single-sweep passes
+  double ms, ms1;              // their time per sweep; per sweep at one sweep per pass
 };
 static std::map<std::string, TuneChoice> g_tune_cache;
 
-
-mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out,
-                        int32_t *threads1_out) {
-  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
-  if (trial_sweeps < 1) return fail(ctx, MPR_E_ARG, "trial_sweeps must be >= 1");
-  const std::string key = tune_key(ctx);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      ctx->nsw_run = it->second.nsw;
-      ctx->threads = it->second.threads;
-      ctx->threads1 = it->second.threads1;
-      if (nsw_out) *nsw_out = ctx->nsw_run;
-      if (threads_out) *threads_out = ctx->threads;
-      if (threads1_out) *threads1_out = ctx->threads1;
-      return MPR_OK;
-    }
-  }
+// Time trial passes over (workgroup size x sweeps per pass) on the
+// context's grids and restore the chains afterwards.
+static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, TuneChoice &out) {
   mpr_status st = set_beta(ctx, T);
   if (st != MPR_OK) return st;
   const int64_t C = ctx->plan.total_chains;
@@ -1212,6 +1208,7 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   const int cur0 = ctx->cur;
   const int64_t sweep0 = ctx->sweep_index, pass0 = ctx->pass_no;
   const bool timing0 = ctx->timing;
+  const int nsw0 = ctx->nsw_run, thr0 = ctx->threads, thr10 = ctx->threads1;
   ctx->timing = false;
 
   hipEvent_t e0, e1;
@@ -1283,17 +1280,165 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   HIP_TRY(ctx, launch_fill_f64(ctx->v.accsum, C, 0.0, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ctx->timing = timing0;
+  ctx->nsw_run = nsw0;
+  ctx->threads = thr0;
+  ctx->threads1 = thr10;
   if (st != MPR_OK) return st;
-  ctx->nsw_run = best_nsw;
-  ctx->threads = best_thr;
-  ctx->threads1 = best_thr1;
+  out = {best_nsw, best_thr, best_thr1, best, best1};
+  return MPR_OK;
+}
+
+// The context's launch shape, from the cache or timed.
+static mpr_status tuned_shape(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, TuneChoice &ch) {
+  const std::string key = tune_key(ctx);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_nsw, best_thr, best_thr1};
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      ch = it->second;
+      return MPR_OK;
+    }
   }
-  if (nsw_out) *nsw_out = best_nsw;
-  if (threads_out) *threads_out = best_thr;
-  if (threads1_out) *threads1_out = best_thr1;
+  const mpr_status st = time_launch_shapes(ctx, T, trial_sweeps, ch);
+  if (st != MPR_OK) return st;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = ch;
+  return MPR_OK;
+}
+
+mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out,
+                        int32_t *threads1_out) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (trial_sweeps < 1) return fail(ctx, MPR_E_ARG, "trial_sweeps must be >= 1");
+  TuneChoice ch{};
+  const mpr_status st = tuned_shape(ctx, T, trial_sweeps, ch);
+  if (st != MPR_OK) return st;
+  ctx->nsw_run = ch.nsw;
+  ctx->threads = ch.threads;
+  ctx->threads1 = ch.threads1;
+  if (nsw_out) *nsw_out = ch.nsw;
+  if (threads_out) *threads_out = ch.threads;
+  if (threads1_out) *threads1_out = ch.threads1;
+  return MPR_OK;
+}
+
+// Tile candidates of mpr_autotune_tile, the library default first so that
+// a tie keeps it.  Tiles are even and row-major wide where they are not
+// square: a workgroup stages whole tile rows.
+static const int kTileCand32[][2] = {{64, 64}, {32, 32}, {64, 32}, {128, 32}, {128, 64}, {96, 96}};
+static const int kTileCand64[][2] = {{32, 32}, {16, 16}, {32, 16}, {64, 32}, {64, 64}};
+
+struct TileChoice {
+  int tile_x, tile_y, nsw;
+};
+static std::map<std::string, TileChoice> g_tile_cache;
+
+mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_params *p, const double *T,
+                             int32_t n_eq, int32_t n_samp, int32_t trial_sweeps, void *workspace, size_t *ws_bytes,
+                             void *hip_stream, int32_t *tile_x, int32_t *tile_y, int32_t *sweeps_per_pass) {
+  g_thread_err.clear();
+  if (!ws_bytes) return fail(nullptr, MPR_E_ARG, "ws_bytes is NULL");
+  mpr_status st = check_params(p);
+  if (st != MPR_OK) return st;
+  if (n_eq < 0 || n_samp < 0 || (int64_t)n_eq + n_samp < 1)
+    return fail(nullptr, MPR_E_ARG, "need n_eq >= 0, n_samp >= 0 and n_eq + n_samp >= 1");
+  if (trial_sweeps < 1) return fail(nullptr, MPR_E_ARG, "trial_sweeps must be >= 1");
+  Plan pl0;  // validates the grids before the device is touched
+  st = make_plan(grids, n_grids, p, workspace != nullptr, pl0);
+  if (st != MPR_OK) return st;
+  int dev = 0, lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "device query");
+  // Each candidate with the most sweeps per pass its LDS holds, up to the
+  // requested (or default) maximum.
+  struct Cand {
+    mpr_params p;
+    size_t bytes;
+  };
+  std::vector<Cand> cands;
+  const bool f64 = p->dtype == MPR_FP64;
+  const int n_cand = f64 ? (int)(sizeof(kTileCand64) / sizeof(kTileCand64[0]))
+                         : (int)(sizeof(kTileCand32) / sizeof(kTileCand32[0]));
+  const int nsw_req = p->sweeps_per_pass ? p->sweeps_per_pass : (f64 ? 1 : 8);
+  size_t need = 0;
+  for (int i = 0; i < n_cand; ++i) {
+    mpr_params pp = *p;
+    pp.tile_x = f64 ? kTileCand64[i][0] : kTileCand32[i][0];
+    pp.tile_y = f64 ? kTileCand64[i][1] : kTileCand32[i][1];
+    for (int nsw = nsw_req; nsw >= 1; --nsw) {
+      pp.sweeps_per_pass = nsw;
+      Plan pl;
+      st = make_plan(grids, n_grids, &pp, workspace != nullptr, pl);
+      if (st != MPR_OK) return st;
+      int w, h;
+      size_t b;
+      lds_extent(pl, nsw, w, h, b);
+      if (b <= (size_t)lds) {
+        cands.push_back({pp, pl.bytes});
+        need = std::max(need, pl.bytes);
+        break;
+      }
+      if (p->sweeps_per_pass) break;  // a requested depth is not lowered
+    }
+  }
+  if (cands.empty()) return fail(nullptr, MPR_E_ARG, "no candidate tile fits the device's LDS at this sweeps_per_pass");
+  if (!workspace) {
+    *ws_bytes = need;
+    return MPR_OK;
+  }
+  if (*ws_bytes < need)
+    return fail(nullptr, MPR_E_WORKSPACE,
+                "workspace of " + std::to_string(*ws_bytes) + " bytes, need " + std::to_string(need));
+  if (((uintptr_t)workspace) & 255) return fail(nullptr, MPR_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!T) return fail(nullptr, MPR_E_ARG, "T is NULL");
+
+  const std::string key = batch_key(*p, pl0.gd) + ":" + std::to_string(p->sweeps_per_pass) + ":" +
+                          std::to_string(n_eq) + ":" + std::to_string(n_samp);
+  TileChoice best{cands[0].p.tile_x, cands[0].p.tile_y, cands[0].p.sweeps_per_pass};
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tile_cache.find(key);
+    if (it != g_tile_cache.end()) {
+      best = it->second;
+      cached = true;
+    }
+  }
+  if (!cached) {
+    // Fill time model: n_eq sweeps at one sweep per pass (the a-rule's
+    // pace when it adapts after every sweep) and n_samp at the tuned pace,
+    // each candidate's launch shape tuned (or taken from the cache) on a
+    // context in the workspace.  With a longer a-rule period the
+    // equilibration passes are costed at the tuned pace too.
+    double best_cost = 1e300;
+    for (const Cand &cd : cands) {
+      mpr_ctx *c = nullptr;
+      size_t have = *ws_bytes;
+      st = mpr_init_field(&c, grids, n_grids, &cd.p, workspace, &have, hip_stream);
+      if (st != MPR_OK) return st;
+      TuneChoice ch{};
+      st = tuned_shape(c, T, trial_sweeps, ch);
+      if (st != MPR_OK) {
+        g_thread_err = c->err;
+        mpr_destroy(c);
+        return st;
+      }
+      mpr_destroy(c);
+      const double cost = n_eq * (p->adapt_every == 1 ? ch.ms1 : ch.ms) + n_samp * ch.ms;
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = {cd.p.tile_x, cd.p.tile_y, cd.p.sweeps_per_pass};
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tile_cache[key] = best;
+  }
+  e = hipStreamSynchronize((hipStream_t)hip_stream);  // the last context's set-up work
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipStreamSynchronize");
+  if (tile_x) *tile_x = best.tile_x;
+  if (tile_y) *tile_y = best.tile_y;
+  if (sweeps_per_pass) *sweeps_per_pass = best.nsw;
   return MPR_OK;
 }
 

@@ -88,6 +88,9 @@ def lib():
         L.mpr_cv_select_q.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, i32, dp, i32,
                                       ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(i32), i32, i32, i32,
                                       vp, ctypes.POINTER(ctypes.c_size_t), vp, dp, ctypes.POINTER(i32)]
+        L.mpr_autotune_tile.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), dp, i32, i32, i32, vp,
+                                        ctypes.POINTER(ctypes.c_size_t), vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32)]
         L.mpr_set_timing.argtypes = [vp, i32]
         L.mpr_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.mpr_destroy.argtypes = [vp]
@@ -96,7 +99,7 @@ def lib():
         L.mpr_last_error.restype = ctypes.c_char_p
         for name in ("mpr_init_field", "mpr_sweep", "mpr_specific_energy", "mpr_match_T", "mpr_fill",
                      "mpr_get_phi", "mpr_set_phi", "mpr_get_chain_state", "mpr_set_chain_state",
-                     "mpr_set_timing", "mpr_get_timing", "mpr_autotune"):
+                     "mpr_set_timing", "mpr_get_timing", "mpr_autotune", "mpr_autotune_tile"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -205,6 +208,53 @@ def cv_select_q(z, known, fold, n_folds, qs, tables, n_eq, n_samp, stride, param
                 q=float(q[best.value]))
 
 
+def _grid_array(grids):
+    """ctypes mpr_grid[] for (z, known, chains) CUDA tensors, and the
+    converted tensors to keep alive while it is used."""
+    import torch
+
+    gs = (Grid * len(grids))()
+    keep = []
+    for g, (z, known, chains) in zip(gs, grids):
+        if not (z.is_cuda and known.is_cuda):
+            raise ValueError("z and known must be CUDA tensors")
+        z = z.contiguous().to(torch.float64)
+        known = known.contiguous().to(torch.uint8)
+        if z.shape != known.shape or z.dim() != 2:
+            raise ValueError("z and known must be 2-D tensors of one shape")
+        ny, nx = z.shape
+        g.nx, g.ny, g.chains, g.reserved = nx, ny, int(chains), 0
+        g.z, g.known = z.data_ptr(), known.data_ptr()
+        keep += [z, known]
+    return gs, keep
+
+
+def autotune_tile(grids, T, n_eq, n_samp, params=None, trial_sweeps=16, stream=None):
+    """mpr_autotune_tile: the tile shape and sweeps per pass to build a
+    Field of these grids with.  grids as for Field; T: per-grid
+    temperatures.  Returns (tile_x, tile_y, sweeps_per_pass)."""
+    import torch
+
+    params = params if params is not None else default_params()
+    if not grids:
+        raise ValueError("need at least one grid")
+    gs, keep = _grid_array(grids)
+    dev = keep[0].device
+    T = np.ascontiguousarray(np.broadcast_to(np.asarray(T, dtype=np.float64), (len(grids),)))
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    L = lib()
+    n = ctypes.c_size_t(0)
+    args = (gs, len(grids), ctypes.byref(params), _dptr(T), int(n_eq), int(n_samp), int(trial_sweeps))
+    _check(L.mpr_autotune_tile(*args, None, ctypes.byref(n), None, None, None, None))
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device=dev)
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    tx, ty, nsw = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(L.mpr_autotune_tile(*args, ctypes.c_void_p(aligned), ctypes.byref(n), ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(nsw)))
+    del ws, keep
+    return tx.value, ty.value, nsw.value
+
+
 class Field:
     """A batch of gappy grids under simulation: one mpr_ctx and its workspace.
 
@@ -218,23 +268,11 @@ class Field:
 
         self._torch = torch
         self.params = params if params is not None else default_params()
-        self._keep = []
-        self.shapes = []
-        gs = (Grid * len(grids))()
-        dev = None
-        for g, (z, known, chains) in zip(gs, grids):
-            if not (z.is_cuda and known.is_cuda):
-                raise ValueError("z and known must be CUDA tensors")
-            z = z.contiguous().to(torch.float64)
-            known = known.contiguous().to(torch.uint8)
-            if z.shape != known.shape or z.dim() != 2:
-                raise ValueError("z and known must be 2-D tensors of one shape")
-            dev = z.device
-            ny, nx = z.shape
-            g.nx, g.ny, g.chains, g.reserved = nx, ny, int(chains), 0
-            g.z, g.known = z.data_ptr(), known.data_ptr()
-            self._keep += [z, known]
-            self.shapes.append((ny, nx, int(chains)))
+        if not grids:
+            raise ValueError("need at least one grid")
+        gs, self._keep = _grid_array(grids)
+        self.shapes = [(g.ny, g.nx, g.chains) for g in gs]
+        dev = self._keep[0].device
         self.device = dev
         self.n_grids = len(grids)
         self.total_chains = sum(s[2] for s in self.shapes)

@@ -15,7 +15,7 @@ from paper_1710_03038_amd import mpr as M
 def test_library_exports_every_declared_symbol():
     L = M.lib()
     names = M.header_functions()
-    assert len(names) == 21
+    assert len(names) == 22
     for n in names:
         assert hasattr(L, n), n
 
@@ -154,3 +154,26 @@ def test_cv_select_q_workspace_query_and_validation():
                dict(model=M.MODEL_GMRF), dict(n_samp=1, stride=2)):
         assert _cv_query(**kw)[0] == M.MPR_E_ARG, kw
     assert _cv_query(shape=(1, 1))[0] == M.MPR_E_SHAPE
+
+
+def _tile_query(n_eq=20, n_samp=80, trial=16, shape=(32, 40), ws_bytes=True, **prm):
+    L = M.lib()
+    g = (M.Grid * 1)()
+    g[0].ny, g[0].nx = shape
+    g[0].chains, g[0].reserved = 1, 0
+    p = M.default_params(**prm)
+    T = np.array([1.0])
+    n = ctypes.c_size_t(0)
+    rc = L.mpr_autotune_tile(g, 1, ctypes.byref(p), M._dptr(T), n_eq, n_samp, trial, None,
+                             ctypes.byref(n) if ws_bytes else None, None, None, None, None)
+    return rc, L.mpr_last_error(None)
+
+
+def test_autotune_tile_validates_before_touching_the_device():
+    # every argument error is reported before the device query, which on a
+    # machine without a GPU is the first thing to fail
+    for kw in (dict(n_eq=-1), dict(n_eq=0, n_samp=0), dict(n_samp=-5), dict(trial=0), dict(ws_bytes=False),
+               dict(q=0.7), dict(tile_x=7), dict(sweeps_per_pass=17)):
+        assert _tile_query(**kw)[0] == M.MPR_E_ARG, kw
+    assert _tile_query(shape=(1, 1))[0] == M.MPR_E_SHAPE
+    assert _tile_query(shape=(0, 4))[0] == M.MPR_E_SHAPE

@@ -440,6 +440,44 @@ def test_autotune_leaves_state_and_results_unchanged():
             assert np.array_equal(f1.get_phi(g, c).cpu().numpy(), f2.get_phi(g, c).cpu().numpy())
 
 
+TILES = {"fp32": [(64, 64), (32, 32), (64, 32), (128, 32), (128, 64), (96, 96)],
+         "fp64": [(32, 32), (16, 16), (32, 16), (64, 32), (64, 64)]}
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_autotune_tile_choice_fits_and_keeps_results(dtype):
+    # the tile autotuner returns one of its candidates at a depth that the
+    # device's LDS holds; a fill on a context built with that choice is
+    # bitwise equal to one on library-default tiles (tiling and fusion are
+    # invariant), and a second call returns the cached choice
+    import torch
+    from paper_1710_03038_amd import mpr as M
+    from tests.gpu_util import device
+    grids = _grids(83)
+    T = [0.01, 0.05, 0.2, 1.0, 0.003]
+    dev = device()
+    ts = [(torch.from_numpy(z).to(dev), torch.from_numpy(k).to(dev), c) for z, k, c in grids]
+    prm = M.default_params(dtype=dtype, seed=5)
+    tx, ty, nsw = M.autotune_tile(ts, T, 10, 30, params=prm, trial_sweeps=4)
+    assert (tx, ty) in TILES[dtype]
+    assert 1 <= nsw <= (8 if dtype == "fp32" else 1)
+    assert M.autotune_tile(ts, T, 10, 30, params=prm, trial_sweeps=4) == (tx, ty, nsw)
+    f_t = make_field(grids, dtype=dtype, seed=5, tile_x=tx, tile_y=ty, sweeps_per_pass=nsw)
+    n_t = f_t.autotune(T, 4)[0]
+    assert 1 <= n_t <= nsw
+    f_d = make_field(grids, dtype=dtype, seed=5)
+    zh_t, zs_t, rep_t = f_t.fill(T, 6, 12, 3)
+    zh_d, zs_d, rep_d = f_d.fill(T, 6, 12, 3)
+    for a, b in zip(zh_t, zh_d):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    for a, b in zip(zs_t, zs_d):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert np.array_equal(rep_t["a_eq"], rep_d["a_eq"]) and np.array_equal(rep_t["acc_samp"], rep_d["acc_samp"])
+    # a requested depth is kept, not lowered
+    prm4 = M.default_params(dtype=dtype, seed=5, sweeps_per_pass=2)
+    assert M.autotune_tile(ts, T, 10, 30, params=prm4, trial_sweeps=4)[2] == 2
+
+
 @pytest.mark.parametrize("shape", [(2, 65536), (65536, 3), (1, 65536)])
 @pytest.mark.parametrize("dtype,nsw", [("fp64", 2), ("fp32", 1)])
 def test_extreme_shapes(shape, dtype, nsw):
