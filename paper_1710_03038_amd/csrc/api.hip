@@ -365,6 +365,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.plan = c->v.plan;
   A.plan_cum = c->v.plan_cum;
   A.plan_dmax = c->plan.dmax;
+  A.n_items = c->plan.n_items;
   HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
   if (c->capturing) {
     c->g_launches += 1;

@@ -87,10 +87,12 @@ struct SweepArgs {
   const uint16_t *plan;
   const uint32_t *plan_cum;
   int32_t plan_dmax;
+  int64_t n_items;                 // workgroups of the launch: (grid, chain, tile) items
 };
 
 // Entries of the gap-site plan are packed into 16 bits with an offset of 32
-// around the tile origin; this bounds tile + 2 * plan_dmax + 32 <= 256.
+// around the tile origin; this bounds plan_dmax <= 32 and
+// tile + plan_dmax <= 224.
 constexpr int kPlanOffset = 32;
 constexpr int kMaxTile = 192;
 

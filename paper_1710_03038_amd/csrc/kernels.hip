@@ -24,6 +24,16 @@
 
 namespace mpr {
 
+// A launch counts its work-items in 32 bits per dimension.  Launches that
+// would pass 2^32 - 1 get rows of 65536 workgroups; each kernel takes its
+// linear workgroup index and skips those past its count.
+static dim3 block_grid(int64_t n_blocks, int threads) {
+  if (n_blocks * threads <= 0xFFFFFFFFLL) return dim3((unsigned)n_blocks);
+  return dim3(65536u, (unsigned)((n_blocks + 65535) / 65536));
+}
+__device__ __forceinline__ int64_t block_index() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+
+
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon et al., SC'11): rounds multiply words 0 and 2 by
 // 0xD2511F53 and 0xCD9E8D57 (32x32 -> 64 bit), swap and xor in the key; the
@@ -387,7 +397,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   __shared__ double red_d[NT / 64];
   __shared__ uint32_t acc_lds[kMaxPass];
 
-  const int64_t item = blockIdx.x;
+  const int64_t item = block_index();
+  if (item >= A.n_items) return;  // the ragged last row of a two-row launch
   const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin);
   const GridDesc G = A.grids[gi];  // by value: kept in registers across LDS stores
   const int64_t local = item - G.item_begin;
@@ -636,11 +647,12 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 // may vary between runs; the sweep's results do not depend on it.
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
-    k_plan(const GridDesc *grids, int n_grids, const P *state, int tile_x, int tile_y, int dmax, uint16_t *plan,
-           uint32_t *plan_cum) {
+    k_plan(const GridDesc *grids, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y, int dmax,
+           uint16_t *plan, uint32_t *plan_cum) {
   __shared__ uint32_t cnt[2][2 * kMaxPass + 2];
   __shared__ uint32_t cur[2][2 * kMaxPass + 2];
-  const int64_t item = blockIdx.x;
+  const int64_t item = block_index();
+  if (item >= n_tiles) return;
   const int gi = find_by(grids, n_grids, item, &GridDesc::plan_begin);
   const GridDesc G = grids[gi];
   const int t = (int)(item - G.plan_begin);
@@ -694,8 +706,8 @@ __global__ void __launch_bounds__(kThreads)
 template <typename P>
 hipError_t launch_plan(const GridDesc *g, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y,
                        int dmax, uint16_t *plan, uint32_t *plan_cum, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan<P>, dim3((unsigned)n_tiles), dim3(kThreads), 0, s, g, n_grids, state, tile_x, tile_y, dmax,
-                     plan, plan_cum);
+  hipLaunchKernelGGL(k_plan<P>, block_grid(n_tiles, kThreads), dim3(kThreads), 0, s, g, n_grids, n_tiles, state, tile_x,
+                     tile_y, dmax, plan, plan_cum);
   return hipGetLastError();
 }
 template hipError_t launch_plan<float>(const GridDesc *, int, int64_t, const float *, int, int, int, uint16_t *,
@@ -719,7 +731,7 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
 
 template <typename P, int MODEL, bool REP, bool STASH>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  const dim3 grid((unsigned)n_items);
+  const dim3 grid = block_grid(n_items, threads);
   switch (threads) {
     case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, STASH>), grid, dim3(256), lds, s, a); break;
     case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, STASH>), grid, dim3(512), lds, s, a); break;
@@ -773,9 +785,11 @@ template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int64_t
 // Eq. (2) needs z_min, z_max over the samples of each grid.  Stage 1: one
 // workgroup per chunk of kChunk sites -> (min, max, #samples, #non-finite).
 __global__ void __launch_bounds__(kThreads)
-    k_minmax(const GridDesc *grids, int n_grids, const double *const *zp, const uint8_t *const *kp, double *part) {
+    k_minmax(const GridDesc *grids, int n_grids, int64_t n_blocks, const double *const *zp, const uint8_t *const *kp,
+             double *part) {
   __shared__ double smin[kThreads], smax[kThreads], scnt[kThreads], sbad[kThreads];
-  const int64_t b = blockIdx.x;
+  const int64_t b = block_index();
+  if (b >= n_blocks) return;
   const int gi = find_by(grids, n_grids, b, &GridDesc::sb_begin);
   const GridDesc &G = grids[gi];
   const int64_t n = (int64_t)G.nx * G.ny;
@@ -820,7 +834,8 @@ __global__ void __launch_bounds__(kThreads)
 __global__ void __launch_bounds__(kThreads)
     k_minmax_final(const GridDesc *grids, int n_grids, const double *part, double *out) {
   __shared__ double smin[kThreads], smax[kThreads], scnt[kThreads], sbad[kThreads];
-  const int gi = blockIdx.x;
+  const int64_t gi = block_index();
+  if (gi >= n_grids) return;
   const GridDesc &G = grids[gi];
   const int64_t nb = (gi + 1 < n_grids ? grids[gi + 1].sb_begin : G.sb_begin + ((int64_t)G.nx * G.ny + kChunk - 1) / kChunk) - G.sb_begin;
   double mn = INFINITY, mx = -INFINITY, cnt = 0, bad = 0;
@@ -855,11 +870,12 @@ __global__ void __launch_bounds__(kThreads)
 
 hipError_t launch_minmax(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
                          const uint8_t *const *known, double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_minmax, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, z, known, part);
+  hipLaunchKernelGGL(k_minmax, block_grid(n_blocks, kThreads), dim3(kThreads), 0, s, g, n_grids, n_blocks, z, known,
+                     part);
   return hipGetLastError();
 }
 hipError_t launch_minmax_final(const GridDesc *g, int n_grids, const double *part, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_minmax_final, dim3((unsigned)n_grids), dim3(kThreads), 0, s, g, n_grids, part, out);
+  hipLaunchKernelGGL(k_minmax_final, block_grid(n_grids, kThreads), dim3(kThreads), 0, s, g, n_grids, part, out);
   return hipGetLastError();
 }
 
@@ -869,9 +885,10 @@ hipError_t launch_minmax_final(const GridDesc *g, int n_grids, const double *par
 // one chain.  The hot start draws the u word of sweep 0xFFFFFFFF.
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
-    k_init(const GridDesc *grids, int n_grids, const double *const *zp, const uint8_t *const *kp, P *s0, P *s1,
-           uint32_t k0, uint32_t k1) {
-  const int64_t b = blockIdx.x;
+    k_init(const GridDesc *grids, int n_grids, int64_t n_blocks, const double *const *zp, const uint8_t *const *kp,
+           P *s0, P *s1, uint32_t k0, uint32_t k1) {
+  const int64_t b = block_index();
+  if (b >= n_blocks) return;
   const int gi = find_by(grids, n_grids, b, &GridDesc::cb_begin);
   const GridDesc &G = grids[gi];
   const int64_t n = (int64_t)G.nx * G.ny;
@@ -903,7 +920,8 @@ __global__ void __launch_bounds__(kThreads)
 template <typename P>
 hipError_t launch_init(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z,
                        const uint8_t *const *known, P *s0, P *s1, P, uint32_t k0, uint32_t k1, hipStream_t s) {
-  hipLaunchKernelGGL(k_init<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, z, known, s0, s1, k0, k1);
+  hipLaunchKernelGGL(k_init<P>, block_grid(n_blocks, kThreads), dim3(kThreads), 0, s, g, n_grids, n_blocks, z, known, s0,
+                     s1, k0, k1);
   return hipGetLastError();
 }
 template hipError_t launch_init<float>(const GridDesc *, int, int64_t, const double *const *, const uint8_t *const *,
@@ -927,9 +945,10 @@ template <typename P> __device__ __forceinline__ P pair_eps(P d, P q, int gmrf) 
 
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
-    k_energy(const GridDesc *grids, int n_grids, int what, const P *state, int gmrf, double *part) {
+    k_energy(const GridDesc *grids, int n_grids, int64_t n_blocks, int what, const P *state, int gmrf, double *part) {
   __shared__ double red[kThreads / 64];
-  const int64_t b = blockIdx.x;
+  const int64_t b = block_index();
+  if (b >= n_blocks) return;
   const int gi = find_by(grids, n_grids, b, what ? &GridDesc::cb_begin : &GridDesc::sb_begin);
   const GridDesc &G = grids[gi];
   const P q = (P)G.q;
@@ -971,9 +990,10 @@ __global__ void __launch_bounds__(kThreads)
 
 // One workgroup per unit (grid or chain): fixed-order sum of its partials.
 __global__ void __launch_bounds__(kThreads)
-    k_energy_final(const GridDesc *grids, int n_grids, int what, const double *part, double *out) {
+    k_energy_final(const GridDesc *grids, int n_grids, int what, int n_units, const double *part, double *out) {
   __shared__ double red[kThreads / 64];
-  const int unit = blockIdx.x;
+  const int unit = (int)block_index();
+  if (unit >= n_units) return;
   int gi = 0, chain = 0;
   if (what) {
     int lo = 0, hi = n_grids - 1;
@@ -1006,8 +1026,8 @@ __global__ void __launch_bounds__(kThreads)
 template <typename P>
 hipError_t launch_energy(const GridDesc *g, int n_grids, int64_t n_blocks, int what, const P *state, int gmrf,
                          double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, what, state, gmrf,
-                     part);
+  hipLaunchKernelGGL(k_energy<P>, block_grid(n_blocks, kThreads), dim3(kThreads), 0, s, g, n_grids, n_blocks, what, state,
+                     gmrf, part);
   return hipGetLastError();
 }
 template hipError_t launch_energy<float>(const GridDesc *, int, int64_t, int, const float *, int, double *,
@@ -1016,7 +1036,8 @@ template hipError_t launch_energy<double>(const GridDesc *, int, int64_t, int, c
                                           hipStream_t);
 hipError_t launch_energy_final(const GridDesc *g, int n_grids, int what, int n_units, const double *part,
                                double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_final, dim3((unsigned)n_units), dim3(kThreads), 0, s, g, n_grids, what, part, out);
+  hipLaunchKernelGGL(k_energy_final, block_grid(n_units, kThreads), dim3(kThreads), 0, s, g, n_grids, what, n_units, part,
+                     out);
   return hipGetLastError();
 }
 
@@ -1094,8 +1115,9 @@ hipError_t launch_measures(const double *z, const double *zh, const uint8_t *kno
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
     k_finalize(const GridDesc *grids, int n_grids, const double *const *zp, const P *state, const P *ref, const P *s1,
-               const P *s2, int32_t records, double *zhat, double *zstd) {
-  const int64_t b = blockIdx.x;
+               const P *s2, int32_t records, int64_t n_blocks, double *zhat, double *zstd) {
+  const int64_t b = block_index();
+  if (b >= n_blocks) return;
   const int gi = find_by(grids, n_grids, b, &GridDesc::sb_begin);
   const GridDesc &G = grids[gi];
   const int64_t n = (int64_t)G.nx * G.ny;
@@ -1134,8 +1156,8 @@ template <typename P>
 hipError_t launch_finalize(const GridDesc *g, int n_grids, int64_t n_blocks, const double *const *z, const P *state,
                            const P *ref, const P *s1, const P *s2, int32_t records, double *zhat, double *zstd,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize<P>, dim3((unsigned)n_blocks), dim3(kThreads), 0, s, g, n_grids, z, state, ref, s1, s2,
-                     records, zhat, zstd);
+  hipLaunchKernelGGL(k_finalize<P>, block_grid(n_blocks, kThreads), dim3(kThreads), 0, s, g, n_grids, z, state, ref, s1,
+                     s2, records, n_blocks, zhat, zstd);
   return hipGetLastError();
 }
 template hipError_t launch_finalize<float>(const GridDesc *, int, int64_t, const double *const *, const float *,
@@ -1147,11 +1169,11 @@ template hipError_t launch_finalize<double>(const GridDesc *, int, int64_t, cons
 
 // ------------------------------------------------------------ state copies
 template <typename P> __global__ void k_get_phi(const P *st, int64_t n, double *out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = block_index() * blockDim.x + threadIdx.x;
   if (i < n) out[i] = fabs((double)st[i]);
 }
 template <typename P> __global__ void k_set_phi(P *s0, P *s1, int64_t n, const double *in) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = block_index() * blockDim.x + threadIdx.x;
   if (i >= n || signbit(s0[i])) return;  // sample sites keep their angle
   P v = (P)in[i];
   v = (v > P(0)) ? v : P(0);  // also turns -0 into +0
@@ -1160,11 +1182,11 @@ template <typename P> __global__ void k_set_phi(P *s0, P *s1, int64_t n, const d
   s1[i] = v;
 }
 template <typename P> hipError_t launch_get_phi(const P *st, int64_t n, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_get_phi<P>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, st, n, out);
+  hipLaunchKernelGGL(k_get_phi<P>, block_grid((n + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0, s, st, n, out);
   return hipGetLastError();
 }
 template <typename P> hipError_t launch_set_phi(P *s0, P *s1, int64_t n, const double *in, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_phi<P>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, s0, s1, n,
+  hipLaunchKernelGGL(k_set_phi<P>, block_grid((n + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0, s, s0, s1, n,
                      in);
   return hipGetLastError();
 }
@@ -1174,30 +1196,30 @@ template hipError_t launch_set_phi<float>(float *, float *, int64_t, const doubl
 template hipError_t launch_set_phi<double>(double *, double *, int64_t, const double *, hipStream_t);
 
 __global__ void k_fill_f64(double *p, int64_t n, double v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = block_index() * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 __global__ void k_zero_u32(uint32_t *p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = block_index() * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
 }
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_fill_f64, block_grid((n + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, p, n);
+  hipLaunchKernelGGL(k_zero_u32, block_grid((n + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0, s, p, n);
   return hipGetLastError();
 }
 __global__ void k_copy_f64(double *dst, const double *src, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = block_index() * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
 }
 hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, dst, src, n);
+  hipLaunchKernelGGL(k_copy_f64, block_grid((n + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0, s, dst, src, n);
   return hipGetLastError();
 }
 
@@ -1207,7 +1229,7 @@ hipError_t launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_
 // the validation measures see only the held-out samples).
 __global__ void k_cv_prepare(const double *z, const uint8_t *known, const uint8_t *fold, int n_folds, int64_t n,
                              uint8_t *masks, double *zt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = block_index() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const bool smp = known[i] != 0;
   const int f = fold[i];
@@ -1221,7 +1243,7 @@ __global__ void k_cv_prepare(const double *z, const uint8_t *known, const uint8_
 hipError_t launch_cv_prepare(const double *z, const uint8_t *known, const uint8_t *fold, int n_folds, int64_t n,
                              uint8_t *masks, double *zt, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cv_prepare, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z, known,
+  hipLaunchKernelGGL(k_cv_prepare, block_grid((n + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0, s, z, known,
                      fold, n_folds, n, masks, zt);
   return hipGetLastError();
 }
