@@ -359,7 +359,9 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
  * mpr_autotune at the host temperatures T[n_grids]; the tile whose fill
  * would take the least time wins, a fill costed as n_eq sweeps at one sweep
  * per pass (the a-rule's pace when adapt_every == 1, else the tuned pace)
- * plus n_samp sweeps at the tuned pace.  The library default wins ties.
+ * plus n_samp sweeps at the tuned pace.  Another tile replaces the library
+ * default (the first candidate) only when its fill costs at least 3 % less:
+ * closer candidates differ by timing noise.
  * Tiling and fusion do not change results (every tile keeps the
  * checkerboard order of Sec. 5.2), so the choice affects speed only.  p's own tile is
  * ignored.  Choices, and each candidate's launch shape, are cached per

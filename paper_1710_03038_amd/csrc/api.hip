@@ -1329,6 +1329,8 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
 static const int kTileCand32[][2] = {{64, 64}, {32, 32}, {64, 32}, {128, 32}, {128, 64}, {96, 96}};
 static const int kTileCand64[][2] = {{32, 32}, {16, 16}, {32, 16}, {64, 32}, {64, 64}};
 
+static constexpr double kTileMargin = 0.97;  // a tile must cost 3 % less than the default to replace it
+
 struct TileChoice {
   int tile_x, tile_y, nsw;
 };
@@ -1412,7 +1414,7 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
     // each candidate's launch shape tuned (or taken from the cache) on a
     // context in the workspace.  With a longer a-rule period the
     // equilibration passes are costed at the tuned pace too.
-    double best_cost = 1e300;
+    double best_cost = 1e300, default_cost = 1e300;
     for (const Cand &cd : cands) {
       mpr_ctx *c = nullptr;
       size_t have = *ws_bytes;
@@ -1427,11 +1429,16 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
       }
       mpr_destroy(c);
       const double cost = n_eq * (p->adapt_every == 1 ? ch.ms1 : ch.ms) + n_samp * ch.ms;
+      if (&cd == &cands[0]) default_cost = cost;
       if (cost < best_cost) {
         best_cost = cost;
         best = {cd.p.tile_x, cd.p.tile_y, cd.p.sweeps_per_pass};
       }
     }
+    // Another tile replaces the default only when it is clearly faster:
+    // candidates within a few per cent of each other differ by timing noise.
+    if (best_cost > kTileMargin * default_cost)
+      best = {cands[0].p.tile_x, cands[0].p.tile_y, cands[0].p.sweeps_per_pass};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tile_cache[key] = best;
   }
