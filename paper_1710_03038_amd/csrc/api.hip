@@ -1396,7 +1396,16 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
   if (((uintptr_t)workspace) & 255) return fail(nullptr, MPR_E_WORKSPACE, "workspace must be 256-byte aligned");
   if (!T) return fail(nullptr, MPR_E_ARG, "T is NULL");
 
-  const std::string key = batch_key(*p, pl0.gd) + ":" + std::to_string(p->sweeps_per_pass) + ":" +
+  // Each candidate is set up as a context in the workspace.  The cache key
+  // holds the grids' gap counts, known once the first context exists.
+  auto init_cand = [&](const Cand &cd, mpr_ctx *&c) {
+    size_t have = *ws_bytes;
+    return mpr_init_field(&c, grids, n_grids, &cd.p, workspace, &have, hip_stream);
+  };
+  mpr_ctx *c0 = nullptr;
+  st = init_cand(cands[0], c0);
+  if (st != MPR_OK) return st;
+  const std::string key = batch_key(*p, c0->plan.gd) + ":" + std::to_string(p->sweeps_per_pass) + ":" +
                           std::to_string(n_eq) + ":" + std::to_string(n_samp);
   TileChoice best{cands[0].p.tile_x, cands[0].p.tile_y, cands[0].p.sweeps_per_pass};
   bool cached = false;
@@ -1408,18 +1417,22 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
       cached = true;
     }
   }
-  if (!cached) {
+  if (cached) {
+    mpr_destroy(c0);
+  } else {
     // Fill time model: n_eq sweeps at one sweep per pass (the a-rule's
     // pace when it adapts after every sweep) and n_samp at the tuned pace,
-    // each candidate's launch shape tuned (or taken from the cache) on a
-    // context in the workspace.  With a longer a-rule period the
-    // equilibration passes are costed at the tuned pace too.
+    // each candidate's launch shape tuned (or taken from the cache).  With
+    // a longer a-rule period the equilibration passes are costed at the
+    // tuned pace too.
     double best_cost = 1e300, default_cost = 1e300;
-    for (const Cand &cd : cands) {
-      mpr_ctx *c = nullptr;
-      size_t have = *ws_bytes;
-      st = mpr_init_field(&c, grids, n_grids, &cd.p, workspace, &have, hip_stream);
-      if (st != MPR_OK) return st;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      mpr_ctx *c = c0;
+      c0 = nullptr;
+      if (i > 0) {
+        st = init_cand(cands[i], c);
+        if (st != MPR_OK) return st;
+      }
       TuneChoice ch{};
       st = tuned_shape(c, T, trial_sweeps, ch);
       if (st != MPR_OK) {
@@ -1429,10 +1442,10 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
       }
       mpr_destroy(c);
       const double cost = n_eq * (p->adapt_every == 1 ? ch.ms1 : ch.ms) + n_samp * ch.ms;
-      if (&cd == &cands[0]) default_cost = cost;
+      if (i == 0) default_cost = cost;
       if (cost < best_cost) {
         best_cost = cost;
-        best = {cd.p.tile_x, cd.p.tile_y, cd.p.sweeps_per_pass};
+        best = {cands[i].p.tile_x, cands[i].p.tile_y, cands[i].p.sweeps_per_pass};
       }
     }
     // Another tile replaces the default only when it is clearly faster:
