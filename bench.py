@@ -594,8 +594,13 @@ def main():
         T0, _ = M.match_T(f0.specific_energy(M.SAMPLE_PAIRS)[0], table[0], table[1])
         f0.close()
         del f0
-        tile_tuned = M.autotune_tile(dev_grids, T0, W["n_eq"], W["n_samp"], params=prm32, trial_sweeps=16)
+        # trial runs of 16 sweeps on small batches, 8 on batches of 2.5e7
+        # sites or more (shorter runs let one-off delays sway the choice)
+        site_chains = sum(k.size * c for (_, k), c in zip(W["grids"], W["chains"]))
+        trial = int(np.clip(16 * 1.25e7 / site_chains, 8, 16))
+        tile_tuned = M.autotune_tile(dev_grids, T0, W["n_eq"], W["n_samp"], params=prm32, trial_sweeps=trial)
         prm32.tile_x, prm32.tile_y, prm32.sweeps_per_pass = tile_tuned
+        print("tile autotuned: %d x %d, up to %d sweeps per pass" % tile_tuned, file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     dt32, out32, (kms, kl, kss) = run_arm(M, dev_grids, W, table, prm32, args.steps, args.warmup, graph=True,
                                           tune=not args.no_autotune)
