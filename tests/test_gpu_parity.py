@@ -365,6 +365,76 @@ def test_fill_fp64_statistics_match_oracle():
     assert abs(mg - mo) <= 3 * math.hypot(sg, so) + 1e-12, (mg, mo, sg, so)
 
 
+def test_fill_fp32_ensemble_matches_oracle():
+    # FP32 chains leave the oracle's trajectory after a few dozen sweeps, so
+    # the FP32 fill is compared as an ensemble over 16 seeds: e_s and T-hat
+    # per seed to FP32 rounding, and the gap-fill MAE, the specific energy
+    # of the final state (Eq. 5) and the sampling acceptance in the mean,
+    # each within 3 combined standard errors of the oracle's
+    import mprgen
+    from oracle.etable import load_table
+    from paper_1710_03038_amd import mpr as M
+    tT, te, _ = load_table()
+    z = mprgen.gaussian_field(32, 32, 4.0, 15, 50.0, 10.0)
+    known = mprgen.mask_random(32, 32, 0.5, 16)
+    kn = known.astype(bool)
+    phi_s, _, _ = om.transform(z, kn)
+    eo, _, _ = om.sample_specific_energy(phi_s, kn, 0.5)
+    To, _ = om.match_T(np.array([eo]), tT, te)
+    g = {"mae": [], "e": [], "acc": []}
+    o = {"mae": [], "e": [], "acc": []}
+    for r in range(16):
+        seed = 4100 + r
+        f = make_field([(z, known, 1)], dtype="fp32", seed=seed)
+        e_s, _ = f.specific_energy(0)
+        That, _ = M.match_T(e_s, tT, te)
+        assert abs(e_s[0] - eo) < 1e-5
+        assert abs(That[0] - To[0]) <= 1e-4 * To[0]
+        zh, _, rep = f.fill(That, 30, 60, 2)
+        e_fin, _ = f.specific_energy(1)
+        f.close()
+        out = om.fill(z, kn, To[0], 30, 60, 2, seed=seed)
+        g["mae"].append(om.mae(z, zh[0].cpu().numpy(), ~kn))
+        o["mae"].append(om.mae(z, out["z_hat"], ~kn))
+        g["e"].append(e_fin[0])
+        o["e"].append(om.state_specific_energy(out["phi"], 0.5)[0][0])
+        g["acc"].append(rep["acc_samp"][0])
+        o["acc"].append(out["acc_samp"].mean())
+    for k in g:
+        a, b = np.asarray(g[k]), np.asarray(o[k])
+        se = math.hypot(a.std(ddof=1), b.std(ddof=1)) / math.sqrt(len(a))
+        assert abs(a.mean() - b.mean()) <= 3 * se + 1e-12, (k, a.mean(), b.mean(), se)
+
+
+def test_batched_chains_fp32_ensemble_matches_oracle():
+    # A sub-batch of the batched-realisation workload's kind (lognormal
+    # field, 60 % gaps in 16 x 16 blocks): 48 FP32 chains of one grid in
+    # one launch against the oracle's 48 chains of the same seed.  Per chain,
+    # the specific energy of the state after the fill (Eq. 5) and the mean
+    # sampling acceptance; their means agree within 3 standard errors.
+    import mprgen
+    from oracle.etable import load_table
+    from paper_1710_03038_amd import mpr as M
+    tT, te, _ = load_table()
+    z = mprgen.lognormal_field(64, 64, 10.0, 31, log_std=0.5)
+    known = mprgen.mask_blocks(64, 64, 0.6, 32)
+    kn = known.astype(bool)
+    C, seed = 48, 4300
+    f = make_field([(z, known, C)], dtype="fp32", seed=seed)
+    e_s, _ = f.specific_energy(0)
+    That, _ = M.match_T(e_s, tT, te)
+    _, _, rep = f.fill(That, 30, 30, 3)
+    e_g, _ = f.specific_energy(1)
+    f.close()
+    out = om.fill(z, kn, That[0], 30, 30, 3, seed=seed, chains=C)
+    e_o = om.state_specific_energy(out["phi"], 0.5)[0]
+    acc_o = np.asarray(out["acc_samp"]).reshape(30, C).mean(axis=0)  # per chain, over the sampling sweeps
+    for a, b, name in ((e_g, e_o, "energy"), (rep["acc_samp"], acc_o, "acceptance")):
+        assert len(a) == C and len(b) == C
+        se = math.hypot(np.std(a, ddof=1), np.std(b, ddof=1)) / math.sqrt(C)
+        assert abs(np.mean(a) - np.mean(b)) <= 3 * se, (name, np.mean(a), np.mean(b), se)
+
+
 @pytest.mark.parametrize("stride,keep", [(1, False), (3, True)])
 def test_fill_fp64_equals_oracle_site_by_site(stride, keep):
     # A short FP64 fill (a-rule equilibration, sampling, records, the
