@@ -365,6 +365,27 @@ def test_fill_fp64_statistics_match_oracle():
     assert abs(mg - mo) <= 3 * math.hypot(sg, so) + 1e-12, (mg, mo, sg, so)
 
 
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_grid_alone_equals_grid_in_batch(dtype):
+    # A grid's chains depend only on that grid: alone, or first in a batch
+    # of five grids of other shapes (so with the same grid index, which keys
+    # its random stream), its fill and report come out the same bit for bit
+    grids = _grids(97, chains=3)
+    T = [0.02, 0.1, 0.005, 0.3, 0.05]
+    f_b = make_field(grids, dtype=dtype, seed=8)
+    f_a = make_field(grids[:1], dtype=dtype, seed=8)
+    zh_b, zs_b, rep_b = f_b.fill(T, 12, 24, 3)
+    zh_a, zs_a, rep_a = f_a.fill(T[:1], 12, 24, 3)
+    assert np.array_equal(zh_a[0].cpu().numpy(), zh_b[0].cpu().numpy())
+    assert np.array_equal(zs_a[0].cpu().numpy(), zs_b[0].cpu().numpy())
+    for k in ("a_eq", "acc_eq", "acc_samp"):
+        assert np.array_equal(rep_a[k], rep_b[k][:3]), k
+    for c in range(3):
+        assert np.array_equal(f_a.get_phi(0, c).cpu().numpy(), f_b.get_phi(0, c).cpu().numpy())
+    f_a.close()
+    f_b.close()
+
+
 def test_fill_fp32_ensemble_matches_oracle():
     # FP32 chains leave the oracle's trajectory after a few dozen sweeps, so
     # the FP32 fill is compared as an ensemble over 16 seeds: e_s and T-hat
