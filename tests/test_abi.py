@@ -177,3 +177,30 @@ def test_autotune_tile_validates_before_touching_the_device():
         assert _tile_query(**kw)[0] == M.MPR_E_ARG, kw
     assert _tile_query(shape=(1, 1))[0] == M.MPR_E_SHAPE
     assert _tile_query(shape=(0, 4))[0] == M.MPR_E_SHAPE
+
+
+def test_workspace_too_small_or_misaligned_is_rejected_before_any_device_call():
+    # the size and alignment checks come before the context touches the
+    # device, so placeholder (never dereferenced) pointers suffice here
+    L = M.lib()
+    g = (M.Grid * 1)()
+    g[0].ny, g[0].nx, g[0].chains, g[0].reserved = 16, 16, 1, 0
+    g[0].z, g[0].known = 4096, 8192
+    p = M.default_params()
+    need = M.workspace_bytes([(16, 16, 1)], p)
+    ctx = ctypes.c_void_p()
+    for ws, size in ((1 << 20, need - 1), (256 + 1, need), (256 + 128, need)):
+        n = ctypes.c_size_t(size)
+        rc = L.mpr_init_field(ctypes.byref(ctx), g, 1, ctypes.byref(p), ctypes.c_void_p(ws), ctypes.byref(n), None)
+        assert rc == M.MPR_E_WORKSPACE, (ws, size)
+        assert b"workspace" in L.mpr_last_error(None)
+    assert not ctx.value
+
+
+def test_autotune_tile_without_a_device_reports_the_hip_error():
+    import torch
+    rc, msg = _tile_query()
+    if torch.cuda.is_available():
+        assert rc == M.MPR_OK
+    else:
+        assert rc == M.MPR_E_HIP and b"device query" in msg

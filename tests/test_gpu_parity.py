@@ -502,6 +502,16 @@ def test_error_paths_on_device():
     e, n = f.specific_energy(0, allow_nopairs=True)
     assert math.isnan(e[0]) and n[0] == 0
     with pytest.raises(M.MPRError) as ei:
+        f.specific_energy(0)
+    assert ei.value.status == M.MPR_E_NOPAIRS
+    # samples on one colour only: no sample-sample neighbour pair for Eq. (4)
+    yy, xx = np.mgrid[0:8, 0:8]
+    f2 = make_field([(random_grid(8, 8, 0.0, 3)[0], ((xx + yy) % 2 == 0).astype(np.uint8), 1)])
+    with pytest.raises(M.MPRError) as ei:
+        f2.specific_energy(0)
+    assert ei.value.status == M.MPR_E_NOPAIRS
+    f2.close()
+    with pytest.raises(M.MPRError) as ei:
         f.fill([0.1], 1, 1, 1)
     assert ei.value.status == M.MPR_E_DEGENERATE
     with pytest.raises(M.MPRError) as ei:
