@@ -37,10 +37,12 @@ struct Views {
   double *rep = nullptr;  // fill report scratch: a and acceptance after equilibration [2][C]
   uint16_t *plan = nullptr;
   uint32_t *plan_cum = nullptr;
+  int32_t *item_grid = nullptr;  // coarse item -> grid index (SweepArgs::item_grid)
 };
 
 struct Plan {
   std::vector<GridDesc> gd;
+  std::vector<int32_t> item_grid;  // host copy of the coarse item -> grid index
   int total_chains = 0;
   int64_t n_items = 0, n_cblocks = 0, n_sblocks = 0, state_elems = 0, sites = 0;
   int64_t n_tiles = 0, plan_entries = 0;
@@ -207,6 +209,17 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   if (pl.n_items > 0x7fffffff || pl.n_cblocks > 0x7fffffff)
     return fail(nullptr, MPR_E_SHAPE, "batch too large for one launch");
   pl.total_chains = (int)chains;
+  {
+    const int64_t K = (pl.n_items - 1) / kItemStride + 1;
+    pl.item_grid.resize(K + 1);
+    int g = 0;
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t item = k * kItemStride;
+      while (g + 1 < n && pl.gd[g + 1].item_begin <= item) ++g;
+      pl.item_grid[k] = g;
+    }
+    pl.item_grid[K] = n - 1;
+  }
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -235,6 +248,7 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.rep = (double *)take(8 * 2 * C);
   v.plan = (uint16_t *)take(2 * (size_t)pl.plan_entries);
   v.plan_cum = (uint32_t *)take(4 * (size_t)pl.n_tiles * 2 * (pl.dmax + 2));
+  v.item_grid = (int32_t *)take(4 * pl.item_grid.size());
   pl.bytes = off;
   return MPR_OK;
 }
@@ -261,6 +275,7 @@ void bind(Views &v, const Views &o, void *ws) {
   v.rep = rebase(o.rep, b);
   v.plan = rebase(o.plan, b);
   v.plan_cum = rebase(o.plan_cum, b);
+  v.item_grid = rebase(o.item_grid, b);
 }
 
 // LDS extent of a pass with nsw sweeps: tile + 2*(2*nsw + 1) halo + a ring,
@@ -366,6 +381,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.plan_cum = c->v.plan_cum;
   A.plan_dmax = c->plan.dmax;
   A.n_items = c->plan.n_items;
+  A.item_grid = c->v.item_grid;
   HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
   if (c->capturing) {
     c->g_launches += 1;
@@ -681,6 +697,8 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
   } while (0)
   TRY(hipMemcpyAsync(c->v.zp, zp.data(), sizeof(void *) * n_grids, hipMemcpyHostToDevice, c->stream));
   TRY(hipMemcpyAsync(c->v.kp, kp.data(), sizeof(void *) * n_grids, hipMemcpyHostToDevice, c->stream));
+  TRY(hipMemcpyAsync(c->v.item_grid, c->plan.item_grid.data(), 4 * c->plan.item_grid.size(), hipMemcpyHostToDevice,
+                     c->stream));
   const mpr_status ist = device_init(c);
   if (ist != MPR_OK) return bail(ist);
 #undef TRY

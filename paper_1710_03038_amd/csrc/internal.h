@@ -88,7 +88,13 @@ struct SweepArgs {
   const uint32_t *plan_cum;
   int32_t plan_dmax;
   int64_t n_items;                 // workgroups of the launch: (grid, chain, tile) items
+  // Grid of item k * kItemStride, k = 0 .. (n_items - 1) / kItemStride,
+  // then n_grids - 1: the grid of an item lies between two entries.
+  const int32_t *item_grid;
 };
+
+// Items per entry of SweepArgs::item_grid.
+constexpr int kItemStride = 256;
 
 // Entries of the gap-site plan are packed into 16 bits with an offset of 32
 // around the tile origin; this bounds plan_dmax <= 32 and

@@ -148,8 +148,9 @@ template <int NT, typename T> __device__ __forceinline__ T block_sum(T v, T *scr
   return r;
 }
 
-__device__ __forceinline__ int find_by(const GridDesc *g, int n, int64_t key, int64_t GridDesc::*field) {
-  int lo = 0, hi = n - 1;
+__device__ __forceinline__ int find_by(const GridDesc *g, int n, int64_t key, int64_t GridDesc::*field, int lo = 0,
+                                       int hi = -1) {
+  if (hi < 0) hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (g[mid].*field <= key) lo = mid;
@@ -399,7 +400,10 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 
   const int64_t item = block_index();
   if (item >= A.n_items) return;  // the ragged last row of a two-row launch
-  const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin);
+  // The coarse index narrows the search to the grids between two entries
+  // (usually one or two in a batch of large grids).
+  const int64_t ik = item / kItemStride;
+  const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin, A.item_grid[ik], A.item_grid[ik + 1]);
   const GridDesc G = A.grids[gi];  // by value: kept in registers across LDS stores
   const int64_t local = item - G.item_begin;
   const int tiles = G.tiles_x * G.tiles_y;
