@@ -390,7 +390,11 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
 // 2*nsw + 1 sites covers hs = 0), so the interior is exact after the last
 // half-sweep.  When the energy of interior pairs is traced, every D is one
 // larger, so that the interior plus one ring is exact after each sweep.
-template <typename P, int NT, int MODEL, bool REP, bool STASH>
+// With RREG (an FP32 pass that records two or more sweeps), the fill sums of
+// a thread's first interior sites stay in registers for the whole pass:
+// loaded before the first record and stored after the last, instead of a
+// read-modify-write in HBM per record.  The sums are the same, term by term.
+template <typename P, int NT, int MODEL, bool REP, bool STASH, bool RREG>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
@@ -520,6 +524,35 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   // every sweep draws its own: the kernel then holds 8 registers fewer,
   // which lets two workgroups share a CU where the LDS would allow it.
   uint32_t stash0[2][2] = {}, stash1[2][2] = {};
+  // Register-held fill sums (RREG): sites f = threadIdx.x + j * NT, j < kRegSites.
+  constexpr int kRegSites = RREG ? (NT >= 512 ? 4096 / NT : 8) : 1;
+  P r_ref[kRegSites], r_s1[kRegSites], r_s2[kRegSites];
+  auto reg_site = [&](int j, int64_t &k, P &v) __attribute__((always_inline)) {
+    const int f = (int)threadIdx.x + j * NT;
+    if (f >= iw * ih) return false;
+    int r, cx;
+    split_index(f, iw, inv_iw, r, cx);
+    const int gx = x0 + cx, gy = y0 + r;
+    k = cbase + (int64_t)gy * nx + gx;
+    v = ph[((gx + gy) & 1) * plane + (gy - oy) * P2 + ((gx - ox) >> 1)];
+    return !signbit(v);  // sample sites carry no sums
+  };
+  if constexpr (RREG) {
+    // The pass's first record continues the fill's sums unless it starts them.
+    const uint32_t low = A.record_mask & (0u - A.record_mask);
+    if (!(A.first_mask & low)) {
+#pragma unroll
+      for (int j = 0; j < kRegSites; ++j) {
+        int64_t k;
+        P v;
+        if (reg_site(j, k, v)) {
+          r_ref[j] = A.acc_ref[k];
+          r_s1[j] = A.acc_s1[k];
+          r_s2[j] = A.acc_s2[k];
+        }
+      }
+    }
+  }
 
   for (int s = 0; s < A.nsw; ++s) {
     const uint32_t sweep = A.sweep0 + (uint32_t)s;
@@ -608,7 +641,24 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
     if (rec) {
       // Algorithm 2, step 5.3: one realisation; shifted sums about the first.
       const bool first = (A.first_mask >> s) & 1u;
-      for (int f = threadIdx.x; f < iw * ih; f += NT) {
+      if constexpr (RREG) {
+#pragma unroll
+        for (int j = 0; j < kRegSites; ++j) {
+          int64_t k;
+          P v;
+          if (!reg_site(j, k, v)) continue;
+          if (first) {
+            r_ref[j] = v;
+            r_s1[j] = P(0);
+            r_s2[j] = P(0);
+          } else {
+            const P d = v - r_ref[j];
+            r_s1[j] += d;
+            r_s2[j] += d * d;
+          }
+        }
+      }
+      for (int f = threadIdx.x + (RREG ? kRegSites * NT : 0); f < iw * ih; f += NT) {
         int r, cx;
         split_index(f, iw, inv_iw, r, cx);
         const int gx = x0 + cx, gy = y0 + r;
@@ -632,6 +682,19 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   __syncthreads();
   if (threadIdx.x < A.nsw && acc_lds[threadIdx.x])
     atomicAdd(&A.counts[(int64_t)gchain * kMaxPass + threadIdx.x], acc_lds[threadIdx.x]);
+
+  if constexpr (RREG) {
+    const bool started = (A.first_mask & A.record_mask) != 0;
+#pragma unroll
+    for (int j = 0; j < kRegSites; ++j) {
+      int64_t k;
+      P v;
+      if (!reg_site(j, k, v)) continue;
+      if (started) A.acc_ref[k] = r_ref[j];
+      A.acc_s1[k] = r_s1[j];
+      A.acc_s2[k] = r_s2[j];
+    }
+  }
 
   P *dst = A.dst + cbase;
   for (int f = threadIdx.x; f < iw * ih; f += NT) {
@@ -733,21 +796,21 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
   apply_pass_end(A, A.grids[lo], ch, true);
 }
 
-template <typename P, int MODEL, bool REP, bool STASH>
+template <typename P, int MODEL, bool REP, bool STASH, bool RREG>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   const dim3 grid = block_grid(n_items, threads);
   switch (threads) {
-    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, STASH>), grid, dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, STASH>), grid, dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP, STASH>), grid, dim3(1024), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, STASH, RREG>), grid, dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, STASH, RREG>), grid, dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP, STASH, RREG>), grid, dim3(1024), lds, s, a); break;
   }
 }
 
-template <typename P, bool REP, bool STASH>
+template <typename P, bool REP, bool STASH, bool RREG = false>
 static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  if (a.gmrf) launch_sweep_q<P, kGmrf, REP, STASH>(a, threads, n_items, lds, s);
-  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP, STASH>(a, threads, n_items, lds, s);
-  else launch_sweep_q<P, kMprQ, REP, STASH>(a, threads, n_items, lds, s);
+  if (a.gmrf) launch_sweep_q<P, kGmrf, REP, STASH, RREG>(a, threads, n_items, lds, s);
+  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP, STASH, RREG>(a, threads, n_items, lds, s);
+  else launch_sweep_q<P, kMprQ, REP, STASH, RREG>(a, threads, n_items, lds, s);
 }
 
 // Passes of 3 or more sweeps keep random words between the sweeps of a pair
@@ -756,9 +819,25 @@ static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, 
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+  // FP32 passes recording two or more sweeps keep their fill sums in registers.
+  bool rreg = false;
+  if constexpr (sizeof(P) == 4) rreg = !a.rep && __builtin_popcount(a.record_mask) >= 2;
   if (a.rep) launch_sweep_m<P, true, true>(a, threads, n_items, lds, s);
-  else if (a.nsw >= 3) launch_sweep_m<P, false, true>(a, threads, n_items, lds, s);
-  else launch_sweep_m<P, false, false>(a, threads, n_items, lds, s);
+  else if (a.nsw >= 3) {
+    if constexpr (sizeof(P) == 4)
+      if (rreg) {
+        launch_sweep_m<P, false, true, true>(a, threads, n_items, lds, s);
+        return hipGetLastError();
+      }
+    launch_sweep_m<P, false, true>(a, threads, n_items, lds, s);
+  } else {
+    if constexpr (sizeof(P) == 4)
+      if (rreg) {
+        launch_sweep_m<P, false, false, true>(a, threads, n_items, lds, s);
+        return hipGetLastError();
+      }
+    launch_sweep_m<P, false, false>(a, threads, n_items, lds, s);
+  }
   return hipGetLastError();
 }
 
@@ -766,9 +845,9 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
-    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false, true>)); break;
-    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false, true>)); break;
-    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false, true>)); break;
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false, true, false>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false, true, false>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false, true, false>)); break;
     default: break;
   }
   return e == hipSuccess ? at.maxThreadsPerBlock : 0;

@@ -365,6 +365,28 @@ def test_fill_fp64_statistics_match_oracle():
     assert abs(mg - mo) <= 3 * math.hypot(sg, so) + 1e-12, (mg, mo, sg, so)
 
 
+@pytest.mark.parametrize("threads", ["256", "512", "1024"])
+def test_fill_sums_held_in_registers_equal_per_record_sums(threads, monkeypatch):
+    # FP32 passes that record two or more sweeps keep each thread's fill
+    # sums in registers (all of them for 512 and 1024 threads, half for 256
+    # with the rest in HBM); one-sweep passes update them in HBM per record.
+    # The sums agree bit for bit, including a fill whose first record falls
+    # inside a pass and strides that put 2 to 8 records in a pass.
+    monkeypatch.setenv("MPR_SWEEP_THREADS", threads)
+    grids = _grids(101, chains=2)
+    T = [0.02, 0.1, 0.005, 0.3, 0.05]
+    f8 = make_field(grids, dtype="fp32", seed=44, sweeps_per_pass=8)
+    f1 = make_field(grids, dtype="fp32", seed=44, sweeps_per_pass=1)
+    for n_eq, n_samp, stride in ((5, 24, 1), (8, 21, 3), (3, 16, 2)):
+        zh8, zs8, r8 = f8.fill(T, n_eq, n_samp, stride)
+        zh1, zs1, r1 = f1.fill(T, n_eq, n_samp, stride)
+        for a, b in zip(zh8 + zs8, zh1 + zs1):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), (n_eq, n_samp, stride)
+        assert r8["records"] == r1["records"] == n_samp // stride
+        f8.reinit()
+        f1.reinit()
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
 def test_grid_alone_equals_grid_in_batch(dtype):
     # A grid's chains depend only on that grid: alone, or first in a batch
