@@ -332,7 +332,9 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
 
 /*
  * Autotuner: choose the sweeps fused per pass (up to the context's
- * sweeps_per_pass) and the sweep workgroup size by timing trial passes of
+ * sweeps_per_pass) and the sweep workgroup size (256, 512 or 1024 threads;
+ * also 64 and 128 when no tile holds more than 1024 sites, i.e. for batches
+ * of small grids) by timing trial passes of
  * at least trial_sweeps sweeps on the context's own grids at the host
  * temperatures T[n_grids].  The angles, the sweep counter and every chain's
  * a are restored exactly afterwards, so the call has no effect on results;

@@ -660,7 +660,7 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
   c->threads = p->dtype == MPR_FP64 ? 256 : 1024;
   if (const char *env = std::getenv("MPR_SWEEP_THREADS")) {
     const int t = std::atoi(env);
-    if (t == 256 || t == 512 || t == 1024) c->threads = t;
+    if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) c->threads = t;
   }
   c->threads1 = c->threads;
   c->sites_all_chains = plan.state_elems;
@@ -1236,7 +1236,14 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
   double best = 1e300, best1 = 1e300;
   int best_nsw = ctx->nsw_run, best_thr = ctx->threads, best_thr1 = ctx->threads1;
   const int nsws[] = {1, 2, 3, 4, 6, 8, 12, 16};
-  for (int thr : {256, 512, 1024}) {
+  // Workgroups of 64 and 128 threads are tried only where every tile is
+  // small (grids below 32 x 32 sites): there many more of them share a CU.
+  int64_t max_tile_sites = 0;
+  for (const GridDesc &d : ctx->plan.gd)
+    max_tile_sites = std::max<int64_t>(max_tile_sites, (int64_t)std::min(d.nx, ctx->plan.tile_x) *
+                                                           std::min(d.ny, ctx->plan.tile_y));
+  for (int thr : {64, 128, 256, 512, 1024}) {
+    if (thr < 256 && max_tile_sites > 1024) continue;
     const bool ok = (ctx->p.dtype == MPR_FP64 ? sweep_max_threads<double>(thr) : sweep_max_threads<float>(thr)) >= thr;
     if (!ok) continue;
     for (int nsw : nsws) {

@@ -800,6 +800,8 @@ template <typename P, int MODEL, bool REP, bool STASH, bool RREG>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   const dim3 grid = block_grid(n_items, threads);
   switch (threads) {
+    case 64: hipLaunchKernelGGL((k_sweep<P, 64, MODEL, REP, STASH, RREG>), grid, dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sweep<P, 128, MODEL, REP, STASH, RREG>), grid, dim3(128), lds, s, a); break;
     case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, STASH, RREG>), grid, dim3(256), lds, s, a); break;
     case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, STASH, RREG>), grid, dim3(512), lds, s, a); break;
     default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP, STASH, RREG>), grid, dim3(1024), lds, s, a); break;
@@ -818,7 +820,8 @@ static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, 
 // leaner kernel.  The replicate boundary, a rarely used option, always does.
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+    return hipErrorInvalidValue;
   // FP32 passes recording two or more sweeps keep their fill sums in registers.
   bool rreg = false;
   if constexpr (sizeof(P) == 4) rreg = !a.rep && __builtin_popcount(a.record_mask) >= 2;
@@ -845,6 +848,8 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
+    case 64: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 64, kMprQ, false, true, false>)); break;
+    case 128: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 128, kMprQ, false, true, false>)); break;
     case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false, true, false>)); break;
     case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false, true, false>)); break;
     case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false, true, false>)); break;

@@ -141,6 +141,22 @@ def test_teacher_forced_sweep_fp32(tile, nsw):
     assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
 
 
+@pytest.mark.parametrize("threads", ["64", "128"])
+def test_teacher_forced_sweep_small_workgroups(threads, monkeypatch):
+    # one- and two-wave workgroups (offered by the autotuner for batches of
+    # small grids): every staging, plan and update loop runs in many strides
+    monkeypatch.setenv("MPR_SWEEP_THREADS", threads)
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp64", (32, 24), 2):
+        assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
+    total_gap = total_bad = 0
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp32", (16, 16), 1):
+        n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+        assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
+        total_bad += n_bad
+        total_gap += int((~known.astype(bool)).sum())
+    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
 def test_teacher_forced_sweep_without_over_relaxation(dtype):
     # Metropolis alone (MPR_NO_OR), the update the paper compares with the
@@ -365,11 +381,12 @@ def test_fill_fp64_statistics_match_oracle():
     assert abs(mg - mo) <= 3 * math.hypot(sg, so) + 1e-12, (mg, mo, sg, so)
 
 
-@pytest.mark.parametrize("threads", ["256", "512", "1024"])
+@pytest.mark.parametrize("threads", ["64", "128", "256", "512", "1024"])
 def test_fill_sums_held_in_registers_equal_per_record_sums(threads, monkeypatch):
     # FP32 passes that record two or more sweeps keep each thread's fill
-    # sums in registers (all of them for 512 and 1024 threads, half for 256
-    # with the rest in HBM); one-sweep passes update them in HBM per record.
+    # sums in registers (all of them for 512 and 1024 threads, 8 per thread
+    # for fewer, the rest in HBM); one-sweep passes update them in HBM per
+    # record.
     # The sums agree bit for bit, including a fill whose first record falls
     # inside a pass and strides that put 2 to 8 records in a pass.
     monkeypatch.setenv("MPR_SWEEP_THREADS", threads)
