@@ -276,6 +276,17 @@ class Field:
         self.device = dev
         self.n_grids = len(grids)
         self.total_chains = sum(s[2] for s in self.shapes)
+        # runs of consecutive grids of one shape: (offset, count, ny, nx),
+        # so that per-grid result views are cut run by run
+        self._runs, off = [], 0
+        for ny, nx, _ in self.shapes:
+            if self._runs and self._runs[-1][2:] == (ny, nx):
+                o, n, _, _ = self._runs[-1]
+                self._runs[-1] = (o, n + 1, ny, nx)
+            else:
+                self._runs.append((off, 1, ny, nx))
+            off += ny * nx
+        self._sites = off
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         n = ctypes.c_size_t(0)
         _check(lib().mpr_init_field(None, gs, len(grids), ctypes.byref(self.params), None, ctypes.byref(n), None))
@@ -354,23 +365,23 @@ class Field:
         """Returns (zhat list, zstd list or None, report dict)."""
         torch = self._torch
         T = self._T(T)
-        total = sum(ny * nx for ny, nx, _ in self.shapes)
-        zhat = torch.empty(total, dtype=torch.float64, device=self.device)
-        zstd = torch.empty(total, dtype=torch.float64, device=self.device) if want_std else None
+        zhat = torch.empty(self._sites, dtype=torch.float64, device=self.device)
+        zstd = torch.empty(self._sites, dtype=torch.float64, device=self.device) if want_std else None
         a_eq = np.empty(self.total_chains)
         acc_eq = np.empty(self.total_chains)
         acc_samp = np.empty(self.total_chains)
         rep = FillReport(0, 0, a_eq.ctypes.data, acc_eq.ctypes.data, acc_samp.ctypes.data)
         _check(lib().mpr_fill(self.ctx, _dptr(T), n_eq, n_samp, stride, ctypes.c_void_p(zhat.data_ptr()),
                               ctypes.c_void_p(zstd.data_ptr() if zstd is not None else 0), ctypes.byref(rep)), self.ctx)
-        out_h, out_s, off = [], [], 0
-        for ny, nx, _ in self.shapes:
-            out_h.append(zhat[off:off + ny * nx].view(ny, nx))
-            if zstd is not None:
-                out_s.append(zstd[off:off + ny * nx].view(ny, nx))
-            off += ny * nx
-        return out_h, (out_s if zstd is not None else None), dict(
+        return self._per_grid(zhat), (self._per_grid(zstd) if zstd is not None else None), dict(
             records=rep.records, a_eq=a_eq, acc_eq=acc_eq, acc_samp=acc_samp)
+
+    def _per_grid(self, flat):
+        """Views (ny, nx) of each grid's part of a flat site array."""
+        out = []
+        for off, n, ny, nx in self._runs:
+            out.extend(flat[off:off + n * ny * nx].view(n, ny, nx).unbind(0))
+        return out
 
     def set_grid_q(self, q):
         """mpr_set_grid_q: one modification factor per grid."""
