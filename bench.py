@@ -544,7 +544,7 @@ def main():
                     help="only run a plain 256 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures one GPU; chains and "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the benchmark measures one GPU; chains and "
               "grids would shard across GPUs with no exchange during sweeps.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
