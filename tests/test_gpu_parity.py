@@ -404,6 +404,37 @@ def test_fill_sums_held_in_registers_equal_per_record_sums(threads, monkeypatch)
         f1.reinit()
 
 
+def test_many_grids_find_their_items():
+    # 600 grids of sides 8-100 in 32 x 32 tiles (about 2000 sweep items, so
+    # the coarse item-to-grid index has several entries and most entries
+    # span several grids): one FP64 sweep of every chain, compared with the
+    # oracle on grids at the start, around index-entry boundaries and at
+    # the end of the batch
+    rng = np.random.default_rng(606)
+    grids = []
+    for g in range(600):
+        ny, nx = (int(v) for v in rng.integers(8, 101, 2))
+        z, known = random_grid(ny, nx, 0.5, 7000 + g, smooth=False)
+        grids.append((z, known, 1 + g % 2))
+    seed, T, a, sweep0 = 5, 0.2, 2.0, 4
+    f = make_field(grids, dtype="fp64", seed=seed, tile_x=32, tile_y=32, sweeps_per_pass=1)
+    f.set_chain_state(sweep0, np.full(f.total_chains, a))
+    f.sweep(1, [T] * len(grids))
+    items = np.cumsum([0] + [(-(-gr[0].shape[0] // 32)) * (-(-gr[0].shape[1] // 32)) * gr[2] for gr in grids])
+    assert items[-1] > 4 * 256
+    # grids whose items straddle a multiple of 256, and the ends
+    cross = [g for g in range(600) if items[g] // 256 != (items[g + 1] - 1) // 256][:6]
+    for g in sorted(set([0, 1, 598, 599] + cross)):
+        z, known, chains = grids[g]
+        kn = known.astype(bool)
+        phi = np.stack([oracle_init(z, known, seed, c, g, "fp64") for c in range(chains)])
+        ref, _ = om.hybrid_sweep(phi, kn, [beta_of(T)] * chains, [TWO_PI / a] * chains, 0.5, seed, sweep0,
+                                 np.arange(chains), g)
+        for c in range(chains):
+            assert np.abs(f.get_phi(g, c).cpu().numpy() - ref[c]).max() <= 1e-5, (g, c)
+    f.close()
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
 def test_grid_alone_equals_grid_in_batch(dtype):
     # A grid's chains depend only on that grid: alone, or first in a batch
