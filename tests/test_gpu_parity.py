@@ -418,13 +418,32 @@ def test_many_grids_find_their_items():
         grids.append((z, known, 1 + g % 2))
     seed, T, a, sweep0 = 5, 0.2, 2.0, 4
     f = make_field(grids, dtype="fp64", seed=seed, tile_x=32, tile_y=32, sweeps_per_pass=1)
-    f.set_chain_state(sweep0, np.full(f.total_chains, a))
-    f.sweep(1, [T] * len(grids))
     items = np.cumsum([0] + [(-(-gr[0].shape[0] // 32)) * (-(-gr[0].shape[1] // 32)) * gr[2] for gr in grids])
     assert items[-1] > 4 * 256
     # grids whose items straddle a multiple of 256, and the ends
     cross = [g for g in range(600) if items[g] // 256 != (items[g + 1] - 1) // 256][:6]
-    for g in sorted(set([0, 1, 598, 599] + cross)):
+    check = sorted(set([0, 1, 298, 598, 599] + cross))
+    chain0 = np.cumsum([0] + [gr[2] for gr in grids])
+    # the set-up and reduction kernels of the same batch: hot start, Eq. (4)
+    # per grid and Eq. (5) per chain
+    e_s, _ = f.specific_energy(0, allow_nopairs=True)
+    e_c, _ = f.specific_energy(1)
+    for g in check:
+        z, known, chains = grids[g]
+        kn = known.astype(bool)
+        for c in range(chains):
+            phi0 = oracle_init(z, known, seed, c, g, "fp64")
+            assert np.array_equal(f.get_phi(g, c).cpu().numpy(), phi0), (g, c)
+            assert abs(e_c[chain0[g] + c] - om.state_specific_energy(phi0[None], 0.5)[0][0]) <= 1e-12, (g, c)
+        try:
+            es, _, _ = om.sample_specific_energy(om.transform(z, kn)[0], kn, 0.5)
+        except om.OracleError:
+            assert np.isnan(e_s[g])
+        else:
+            assert abs(e_s[g] - es) <= 1e-12, g
+    f.set_chain_state(sweep0, np.full(f.total_chains, a))
+    f.sweep(1, [T] * len(grids))
+    for g in check:
         z, known, chains = grids[g]
         kn = known.astype(bool)
         phi = np.stack([oracle_init(z, known, seed, c, g, "fp64") for c in range(chains)])
