@@ -362,7 +362,7 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
  * would take the least time wins, a fill costed as n_eq sweeps at one sweep
  * per pass (the a-rule's pace when adapt_every == 1, else the tuned pace)
  * plus n_samp sweeps at the tuned pace.  Another tile replaces the library
- * default (the first candidate) only when its fill costs at least 3 % less:
+ * default (the first candidate) only when its fill costs at least 5 % less:
  * closer candidates differ by timing noise.
  * Tiling and fusion do not change results (every tile keeps the
  * checkerboard order of Sec. 5.2), so the choice affects speed only.  p's own tile is

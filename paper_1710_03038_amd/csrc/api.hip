@@ -1354,7 +1354,7 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
 static const int kTileCand32[][2] = {{64, 64}, {32, 32}, {64, 32}, {128, 32}, {128, 64}, {96, 96}};
 static const int kTileCand64[][2] = {{32, 32}, {16, 16}, {32, 16}, {64, 32}, {64, 64}};
 
-static constexpr double kTileMargin = 0.97;  // a tile must cost 3 % less than the default to replace it
+static constexpr double kTileMargin = 0.95;  // a tile must cost 5 % less than the default to replace it
 
 struct TileChoice {
   int tile_x, tile_y, nsw;
