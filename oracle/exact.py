@@ -52,6 +52,21 @@ def single_site_bins(nbr_angles, beta, q, nbins=8, per_bin=48):
     return _bin_probs(dens, w, nbins)
 
 
+def single_site_moments(nbr_angles, beta, q, n=256):
+    """Mean and variance of the angle of one free site whose neighbours are
+    frozen at ``nbr_angles``, under the density proportional to
+    prod_j exp(beta cos q(phi - phi_j)) on [0, 2*pi): Gauss-Legendre
+    quadrature with ``n`` nodes per eighth of the circle."""
+    x, w = _nodes(8, n)
+    dens = np.ones_like(x)
+    for a in nbr_angles:
+        dens = dens * _bond(beta, q, x, a)
+    m0 = float((dens * w).sum())
+    m1 = float((dens * w * x).sum()) / m0
+    m2 = float((dens * w * x * x).sum()) / m0
+    return m1, m2 - m1 * m1
+
+
 EDGE_CORNERS = {(0, 1): ((0, 0), (0, 2)), (1, 0): ((0, 0), (2, 0)),
                 (1, 2): ((0, 2), (2, 2)), (2, 1): ((2, 0), (2, 2))}
 
