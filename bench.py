@@ -13,18 +13,23 @@ shape (set-up, untimed, skipped with --no-autotune or an explicit --tile).
 
 Prints one JSON line.  value = spin-updates/s (hybrid updates of gap sites,
 whole job); realisations/s is reported beside it.  The default workload is
-a 1024 x 1024 Gaussian field (correlation length 16, mean 50, std 10) with
-50 % random gaps, 1 chain, 1000 hybrid sweeps (100 equilibration + 900
-sampling, every 9th recorded: 100 realisations), FP32.  The plain FP64 arm
-(one sweep per pass) and the FP64 CPU oracle are timed on the same input.
+the satellite-scale case: an 8192 x 8192 Gaussian field (squared-
+exponential, correlation length 64, mean 50, std 10) with >= 90 % gaps as
+random elliptical cloud masks and the truth held out, 64 conditional chains
+in one batch, 100 equilibration sweeps with the a-rule and the final state
+recorded (64 realisations), FP32.  The plain FP64 arm (one context per
+grid, FP64 library math, one sweep per pass, no graph, no autotuning) runs
+the same input, and its fill MAE is compared with the FP32 one; the FP64
+CPU oracle is timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 
-Workloads: grid64_fp64, grid1024 (default), grid512x512chains,
-grid8192x64chains, uneven2000.
+Workloads: grid64_fp64, grid1024, grid512x512chains,
+grid8192x64chains (default), uneven2000.
 """
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -72,7 +77,10 @@ def stash_fraction(n_eq, n_samp, nsw):
     return served / (n_eq + n_samp)
 KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
                   "paper_1710_03038_amd/csrc/internal.h")
-PROFILE = "profiles/k_sweep_fp32_grid1024.md"
+# rocprofv3 summaries whose FETCH_SIZE / WRITE_SIZE give the measured HBM
+# traffic of the sweep launches, per workload.
+PROFILES = {"grid8192x64chains": "profiles/k_sweep_fp32_grid8192x64chains.md",
+            "grid1024": "profiles/k_sweep_fp32_grid1024.md"}
 
 
 def bytes_per_site_sweep(elem, p):
@@ -81,22 +89,32 @@ def bytes_per_site_sweep(elem, p):
     return elem * (1.0 + p) + 0.125
 
 
-def profiled_traffic():
+def profiled_traffic(workload, shape, tile):
     """HBM bytes per sweep launch measured by rocprofv3 (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy) for the default configuration, or
-    None when the kernel sources changed since that profile was taken."""
+    WRITE_SIZE, scaled by a plain copy) for this workload, or None when
+    there is no profile for it, the kernel sources changed since it was
+    taken, or this run's launch shape or tile differs from the profiled
+    one."""
     import hashlib
     import re
+    if workload not in PROFILES:
+        return None
     try:
-        text = open(os.path.join(ROOT, PROFILE)).read()
+        text = open(os.path.join(ROOT, PROFILES[workload])).read()
         h = hashlib.sha256()
         for f in KERNEL_SOURCES:
             h.update(open(os.path.join(ROOT, f), "rb").read())
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+) kernel_sources_sha256: ([0-9a-f]+)", text)
+    m = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+) kernel_sources_sha256: ([0-9a-f]+)"
+                  r"(?: shape: (\d+) (\d+) (\d+) tile: (\d+) (\d+))?", text)
     if not m or m.group(2) != h.hexdigest():
         return None
+    if m.group(3) is not None:
+        prof_shape = tuple(int(m.group(i)) for i in (3, 4, 5))
+        prof_tile = (int(m.group(6)), int(m.group(7)))
+        if tuple(int(v or 0) for v in shape) != prof_shape or tuple(tile)[:2] not in (prof_tile, (0, 0)):
+            return None
     return float(m.group(1))
 
 
@@ -433,7 +451,7 @@ def load_workload(name):
                         "mask": spec["mask"], "chains": spec["chains"]})
 
 
-def one_step(M, f, W, table, tune, timing=False):
+def one_step(M, f, W, table, tune, timing=False, shape=None):
     """One pass of the whole path on a set-up context: hot start from the
     resident inputs (mpr_reinit), e_s, T-hat by SEM, launch shape (cached
     after the first tuning), fill."""
@@ -442,43 +460,84 @@ def one_step(M, f, W, table, tune, timing=False):
         f.set_timing(True)
     e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
     T, _ = M.match_T(e_s, table[0], table[1])
-    tuned = f.autotune(T, 16) if tune else (f.params.sweeps_per_pass, None, None)
+    tuned = f.autotune(T, 16) if tune else (shape or (f.params.sweeps_per_pass, None, None))
     zh, zs, rep = f.fill(T, W["n_eq"], W["n_samp"], W["stride"])
     kt = f.timing() if timing else (0.0, 0, 0)
-    return zh, rep, T, e_s, kt, tuned
+    return dict(zh=zh, zs=zs, rep=rep, T=T, e_s=e_s, kt=kt, tuned=tuned)
 
 
-def run_arm(M, dev_grids, W, table, params, steps, warmup, graph, tune=True):
-    """Host set-up (context, workspace) once, outside the timed region; the
+def run_arm(M, dev_grids, W, table, params, steps, warmup, graph, tune=True, shape=None):
+    """Batched arm: one context over every grid and chain of the workload.
+    Host set-up (context, workspace) once, outside the timed region; the
     timed steps run the whole path on the device."""
     import torch
     tune = tune and params.dtype == M.FP32
     f = M.Field(dev_grids, params)
     f.set_graph(graph)
+    if shape:
+        f.set_launch_shape(*shape)
+        tune = False
     for _ in range(warmup):
-        one_step(M, f, W, table, tune)
+        one_step(M, f, W, table, tune, shape=shape)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kms = kl = kss = 0
     out = None
     for _ in range(steps):
-        out = one_step(M, f, W, table, tune, timing=True)
-        kms += out[4][0]
-        kl += out[4][1]
-        kss += out[4][2]
+        out = one_step(M, f, W, table, tune, timing=True, shape=shape)
+        kms += out["kt"][0]
+        kl += out["kt"][1]
+        kss += out["kt"][2]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     f.close()
     return dt, out, (kms, kl, kss)
 
 
-def fill_mae(W, zh):
+def run_plain_arm(M, dev_grids, W, table, params, steps, warmup):
+    """Plain per-grid arm: each grid in a context of its own (its chains
+    together), run one after the other; the step time is the sum over the
+    grids.  No graph and no autotuning; the caller's params fix the
+    precision and sweeps per pass."""
+    import torch
+    dt = 0.0
+    outs = []
+    for g, grid in enumerate(dev_grids):
+        wg = dict(W, grids=[W["grids"][g]])
+        f = M.Field([grid], params)
+        for _ in range(warmup):
+            one_step(M, f, wg, table, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = None
+        for _ in range(steps):
+            out = one_step(M, f, wg, table, False)
+        torch.cuda.synchronize()
+        dt += (time.perf_counter() - t0) / steps
+        outs.append(out)
+        f.close()
+        del f
+    zh = [o["zh"][0] for o in outs]
+    zs = [o["zs"][0] for o in outs]
+    return dt, dict(zh=zh, zs=zs, rep=outs[0]["rep"], T=np.concatenate([o["T"] for o in outs]),
+                    e_s=np.concatenate([o["e_s"] for o in outs]))
+
+
+def fill_mae(W, zh, zs, chains):
+    """Gap-fill MAE against the held-out truth, and a bound on its Monte
+    Carlo standard error: the prediction at a gap site is a mean of R
+    recorded states, so its error has standard deviation z_std / sqrt(R)
+    for independent records, and the MAE moves by at most the mean of
+    those errors; their root-mean-square over the gaps is reported as
+    sigma (R = records per chain x chains)."""
     err = n = 0.0
-    for (z, known), h in zip(W["grids"], zh):
+    var = 0.0
+    for (z, known), h, s, r in zip(W["grids"], zh, zs, chains):
         gap = known == 0
         err += float(np.abs(h.cpu().numpy()[gap] - z[gap]).sum())
+        var += float((s.cpu().numpy()[gap] ** 2).sum()) / r
         n += int(gap.sum())
-    return err / n
+    return err / n, math.sqrt(var / n)
 
 
 def cpu_baseline(W, T, budget_s=10.0, max_side=1024, boundary="open"):
@@ -509,15 +568,49 @@ def cpu_baseline(W, T, budget_s=10.0, max_side=1024, boundary="open"):
     return done / spent, spent, used
 
 
+def oracle_scalars(W, table, max_grids=4):
+    """Eq. (4) and T-hat by the FP64 oracle (NumPy pair sums, scipy PCHIP
+    and Brent) on the first grids of the workload, for the error of the
+    GPU results against it."""
+    from oracle import mpr as om
+    e_o, T_o = [], []
+    for z, known in W["grids"][:max_grids]:
+        kn = known.astype(bool)
+        phi_s, _, _ = om.transform(z, kn)
+        e, _, _ = om.sample_specific_energy(phi_s, kn, 0.5)
+        e_o.append(e)
+        T_o.append(float(om.match_T([e], table[0], table[1])[0][0]))
+    return np.array(e_o), np.array(T_o)
+
+
+# The paper's own timing (Sec. 4.1.3, table of MPR validation measures):
+# Matlab on one desktop CPU, mean CPU time of one conditional simulation
+# (SEM, about 50 hybrid equilibration sweeps, M = 100 recorded sampling
+# sweeps) over S = 100 configurations of WM(0.2, 0.5) data.
+PAPER_TIMING = {
+    "hardware": "Intel Core i7-4790 3.60 GHz, 16 GB RAM, Matlab (Sec. 3)",
+    "workload": "L = 2048, case (b): 66 % random gaps, WM(kappa = 0.2, nu = 0.5), one chain",
+    "t_cpu_s_per_simulation": 149.11,
+    "spin_updates_per_s_derived": 150 * 2768240 / 149.11,
+    "derivation": "about 150 sweeps (50 equilibration + 100 sampling) x floor(0.66 * 2048^2) gap sites / t_cpu",
+    "note": "another machine and a smaller workload: context, not a target",
+}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid1024")
+    ap.add_argument("--workload", default="grid8192x64chains")
     ap.add_argument("--sweeps-per-pass", type=int, default=0)
     ap.add_argument("--tile", type=int, nargs=2, default=(0, 0))
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed steps of the plain FP64 arm (each several seconds on the default workload)")
+    ap.add_argument("--fp64-warmup", type=int, default=1)
+    ap.add_argument("--shape", type=int, nargs=3, default=None, metavar=("NSW", "THREADS", "THREADS1"),
+                    help="fix the launch shape (sweeps per pass, workgroup size, workgroup size of single-sweep "
+                         "passes) instead of autotuning it, e.g. for profiling runs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape (for profiling runs, whose timing would sway "
@@ -573,7 +666,9 @@ def main():
 
     M.lib()
     table = load_table()
+    t_in = time.perf_counter()
     W = load_workload(args.workload)
+    print("inputs drawn: %s in %.1f s" % (args.workload, time.perf_counter() - t_in), file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     dev_grids = [(torch.from_numpy(z).to(dev), torch.from_numpy(k).to(dev), c)
                  for (z, k), c in zip(W["grids"], W["chains"])]
@@ -603,45 +698,58 @@ def main():
         print("tile autotuned: %d x %d, up to %d sweeps per pass" % tile_tuned, file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     dt32, out32, (kms, kl, kss) = run_arm(M, dev_grids, W, table, prm32, args.steps, args.warmup, graph=True,
-                                          tune=not args.no_autotune)
-    mae32 = fill_mae(W, out32[0])
-    records = out32[1]["records"] * sum(W["chains"])
-    T_hat = out32[2]
+                                          tune=not args.no_autotune, shape=args.shape)
+    print("FP32 arm: %.1f ms per step" % (dt32 * 1e3), file=sys.stderr, flush=True)
+    records_per_chain = out32["rep"]["records"]
+    mae32, sig32 = fill_mae(W, out32["zh"], out32["zs"], [records_per_chain * c for c in W["chains"]])
+    records = records_per_chain * sum(W["chains"])
+    T_hat = out32["T"]
+    e_s32 = out32["e_s"]
+    tuned = out32["tuned"]
+    del out32
+    torch.cuda.empty_cache()
 
-    # plain FP64 arm: one sweep per pass, library default tiles, same input
+    # Plain FP64 arm: a context per grid, FP64 library math, one sweep per
+    # pass, the library's default tile, no graph and no autotuning.
     fp64 = None
+    e_s64 = T64 = None
     if args.fp64_steps > 0:
-        torch.cuda.empty_cache()
         prm64 = M.default_params(dtype="fp64", seed=W["seed"], sweeps_per_pass=1, boundary=args.boundary)
-        dt64, out64, _ = run_arm(M, dev_grids, W, table, prm64, args.fp64_steps, 0, graph=False)
-        mae64 = fill_mae(W, out64[0])
+        dt64, out64 = run_plain_arm(M, dev_grids, W, table, prm64, args.fp64_steps, args.fp64_warmup)
+        print("FP64 plain arm: %.1f ms per step" % (dt64 * 1e3), file=sys.stderr, flush=True)
+        mae64, sig64 = fill_mae(W, out64["zh"], out64["zs"], [out64["rep"]["records"] * c for c in W["chains"]])
+        sigma = math.sqrt(sig32 ** 2 + sig64 ** 2)
+        e_s64, T64 = out64["e_s"], out64["T"]
         fp64 = {"spin_updates_per_s": updates / dt64, "realisations_per_s": records / dt64,
-                "ms_per_step": dt64 * 1e3, "mae": mae64, "speedup_fp32_over_fp64": dt64 / dt32}
+                "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps, "warmup": args.fp64_warmup,
+                "arm": "one context per grid, FP64, one sweep per pass, default tile, no graph, no autotuning",
+                "mae": mae64, "mae_sigma": sig64,
+                "mae_diff_over_sigma": abs(mae32 - mae64) / sigma if sigma > 0 else None,
+                "equal_mae_3sigma": abs(mae32 - mae64) <= 3 * sigma,
+                "speedup_fp32_over_fp64": dt64 / dt32}
         del out64
         torch.cuda.empty_cache()
 
     b_site = bytes_per_site_sweep(4, p)
     ksec = kms * 1e-3
-    hbm_gbs = kss * b_site / ksec / 1e9 if kms > 0 else None
     useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
-    nsw_run = out32[5][0] or (prm32.sweeps_per_pass or 8)
+    nsw_run = tuned[0] or (prm32.sweeps_per_pass or 8)
     inst = VALU_INST_PER_UPDATE - VALU_INST_PHILOX * stash_fraction(W["n_eq"], W["n_samp"], nsw_run)
     achieved = useful_updates * inst / ksec / 1e12 if kms > 0 else None
-    # The profiled traffic holds for the default workload in the profiled
-    # multi-sweep shape; the bytes a pass moves do not depend on the
-    # workgroup size the single-sweep passes run with.
-    default_config = (args.workload == "grid1024" and args.sweeps_per_pass == 0 and tuple(args.tile) == (0, 0)
-                      and tile_tuned in (None, (64, 64, 8)) and args.boundary == "open"
-                      and "MPR_SWEEP_THREADS" not in os.environ and tuple(out32[5])[:2] in ((8, 1024), (0, None)))
+    avg_us = kms * 1e3 / kl if kl else None
+    alg_bytes = kss / kl * b_site if kl else None  # algorithmic one-pass bytes per launch
+    hbm_gbs = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
+    traffic = profiled_traffic(args.workload, tuple(tuned)[:3], tile_tuned or tuple(args.tile)) \
+        if args.boundary == "open" and "MPR_SWEEP_THREADS" not in os.environ else None
     cfg = dict(W["config"])
-    cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"], "n_samp": W["n_samp"],
-                "stride": W["stride"], "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
+    cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"],
+                "n_samp": W["n_samp"], "stride": W["stride"], "tile": [prm32.tile_x or 64, prm32.tile_y or 64],
                 "tile_autotuned": tile_tuned is not None,
                 "sweeps_per_pass_max": prm32.sweeps_per_pass or 8,
-                "autotuned_shape": {"sweeps_per_pass": out32[5][0], "threads": out32[5][1],
-                                    "threads_single_sweep_passes": out32[5][2]}, "fill_graph": True,
+                "autotuned_shape": {"sweeps_per_pass": tuned[0], "threads": tuned[1],
+                                    "threads_single_sweep_passes": tuned[2]}, "fill_graph": True,
                 "T_hat": float(T_hat[0]) if len(T_hat) == 1 else [float(T_hat.min()), float(T_hat.max())],
-                "e_s": float(out32[3][0]) if len(T_hat) == 1 else None})
+                "e_s": float(e_s32[0]) if len(T_hat) == 1 else None})
     res = {
         "metric": METRIC,
         "value": updates / dt32,
@@ -657,18 +765,23 @@ def main():
         "data": "synthetic (seeded Gaussian/lognormal random fields and gap masks; no dataset)",
         "config": cfg,
         "realisations_per_s": records / dt32,
+        "fills_per_s": len(W["grids"]) / dt32,
         "mae_fp32": mae32,
+        "mae_fp32_sigma": sig32,
         "fp64_plain": fp64,
-        "roofline": {"bound": "alu", "kernel": "k_sweep<float>",
-                     "achieved": achieved, "peak": VALU_PEAK_TINST, "unit": "T VALU issue slots/s (lane-instructions, transcendentals x4)",
+        "roofline": {"bound": "alu", "kernel": "k_sweep<float> (every sweep launch of the fill)",
+                     "achieved": achieved, "peak": VALU_PEAK_TINST,
+                     "unit": "T VALU issue slots/s (lane-instructions, transcendentals x4)",
                      "frac": (achieved / VALU_PEAK_TINST) if achieved else None,
-                     "traffic": profiled_traffic() if default_config else None,
-                     "inst_per_update": inst,
-                     "avg_launch_us": kms * 1e3 / kl if kl else None, "launches": kl,
-                     "site_sweeps_per_launch": kss / kl if kl else None,
-                     "hbm_one_pass": {"achieved_GBps": hbm_gbs, "peak_GBps": HBM_PEAK_GBS,
-                                      "frac": hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
-                                      "bytes_per_site_sweep": b_site}},
+                     "traffic": traffic,
+                     "alu_frac": (achieved / VALU_PEAK_TINST) if achieved else None,
+                     "hbm_achieved_GBps": hbm_gbs, "hbm_peak_GBps": HBM_PEAK_GBS,
+                     "hbm_frac": hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
+                     "hbm_measured_GBps": traffic / (avg_us * 1e-6) / 1e9 if traffic and avg_us else None,
+                     "hbm_algorithmic_bytes_per_launch": alg_bytes, "bytes_per_site_sweep": b_site,
+                     "inst_per_update": inst, "avg_launch_us": avg_us, "launches": kl,
+                     "site_sweeps_per_launch": kss / kl if kl else None},
+        "paper_timing": PAPER_TIMING,
     }
     if not args.no_cpu:
         os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -677,6 +790,16 @@ def main():
         res["cpu_baseline"] = {"value": v, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
                                "sample": f"{desc} (1 chain each, from the hot start, a-rule on), FP64 NumPy oracle, "
                                          f"one thread, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+        # Error of the GPU's Eq. (4) and T-hat against the FP64 oracle (the
+        # oracle's pair sums and scipy root-find on the same table).
+        e_o, T_o = oracle_scalars(W, table)
+        k = len(e_o)
+        errs = {"grids": k, "e_s_rel_err_fp32": float(np.max(np.abs(e_s32[:k] / e_o - 1))),
+                "T_hat_rel_err_fp32": float(np.max(np.abs(T_hat[:k] / T_o - 1)))}
+        if e_s64 is not None:
+            errs["e_s_rel_err_fp64"] = float(np.max(np.abs(e_s64[:k] / e_o - 1)))
+            errs["T_hat_rel_err_fp64"] = float(np.max(np.abs(T64[:k] / T_o - 1)))
+        res["vs_fp64_oracle"] = errs
     print(json.dumps(res), flush=True)
 
 

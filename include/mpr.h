@@ -351,6 +351,17 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
                         int32_t *threads1_out);
 
 /*
+ * Set the launch shape by hand, as mpr_autotune would: sweeps fused per
+ * multi-sweep pass (1 .. the context's sweeps_per_pass), the workgroup size
+ * of those passes and of single-sweep passes (64, 128, 256, 512 or 1024).
+ * For callers that know their shape (repeated runs, profiling, where timing
+ * the candidates would sway the choice).  The shape does not change
+ * results.  MPR_E_ARG if a value is out of range or the pass's LDS exceeds
+ * the device's; the context is then unchanged.  No device work.
+ */
+mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1);
+
+/*
  * Tile autotuner: choose the tile shape (mpr_params.tile_x, tile_y) and the
  * most sweeps per pass (sweeps_per_pass) for mpr_init_field of these grids
  * and params, before any context exists.  Each candidate tile (FP32: 64x64,

@@ -33,6 +33,7 @@ struct Views {
   double *a = nullptr, *beta = nullptr, *window = nullptr, *accsum = nullptr;
   uint32_t *counts = nullptr;
   double *energy = nullptr;
+  double *energy_part = nullptr;  // per-item energies of a traced pass [kMaxPass][n_items]
   double *part = nullptr, *out = nullptr;
   double *rep = nullptr;  // fill report scratch: a and acceptance after equilibration [2][C]
   uint16_t *plan = nullptr;
@@ -243,6 +244,7 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.accsum = (double *)take(8 * C);
   v.counts = (uint32_t *)take(4 * 3 * C * kMaxPass);  // by pass number mod 3
   v.energy = (double *)take(8 * 3 * C * kMaxPass);
+  v.energy_part = (double *)take(8 * (size_t)pl.n_items * kMaxPass);
   v.part = (double *)take(8 * (size_t)std::max<int64_t>(pl.n_sblocks * kMeasureSums, pl.n_cblocks * 2));
   v.out = (double *)take(8 * std::max<size_t>({(size_t)n * 4, C * 2, (size_t)8}));
   v.rep = (double *)take(8 * 2 * C);
@@ -270,6 +272,7 @@ void bind(Views &v, const Views &o, void *ws) {
   v.accsum = rebase(o.accsum, b);
   v.counts = rebase(o.counts, b);
   v.energy = rebase(o.energy, b);
+  v.energy_part = rebase(o.energy_part, b);
   v.part = rebase(o.part, b);
   v.out = rebase(o.out, b);
   v.rep = rebase(o.rep, b);
@@ -372,8 +375,8 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.accsum = c->v.accsum;
   A.counts = counts_buf(c, pn);
   A.energy = trace_e ? energy_buf(c, pn) : nullptr;
+  A.energy_part = trace_e ? c->v.energy_part : nullptr;
   A.counts_clear = counts_buf(c, pn + 1);
-  A.energy_clear = energy_buf(c, pn + 1);
   A.acc_ref = (P *)c->v.acc_ref;
   A.acc_s1 = (P *)c->v.acc_s1;
   A.acc_s2 = (P *)c->v.acc_s2;
@@ -383,6 +386,9 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.n_items = c->plan.n_items;
   A.item_grid = c->v.item_grid;
   HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
+  if (trace_e)
+    HIP_TRY(c, launch_energy_reduce(c->v.gd, c->n_grids, c->plan.total_chains, c->plan.n_items, nsw,
+                                    c->v.energy_part, A.energy, c->stream));
   if (c->capturing) {
     c->g_launches += 1;
     c->g_site_sweeps += (int64_t)nsw * c->sites_all_chains;
@@ -1345,6 +1351,26 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   if (nsw_out) *nsw_out = ch.nsw;
   if (threads_out) *threads_out = ch.threads;
   if (threads1_out) *threads1_out = ch.threads1;
+  return MPR_OK;
+}
+
+mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1) {
+  if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
+  if (nsw < 1 || nsw > ctx->nsw_max)
+    return fail(ctx, MPR_E_ARG, "nsw must be in 1.." + std::to_string(ctx->nsw_max));
+  for (int t : {threads, threads1}) {
+    if (t != 64 && t != 128 && t != 256 && t != 512 && t != 1024)
+      return fail(ctx, MPR_E_ARG, "workgroup sizes must be 64, 128, 256, 512 or 1024");
+    const int mx = ctx->p.dtype == MPR_FP64 ? sweep_max_threads<double>(t) : sweep_max_threads<float>(t);
+    if (mx < t) return fail(ctx, MPR_E_ARG, "the sweep kernel cannot run " + std::to_string(t) + " threads");
+  }
+  int w, h;
+  size_t lds;
+  lds_extent(ctx, nsw, w, h, lds);
+  if (lds > ctx->lds_limit) return fail(ctx, MPR_E_ARG, "the pass needs more LDS than the device has");
+  ctx->nsw_run = nsw;
+  ctx->threads = threads;
+  ctx->threads1 = threads1;
   return MPR_OK;
 }
 

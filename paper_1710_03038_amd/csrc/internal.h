@@ -75,9 +75,9 @@ struct SweepArgs {
   double *a_now, *win_now;         // a and window this pass runs with (written by tile 0 if pe.valid)
   double *accsum;                  // per chain, sum of acceptance ratios (written by tile 0)
   uint32_t *counts;                // this pass: [chains][kMaxPass] accepted updates
-  double *energy;                  // this pass: [chains][kMaxPass] or nullptr
+  double *energy;                  // this pass: [chains][kMaxPass] or nullptr (written by k_energy_reduce)
+  double *energy_part;             // this pass: [kMaxPass][n_items] energy of each item's interior pairs
   uint32_t *counts_clear;          // buffer of the pass after next, cleared by tile 0
-  double *energy_clear;
   P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
   // Gap-site plan (k_plan): per tile, the gap sites within ring distance
   // plan_dmax of the interior, colour 0 then colour 1, each sorted by ring
@@ -107,6 +107,10 @@ template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds_bytes, hipStream_t s);
 template <typename P>
 hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s);
+// Per chain and sweep of a pass with the energy traced: the sum of the
+// chain's per-item partials in a fixed order -> energy[chain][s].
+hipError_t launch_energy_reduce(const GridDesc *g, int n_grids, int total_chains, int64_t n_items, int nsw,
+                                const double *part, double *energy, hipStream_t s);
 // Largest workgroup the sweep kernel instance for `threads` can run with
 // (0 if it cannot be queried).
 template <typename P>

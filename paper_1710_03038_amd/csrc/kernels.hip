@@ -41,13 +41,9 @@ __device__ __forceinline__ int64_t block_index() { return (int64_t)blockIdx.y * 
 // The 32x32 -> 64-bit products use one v_mad_u64_u32 each (both halves at
 // once); the compiler would otherwise split them into mul_lo + mul_hi.
 __device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b) {
-#ifdef MPR_PHILOX_SPLIT_MUL
-  return ((uint64_t)__umulhi(a, b) << 32) | (uint64_t)(a * b);
-#else
   uint64_t r, carry;
   asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "v"(b));
   return r;
-#endif
 }
 
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
@@ -228,6 +224,9 @@ template <typename P> struct UpdateCtx {
   // LDS column of grid x = 0 and x = nx - 1, row of y = 0 and y = ny - 1
   // (outside the LDS range when the tile is away from that edge).
   int ex0, ex1, ey0, ey1;
+  // Store the updated sites' (cos, sin): false in the pass's last
+  // half-sweep, after which nothing reads them.
+  bool store_cs;
 };
 
 // Replicate auxiliary nodes (Sec. 2.5): the number of a site's neighbours
@@ -359,8 +358,9 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
     P p1 = phi[k];
     if (live && U.or_step) {
       const P star = (P(2) * psi - q * phi[k]) * U.inv_q;
+      // (+ 0 turns a reflection to -0 into +0: a set sign bit marks a sample site)
       if (QONE) p1 = wrap_any(star);
-      else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+      else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star + P(0);
     }
     // Steps 2-3: restricted Metropolis proposal.
     const P p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
@@ -372,11 +372,13 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
     // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
     const bool ok = (dH <= P(0)) || (rr[k] < Prec<P>::exp_(-U.beta * dH));
     const P nv = ok ? p2 : p1;
-    P s_, c_;
-    if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
-    else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
     U.pc[o[k]] = nv;
-    U.cc[o[k]] = V2{c_, s_};
+    if (U.store_cs) {
+      P s_, c_;
+      if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
+      else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
+      U.cc[o[k]] = V2{c_, s_};
+    }
     acc += (ok && cnt[k]) ? 1u : 0u;
   }
   return acc;
@@ -401,6 +403,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_d[NT / 64];
   __shared__ uint32_t acc_lds[kMaxPass];
+  __shared__ double a_lds;
 
   const int64_t item = block_index();
   if (item >= A.n_items) return;  // the ragged last row of a two-row launch
@@ -434,21 +437,38 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   // distance 2*nsw, then colour-1 entries within distance 2*nsw - 1.  Each
   // thread issues the loads of up to kStage sites and kPlanStage plan
   // entries before it waits for any, so the staging costs one memory
-  // latency per batch (one batch for the library's default shapes).  Sites
-  // outside the grid and lanes past the end read element 0 and discard it.
+  // latency per batch (one batch for the library's default shapes).
   if (threadIdx.x < kMaxPass) acc_lds[threadIdx.x] = 0u;
+  const int gchain = G.chain_base + chain;
+  // Close the previous pass (every tile derives the same a; tile 0 records):
+  // one thread, while the staging loads are in flight.
+  if (threadIdx.x == 0) a_lds = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0) : A.a_now[gchain];
+  if (t == 0 && threadIdx.x < kMaxPass) A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
   uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);  // past both planes
   const int64_t pitem = G.plan_begin + t;
   const uint32_t *cum = A.plan_cum + pitem * 2 * (A.plan_dmax + 2);
   const int cstride = A.plan_dmax + 2;
   const uint32_t n0_all = cum[A.plan_dmax + 1];
   const uint32_t na = cum[2 * A.nsw + 1], nb = cum[cstride + 2 * A.nsw];
+  // LDS site (ly, lx) is grid site (oy + ly, ox + lx); its colour is
+  // (lx + ly + par0) & 1.
+  const int par0 = (ox + oy) & 1;
   {
     constexpr int kStage = 16, kPlanStage = 8;
     const int n_lds = W * A.lds_h;
     const float invw = 1.0f / (float)W;
     const uint16_t *pl = A.plan + G.plan_ebase + (int64_t)t * G.plan_cap;
     const uint32_t n_all = na + nb;
+    // Thread i stages LDS sites i, i + NT, ... in row-major order: its
+    // (ly, lx) moves by (NT / W, NT % W) per site, with a carry.  The
+    // in-grid part of the LDS rectangle is [ax, ax + aw) x [ay, ay + ah);
+    // the chain's angle of LDS site (ly, lx) is src[ib + ly * nx + lx],
+    // an index below 2^32 for every in-grid site.
+    const int dly = NT / W, dlx = NT - (NT / W) * W;
+    int sly, slx;
+    split_index((int)threadIdx.x, W, invw, sly, slx);
+    const int ax = lxs - ox, aw = lxe - lxs, ay = lys - oy, ah = lye - lys;
+    const uint32_t ib = (uint32_t)((int64_t)oy * nx + ox);
     for (int base = 0, pb = 0; base < n_lds || pb < (int)n_all; base += NT * kStage, pb += NT * kPlanStage) {
       // Slots wholly past the end (a workgroup-uniform test) issue nothing.
       uint16_t e[kPlanStage] = {};
@@ -458,24 +478,29 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         const uint32_t f = (uint32_t)(pb + k * NT) + threadIdx.x;
         e[k] = pl[f < na ? f : (f < n_all ? n0_all + (f - na) : 0u)];
       }
-      P v[kStage] = {};
+      P v[kStage];
       int o[kStage];
       bool in[kStage];
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
-        o[k] = -1;
+        o[k] = -1;  // every slot, also those past the loop's break below
         in[k] = false;
+        v[k] = P(0);
       }
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
         if (base + k * NT >= n_lds) break;
-        const int idx = base + k * NT + (int)threadIdx.x;
-        int ly, lx;
-        split_index(idx, W, invw, ly, lx);
-        const int gx = ox + lx, gy = oy + ly;
-        o[k] = idx < n_lds ? ((gx + gy) & 1) * plane + ly * P2 + (lx >> 1) : -1;
-        in[k] = idx < n_lds && gx >= lxs && gx < lxe && gy >= lys && gy < lye;
-        v[k] = src[in[k] ? (int64_t)gy * nx + gx : 0];
+        if (sly < A.lds_h) {
+          o[k] = ((slx + sly + par0) & 1) * plane + sly * P2 + (slx >> 1);
+          in[k] = (uint32_t)(slx - ax) < (uint32_t)aw && (uint32_t)(sly - ay) < (uint32_t)ah;
+          if (in[k]) v[k] = src[ib + (uint32_t)(sly * nx + slx)];
+        }
+        slx += dlx;
+        sly += dly;
+        if (slx >= W) {
+          slx -= W;
+          ++sly;
+        }
       }
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
@@ -484,14 +509,21 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
           // angles only; NaN marks a site outside the grid or the halo
           ph[o[k]] = in[k] ? v[k] : P(__builtin_nan(""));
         } else {
-          P s_ = P(0), c_ = P(0), val = -P(0);
-          if (in[k]) {
-            val = v[k];
-            if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
-            else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+          // (cos, sin) of colour-0 gap sites is never read before the
+          // pass's first half-sweep recomputes it (every colour-0 gap site
+          // a colour-1 update reads lies in that half-sweep's reach), except
+          // for a site's own value at the replicate boundary.
+          const P val = in[k] ? v[k] : -P(0);
+          const bool need = !in[k] || REP || o[k] >= plane || signbit(val);
+          if (need) {
+            P s_ = P(0), c_ = P(0);
+            if (in[k]) {
+              if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
+              else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+            }
+            cs[o[k]] = V2{c_, s_};
           }
           ph[o[k]] = val;
-          cs[o[k]] = V2{c_, s_};
         }
       }
 #pragma unroll
@@ -502,14 +534,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
     }
   }
   __syncthreads();
-
-  const int gchain = G.chain_base + chain;
-  // Close the previous pass (every tile derives the same a; tile 0 records).
-  const double a_d = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0 && threadIdx.x == 0) : A.a_now[gchain];
-  if (t == 0 && threadIdx.x < kMaxPass) {
-    A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
-    A.energy_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0.0;
-  }
+  const double a_d = a_lds;
   const P beta = (P)A.beta[gchain], alpha = (P)(6.28318530717958647692 / a_d);
   const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
   const int iw = ix1 - x0, ih = iy1 - y0;
@@ -572,7 +597,8 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
                            Ly,    Lx,  P2,  sbase, nx,
                            sweep, cid, gid, k0,    k1,
                            q,     inv_q, alpha, beta, A.or_step != 0,
-                           -ox,   nx - 1 - ox, -oy, ny - 1 - oy};
+                           -ox,   nx - 1 - ox, -oy, ny - 1 - oy,
+                           !(c == 1 && s == A.nsw - 1)};
       // In FP32, two independent updates per thread and iteration (items f
       // and f + NT) give the scheduler two dependency chains to interleave;
       // a lane without a second item repeats its first, with the first's
@@ -635,8 +661,10 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         if (gx + 1 < nx) e += pair(v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]));
         if (gy + 1 < ny) e += pair(v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]));
       }
+      // One partial per item; k_energy_reduce sums a chain's partials in a
+      // fixed order, so the trace does not depend on workgroup timing.
       const double et = block_sum<NT>((double)e, red_d);
-      if (threadIdx.x == 0) atomicAdd(&A.energy[(int64_t)gchain * kMaxPass + s], et);
+      if (threadIdx.x == 0) A.energy_part[(int64_t)s * A.n_items + item] = et;
     }
     if (rec) {
       // Algorithm 2, step 5.3: one realisation; shifted sums about the first.
@@ -696,13 +724,26 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
     }
   }
 
-  P *dst = A.dst + cbase;
-  for (int f = threadIdx.x; f < iw * ih; f += NT) {
+  // Write the interior's gap sites to the other buffer (sample sites hold
+  // the same value in both buffers from set-up on).  Thread i writes
+  // interior sites i, i + NT, ... in row-major order, its (row, column)
+  // moved by (NT / iw, NT % iw) per site.
+  {
+    P *dst = A.dst + cbase;
+    const int dr = NT / iw, dc = NT - (NT / iw) * iw;
     int r, cx;
-    split_index(f, iw, inv_iw, r, cx);
-    const int gx = x0 + cx, gy = y0 + r;
-    const int lx = gx - ox, ly = gy - oy;
-    dst[(int64_t)gy * nx + gx] = ph[((gx + gy) & 1) * plane + ly * P2 + (lx >> 1)];
+    split_index((int)threadIdx.x, iw, inv_iw, r, cx);
+    for (int f = threadIdx.x; f < iw * ih; f += NT) {
+      const int lx = x0 - ox + cx, ly = y0 - oy + r;
+      const P v = ph[((lx + ly + par0) & 1) * plane + ly * P2 + (lx >> 1)];
+      if (!signbit(v)) dst[(uint32_t)(y0 + r) * (uint32_t)nx + (uint32_t)(x0 + cx)] = v;
+      cx += dc;
+      r += dr;
+      if (cx >= iw) {
+        cx -= iw;
+        ++r;
+      }
+    }
   }
 
 }
@@ -710,14 +751,18 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 // ------------------------------------------------------------------- plan
 // One workgroup per (grid, tile): list the tile's gap sites within
 // Manhattan distance dmax of its interior, colour 0 first, each colour
-// sorted by distance (a counting sort).  The order inside one ring follows the LDS atomics and
-// may vary between runs; the sweep's results do not depend on it.
+// sorted by distance and, within one distance, in row-major order (a
+// counting sort that keeps the scan order), so that neighbouring lanes of
+// the sweep update neighbouring sites.  The plan is the same on every run.
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
     k_plan(const GridDesc *grids, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y, int dmax,
            uint16_t *plan, uint32_t *plan_cum) {
-  __shared__ uint32_t cnt[2][2 * kMaxPass + 2];
-  __shared__ uint32_t cur[2][2 * kMaxPass + 2];
+  constexpr int kBuckets = 2 * (2 * kMaxPass + 2);  // (colour, ring) pairs, ring <= 2 * kMaxPass + 1
+  constexpr int kWaves = kThreads / 64;
+  __shared__ uint32_t cnt[kBuckets];
+  __shared__ uint32_t cur[kBuckets];
+  __shared__ uint32_t wcnt[kWaves][kBuckets];
   const int64_t item = block_index();
   if (item >= n_tiles) return;
   const int gi = find_by(grids, n_grids, item, &GridDesc::plan_begin);
@@ -730,17 +775,29 @@ __global__ void __launch_bounds__(kThreads)
   const int ry0 = max(y0 - dmax, 0), ry1 = min(iy1 + dmax, ny);
   const int rw = rx1 - rx0, n = rw * (ry1 - ry0);
   const float inv = 1.0f / (float)rw;
+  const int nb = 2 * (dmax + 2);
   const P *st = state + G.state_off;  // chain 0: the sample sites are those of every chain
-  for (int i = threadIdx.x; i < 2 * (2 * kMaxPass + 2); i += kThreads) (&cnt[0][0])[i] = 0u;
-  __syncthreads();
-  for (int f = threadIdx.x; f < n; f += kThreads) {
+  // Bucket of scanned site f: colour * (dmax + 2) + ring, or -1 (a sample
+  // site or a corner of the scanned square beyond distance dmax).
+  auto bucket = [&](int f, uint16_t &entry) {
     int r, cx;
     split_index(f, rw, inv, r, cx);
     const int gx = rx0 + cx, gy = ry0 + r;
-    if (signbit(st[(int64_t)gy * nx + gx])) continue;
+    if (signbit(st[(int64_t)gy * nx + gx])) return -1;
     const int ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
-    if (ring > dmax) continue;  // the corners of the scanned square
-    atomicAdd(&cnt[(gx + gy) & 1][ring], 1u);
+    if (ring > dmax) return -1;
+    entry = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (gx - x0 + kPlanOffset));
+    return ((gx + gy) & 1) * (dmax + 2) + ring;
+  };
+  for (int i = threadIdx.x; i < kBuckets; i += kThreads) {
+    cnt[i] = 0u;
+    for (int w = 0; w < kWaves; ++w) wcnt[w][i] = 0u;
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < n; f += kThreads) {
+    uint16_t e;
+    const int b = bucket(f, e);
+    if (b >= 0) atomicAdd(&cnt[b], 1u);
   }
   __syncthreads();
   uint32_t *cum = plan_cum + item * 2 * (dmax + 2);
@@ -750,23 +807,49 @@ __global__ void __launch_bounds__(kThreads)
       uint32_t acc = 0;
       for (int r = 0; r <= dmax + 1; ++r) {
         cum[c * (dmax + 2) + r] = acc;
-        cur[c][r] = base + acc;
-        if (r <= dmax) acc += cnt[c][r];
+        cur[c * (dmax + 2) + r] = base + acc;
+        if (r <= dmax) acc += cnt[c * (dmax + 2) + r];
       }
       base += acc;
     }
   }
   __syncthreads();
+  // Placement in scan order: per chunk of kThreads sites, a site's slot is
+  // its bucket's running start, plus the bucket's sites in earlier waves of
+  // the chunk, plus those in earlier lanes of its own wave (by ballot).
   uint16_t *out = plan + G.plan_ebase + (int64_t)t * G.plan_cap;
-  for (int f = threadIdx.x; f < n; f += kThreads) {
-    int r, cx;
-    split_index(f, rw, inv, r, cx);
-    const int gx = rx0 + cx, gy = ry0 + r;
-    if (signbit(st[(int64_t)gy * nx + gx])) continue;
-    const int ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
-    if (ring > dmax) continue;
-    const uint32_t pos = atomicAdd(&cur[(gx + gy) & 1][ring], 1u);
-    out[pos] = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (gx - x0 + kPlanOffset));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int base = 0; base < n; base += kThreads) {
+    const int f = base + (int)threadIdx.x;
+    uint16_t e = 0;
+    const int b = f < n ? bucket(f, e) : -1;
+    int rank = 0;
+    uint64_t todo = __ballot(b >= 0);
+    while (todo) {
+      const int lead = __ffsll((unsigned long long)todo) - 1;
+      const int bl = __shfl(b, lead, 64);
+      const uint64_t m = __ballot(b == bl);
+      if (b == bl) rank = __popcll(m & below);
+      if (lane == 0) wcnt[wv][bl] = (uint32_t)__popcll(m);
+      todo &= ~m;
+    }
+    __syncthreads();
+    if (b >= 0) {
+      uint32_t pos = cur[b] + (uint32_t)rank;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w][b];
+      out[pos] = e;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kThreads) {
+      uint32_t add = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        add += wcnt[w][i];
+        wcnt[w][i] = 0u;
+      }
+      cur[i] += add;
+    }
+    __syncthreads();
   }
 }
 
@@ -794,6 +877,39 @@ __global__ void k_pass_end(const SweepArgs<P> A) {
     else hi = mid - 1;
   }
   apply_pass_end(A, A.grids[lo], ch, true);
+}
+
+// One workgroup per chain: for each sweep s of the pass, the energies of
+// the chain's items (tiles) summed by thread-strided partial sums and a
+// fixed-order workgroup sum.
+__global__ void __launch_bounds__(kThreads)
+    k_energy_reduce(const GridDesc *grids, int n_grids, int total_chains, int64_t n_items, int nsw,
+                    const double *part, double *energy) {
+  __shared__ double red[kThreads / 64];
+  const int64_t ch = block_index();
+  if (ch >= total_chains) return;
+  int lo = 0, hi = n_grids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (grids[mid].chain_base <= ch) lo = mid;
+    else hi = mid - 1;
+  }
+  const GridDesc &G = grids[lo];
+  const int tiles = G.tiles_x * G.tiles_y;
+  const int64_t i0 = G.item_begin + (ch - G.chain_base) * (int64_t)tiles;
+  for (int s = 0; s < nsw; ++s) {
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < tiles; t += kThreads) acc += part[(int64_t)s * n_items + i0 + t];
+    const double tot = block_sum<kThreads>(acc, red);
+    if (threadIdx.x == 0) energy[ch * kMaxPass + s] = tot;
+  }
+}
+
+hipError_t launch_energy_reduce(const GridDesc *g, int n_grids, int total_chains, int64_t n_items, int nsw,
+                                const double *part, double *energy, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_reduce, block_grid(total_chains, kThreads), dim3(kThreads), 0, s, g, n_grids,
+                     total_chains, n_items, nsw, part, energy);
+  return hipGetLastError();
 }
 
 template <typename P, int MODEL, bool REP, bool STASH, bool RREG>

@@ -81,6 +81,7 @@ def lib():
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
         L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_reinit.argtypes = [vp]
+        L.mpr_set_launch_shape.argtypes = [vp, i32, i32, i32]
         L.mpr_validation_measures.argtypes = [vp, i32, vp, vp, dp]
         L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_set_graph.argtypes = [vp, i32]
@@ -431,6 +432,11 @@ class Field:
         _check(lib().mpr_autotune(self.ctx, _dptr(T), trial_sweeps, ctypes.byref(nsw), ctypes.byref(thr),
                                   ctypes.byref(thr1)), self.ctx)
         return nsw.value, thr.value, thr1.value
+
+    def set_launch_shape(self, nsw, threads, threads1):
+        """mpr_set_launch_shape: sweeps per multi-sweep pass and the two
+        workgroup sizes, without timing."""
+        _check(lib().mpr_set_launch_shape(self.ctx, int(nsw), int(threads), int(threads1)), self.ctx)
 
     def reinit(self):
         """mpr_reinit: hot start again from the z and known tensors given at

@@ -74,3 +74,21 @@ def test_hybrid_equilibrates_where_standard_metropolis_lags():
     tr_s = g.sweep(n, T, trace=True, trace_energy=True, over_relax=False).cpu().numpy()
     g.close()
     assert np.all(tr_s[-1, :, 1] > e_h), (tr_s[-1, :, 1], e_h)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_equilibrate_is_bit_reproducible(dtype):
+    # The per-sweep energies are summed over a chain's tiles in a fixed
+    # order, so two identical runs give bit-equal traces and stop points
+    # (Algorithm 2, steps 4.3-4.4), here on a batch of many tiles per chain.
+    z, known = random_grid(256, 320, 0.8, 23, smooth=True)
+    runs = []
+    for _ in range(2):
+        f = make_field([(z, known, 3)], dtype=dtype, seed=12, tile_x=32, tile_y=32)
+        n, at, tr = f.equilibrate([0.01], n_f=5, n_fit=20, i_max=300)
+        runs.append((n, at.copy(), tr.cpu().numpy().copy(), f.get_phi(0, 2).cpu().numpy()))
+        f.close()
+    (n1, at1, tr1, p1), (n2, at2, tr2, p2) = runs
+    assert n1 == n2 and np.array_equal(at1, at2)
+    assert np.array_equal(tr1, tr2)
+    assert np.array_equal(p1, p2)

@@ -270,6 +270,36 @@ def test_adaptation_matches_oracle_fp64():
     assert np.abs(got - phi).max() < 1e-5
 
 
+@pytest.mark.parametrize("adapt_every,nsw", [(3, 4), (2, 1), (4, 8)])
+def test_windowed_adaptation_matches_oracle_fp64(adapt_every, nsw):
+    # The a-rule on the mean acceptance of each adapt_every-sweep window
+    # (Algorithm 2, step 4.2), in calls whose lengths cross window ends and
+    # passes of up to nsw sweeps: a bit-equal to the oracle's after every
+    # call, the acceptance trace and the state as in the one-window test.
+    z, known = random_grid(48, 40, 0.5, 5)
+    kn = known.astype(bool)
+    seed = 2025
+    f = make_field([(z, known, 2)], dtype="fp64", seed=seed, tile_x=16, tile_y=16, sweeps_per_pass=nsw,
+                   adapt_every=adapt_every)
+    phi = np.stack([oracle_init(z, known, seed, c, 0, "fp64") for c in range(2)])
+    T = 2e-3
+    a = np.ones(2)
+    window = np.zeros(2)
+    i0 = 0
+    for n in (2, 5, 3, 7):
+        phi, a, acc, _ = om.run_sweeps(phi, kn, T, a, 0.5, seed, i0, n, np.arange(2), 0, adapt=True,
+                                       adapt_every=adapt_every, window=window)
+        tr = f.sweep(n, [T], adapt=True, trace=True).cpu().numpy()
+        i0 += n
+        idx, a_gpu = f.chain_state()
+        assert idx == i0
+        np.testing.assert_allclose(tr[:, :, 0], acc, rtol=0, atol=1e-12)
+        np.testing.assert_array_equal(a_gpu, a)
+    assert np.all(a > 1.0)   # the rule fired
+    got = np.stack([f.get_phi(0, c).cpu().numpy() for c in range(2)])
+    assert np.abs(got - phi).max() < 1e-5
+
+
 def test_energy_trace_matches_state_energy():
     grids = _grids(51)
     f = make_field(grids, dtype="fp64", seed=4)
