@@ -242,6 +242,25 @@ mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_t
                                    double *out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): the validation measures of
+ * mpr_validation_measures without a context, on the library's own static
+ * device scratch (one fixed array per device, kept until the process
+ * ends); no hipMalloc, no allocating library call, no synchronisation.
+ * z_true, zhat: device [n_sites] doubles; known: device [n_sites] bytes
+ * (1 = sample, left out); shift: subtracted from Z and Z_hat before the
+ * second moments of R (pass the grid's z_min to reproduce
+ * mpr_validation_measures bit for bit); out: DEVICE [8] doubles, the same
+ * eight values, written asynchronously on hip_stream (out[5] = 0 when no
+ * gap site has a finite z_true).  n_sites at most 107 372 544 (26214 chunks
+ * of 4096 sites), else MPR_E_ARG.  Every call on a device shares that
+ * device's scratch: calls that overlap on one device race.  Errors:
+ * MPR_E_ARG, MPR_E_HIP.
+ */
+mpr_status mpr_validation_measures_static(const double *z_true, const double *zhat, const uint8_t *known,
+                                          int64_t n_sites, double shift, double *out, void *hip_stream);
+
+/*
  * Give every grid of the context its own modification factor q of Eq. (3)
  * (q: host [n_grids], each in (0, 0.5]), in place of mpr_params.q.  The
  * sample and state specific energies and the sweeps of each grid then use

@@ -612,6 +612,38 @@ struct Pchip {
 
 }  // namespace
 
+// ------------------------------------------------------- static scratch
+// Device memory of mpr_validation_measures_static, which allocates nothing:
+// the per-chunk partial sums of the measures kernels.  Each device holds its
+// own copy for the life of the process.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address, per device, is
+// taken once with hipGetSymbolAddress and used everywhere instead.
+constexpr int64_t kStaticBlocks = 26214;                        // chunks of kChunk sites
+constexpr int64_t kStaticMaxSites = kStaticBlocks * kChunk;      // 107 372 544 sites; 2 MiB of scratch
+static __device__ __align__(256) double scratch[kStaticBlocks * kMeasureSums];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_dev;  // device -> address of that device's `scratch`
+
+// The current device's address of `scratch`, looked up on its first use there.
+mpr_status static_scratch(double **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_dev.find(dev);
+  if (it == g_scratch_dev.end()) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    it = g_scratch_dev.emplace(dev, static_cast<double *>(p)).first;
+  }
+  *ptr = it->second;
+  return MPR_OK;
+}
+}  // namespace
+
 // =================================================================== ABI
 extern "C" {
 
@@ -1017,6 +1049,23 @@ mpr_status mpr_validation_measures(mpr_ctx *ctx, int32_t grid, const double *z_t
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (out[5] == 0.0)
     return fail(ctx, MPR_E_DEGENERATE, "grid " + std::to_string(grid) + ": no prediction site with a finite z_true");
+  return MPR_OK;
+}
+
+mpr_status mpr_validation_measures_static(const double *z_true, const double *zhat, const uint8_t *known,
+                                          int64_t n_sites, double shift, double *out, void *hip_stream) {
+  g_thread_err.clear();
+  if (!z_true || !zhat || !known || !out) return fail(nullptr, MPR_E_ARG, "z_true, zhat, known and out are required");
+  if (n_sites < 1) return fail(nullptr, MPR_E_ARG, "n_sites must be >= 1");
+  if (n_sites > kStaticMaxSites)
+    return fail(nullptr, MPR_E_ARG, "n_sites = " + std::to_string(n_sites) + " exceeds the static scratch, which holds " +
+                                        std::to_string(kStaticMaxSites) + " sites");
+  if (!std::isfinite(shift)) return fail(nullptr, MPR_E_ARG, "shift must be finite");
+  double *scr = nullptr;
+  const mpr_status st = static_scratch(&scr);
+  if (st != MPR_OK) return st;
+  const hipError_t e = launch_measures(z_true, zhat, known, n_sites, shift, scr, out, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch_measures");
   return MPR_OK;
 }
 

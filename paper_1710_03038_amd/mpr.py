@@ -83,6 +83,7 @@ def lib():
         L.mpr_reinit.argtypes = [vp]
         L.mpr_set_launch_shape.argtypes = [vp, i32, i32, i32]
         L.mpr_validation_measures.argtypes = [vp, i32, vp, vp, dp]
+        L.mpr_validation_measures_static.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
         L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mpr_set_graph.argtypes = [vp, i32]
         L.mpr_set_grid_q.argtypes = [vp, dp]
@@ -135,6 +136,29 @@ def default_params(**overrides):
             v = {"open": BC_OPEN, "replicate": BC_REPLICATE}[v]
         setattr(p, k, v)
     return p
+
+
+STATIC_MAX_SITES = 26214 * 4096
+
+
+def validation_measures_static(z_true, zhat, known, shift, out, stream=None):
+    """mpr_validation_measures_static: the eight validation measures of
+    z_true, zhat (device float64) over the sites where known (device uint8)
+    is 0, written asynchronously into the device tensor out (8 float64s)
+    on the library's static scratch; nothing is allocated."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    n = z_true.numel()
+    if zhat.numel() != n or known.numel() != n or out.numel() < 8:
+        raise ValueError("z_true, zhat and known need one value per site; out needs 8")
+    if z_true.dtype != torch.float64 or zhat.dtype != torch.float64 or out.dtype != torch.float64 \
+            or known.dtype != torch.uint8:
+        raise ValueError("z_true, zhat, out must be float64 and known uint8")
+    _check(lib().mpr_validation_measures_static(ctypes.c_void_p(z_true.data_ptr()), ctypes.c_void_p(zhat.data_ptr()),
+                                                ctypes.c_void_p(known.data_ptr()), n, float(shift),
+                                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 def match_T(e_s, tab_T, tab_e, raise_on_range=False):

@@ -15,7 +15,7 @@ from paper_1710_03038_amd import mpr as M
 def test_library_exports_every_declared_symbol():
     L = M.lib()
     names = M.header_functions()
-    assert len(names) == 23
+    assert len(names) == 24
     for n in names:
         assert hasattr(L, n), n
 
