@@ -107,12 +107,12 @@ def profiled_traffic(workload, shape, tile):
     except OSError:
         return None
     m = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+) kernel_sources_sha256: ([0-9a-f]+)"
-                  r"(?: shape: (\d+) (\d+) (\d+) tile: (\d+) (\d+))?", text)
+                  r"(?: shape: (\d+) (\d+) (\d+) (\d+) tile: (\d+) (\d+))?", text)
     if not m or m.group(2) != h.hexdigest():
         return None
     if m.group(3) is not None:
-        prof_shape = tuple(int(m.group(i)) for i in (3, 4, 5))
-        prof_tile = (int(m.group(6)), int(m.group(7)))
+        prof_shape = tuple(int(m.group(i)) for i in (3, 4, 5, 6))
+        prof_tile = (int(m.group(7)), int(m.group(8)))
         if tuple(int(v or 0) for v in shape) != prof_shape or tuple(tile)[:2] not in (prof_tile, (0, 0)):
             return None
     return float(m.group(1))
@@ -460,7 +460,7 @@ def one_step(M, f, W, table, tune, timing=False, shape=None):
         f.set_timing(True)
     e_s, _ = f.specific_energy(M.SAMPLE_PAIRS)
     T, _ = M.match_T(e_s, table[0], table[1])
-    tuned = f.autotune(T, 16) if tune else (shape or (f.params.sweeps_per_pass, None, None))
+    tuned = f.autotune(T, 16) if tune else (shape or (f.params.sweeps_per_pass, None, None, None))
     zh, zs, rep = f.fill(T, W["n_eq"], W["n_samp"], W["stride"])
     kt = f.timing() if timing else (0.0, 0, 0)
     return dict(zh=zh, zs=zs, rep=rep, T=T, e_s=e_s, kt=kt, tuned=tuned)
@@ -608,9 +608,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="timed steps of the plain FP64 arm (each several seconds on the default workload)")
     ap.add_argument("--fp64-warmup", type=int, default=1)
-    ap.add_argument("--shape", type=int, nargs=3, default=None, metavar=("NSW", "THREADS", "THREADS1"),
+    ap.add_argument("--shape", type=int, nargs=4, default=None, metavar=("NSW", "THREADS", "THREADS1", "PERSIST1"),
                     help="fix the launch shape (sweeps per pass, workgroup size, workgroup size of single-sweep "
-                         "passes) instead of autotuning it, e.g. for profiling runs")
+                         "passes, 1 for persistent single-sweep workgroups) instead of autotuning it, e.g. for "
+                         "profiling runs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape (for profiling runs, whose timing would sway "
@@ -739,7 +740,7 @@ def main():
     avg_us = kms * 1e3 / kl if kl else None
     alg_bytes = kss / kl * b_site if kl else None  # algorithmic one-pass bytes per launch
     hbm_gbs = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
-    traffic = profiled_traffic(args.workload, tuple(tuned)[:3], tile_tuned or tuple(args.tile)) \
+    traffic = profiled_traffic(args.workload, tuple(tuned)[:4], tile_tuned or tuple(args.tile)) \
         if args.boundary == "open" and "MPR_SWEEP_THREADS" not in os.environ else None
     cfg = dict(W["config"])
     cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"],
@@ -747,7 +748,8 @@ def main():
                 "tile_autotuned": tile_tuned is not None,
                 "sweeps_per_pass_max": prm32.sweeps_per_pass or 8,
                 "autotuned_shape": {"sweeps_per_pass": tuned[0], "threads": tuned[1],
-                                    "threads_single_sweep_passes": tuned[2]}, "fill_graph": True,
+                                    "threads_single_sweep_passes": tuned[2],
+                                    "persistent_single_sweep_passes": tuned[3]}, "fill_graph": True,
                 "T_hat": float(T_hat[0]) if len(T_hat) == 1 else [float(T_hat.min()), float(T_hat.max())],
                 "e_s": float(e_s32[0]) if len(T_hat) == 1 else None})
     res = {

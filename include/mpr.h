@@ -363,22 +363,29 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
  * pass.  Choices are cached per batch shape for the process, so a later
  * context of the same shape reuses them without timing.  nsw_out,
  * threads_out (nullable) receive the choice for multi-sweep passes,
- * threads1_out (nullable) the workgroup size of single-sweep passes.  Uses the fill accumulators as
- * scratch: do not call during a fill.  Synchronises the stream.
+ * threads1_out (nullable) the workgroup size of single-sweep passes, and
+ * persist1_out (nullable) 1 if those passes run on persistent workgroups
+ * (each looping over many items and loading the next item while it sweeps
+ * the current one), 0 if on one workgroup per item; both kernels are timed.
+ * Uses the fill accumulators as scratch: do not call during a fill.
+ * Synchronises the stream.
  */
 mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out,
-                        int32_t *threads1_out);
+                        int32_t *threads1_out, int32_t *persist1_out);
 
 /*
  * Set the launch shape by hand, as mpr_autotune would: sweeps fused per
  * multi-sweep pass (1 .. the context's sweeps_per_pass), the workgroup size
- * of those passes and of single-sweep passes (64, 128, 256, 512 or 1024).
- * For callers that know their shape (repeated runs, profiling, where timing
+ * of those passes and of single-sweep passes (64, 128, 256, 512 or 1024),
+ * and whether single-sweep passes that record nothing run on persistent
+ * workgroups (persist1 != 0; used where a thread's registers hold an
+ * item's staged sites and plan entries, else one workgroup per item).  For
+ * callers that know their shape (repeated runs, profiling, where timing
  * the candidates would sway the choice).  The shape does not change
  * results.  MPR_E_ARG if a value is out of range or the pass's LDS exceeds
  * the device's; the context is then unchanged.  No device work.
  */
-mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1);
+mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1, int32_t persist1);
 
 /*
  * Tile autotuner: choose the tile shape (mpr_params.tile_x, tile_y) and the

@@ -69,6 +69,8 @@ struct mpr_ctx {
   int nsw_run = 1;             // sweeps per pass used (autotuned, <= nsw_max)
   int threads = 256;           // workgroup size of the sweep kernel
   int threads1 = 256;          // ... for single-sweep passes (the a-rule's); tuned apart
+  bool persist1 = false;       // single-sweep passes on persistent workgroups (k_sweep1) where they fit
+  std::map<std::pair<int, size_t>, int64_t> resident1;  // (threads, LDS bytes) -> k_sweep1 workgroups
   size_t lds_limit = 65536;
   std::vector<double> beta_h;  // staging for per-chain inverse temperatures
   std::string err;
@@ -88,11 +90,11 @@ struct mpr_ctx {
     int64_t sweep_index, pass_no;
     int cur, nsw_run, threads, threads1;
     int32_t n_eq, n_samp, stride;
-    bool keep_a;
+    bool keep_a, persist1;
     bool operator==(const GraphState &o) const {
       return sweep_index == o.sweep_index && pass_no == o.pass_no && cur == o.cur && nsw_run == o.nsw_run &&
              threads == o.threads && threads1 == o.threads1 && n_eq == o.n_eq && n_samp == o.n_samp &&
-             stride == o.stride && keep_a == o.keep_a;
+             stride == o.stride && keep_a == o.keep_a && persist1 == o.persist1;
     }
   };
   GraphState g_key{}, g_post{};
@@ -334,6 +336,36 @@ mpr_status drain_timing(mpr_ctx *c) {
   return MPR_OK;
 }
 
+// Workgroups for a single-sweep pass on persistent workgroups (k_sweep1):
+// as many as are resident at once, or fewer for a small batch (a multiple
+// of 8, one share per XCD); 0 to use the one-workgroup-per-item kernel:
+// when switched off, or when an item's staged sites or plan entries exceed
+// what a thread holds in registers.
+int64_t resident_blocks1(mpr_ctx *c, int thr, size_t lds) {
+  const auto key = std::make_pair(thr, lds);
+  auto it = c->resident1.find(key);
+  if (it == c->resident1.end()) {
+    const int model = c->p.model == MPR_MODEL_GMRF ? kGmrf : (c->p.q == 1.0 ? kMprQ1 : kMprQ);
+    const bool rep = c->p.boundary == MPR_BC_REPLICATE;
+    const int64_t n = c->p.dtype == MPR_FP64 ? sweep1_resident<double>(thr, model, rep, lds)
+                                             : sweep1_resident<float>(thr, model, rep, lds);
+    it = c->resident1.emplace(key, n).first;
+  }
+  return it->second;
+}
+
+template <typename P> int64_t persistent_blocks(mpr_ctx *c, const SweepArgs<P> &A, size_t lds) {
+  if (!c->persist1) return 0;
+  const int thr = c->threads1;
+  if ((int64_t)A.lds_w * A.lds_h > (int64_t)thr * p1_sites(thr)) return 0;
+  const int D0 = A.energy ? 2 : 1;  // reach of the colour-0 half-sweep, in rings
+  const int64_t reach = ((int64_t)(A.tile_x + 2 * D0) * (A.tile_y + 2 * D0) + 1) / 2;
+  if (reach > (int64_t)thr * p1_plan(thr)) return 0;
+  const int64_t res = resident_blocks1(c, thr, lds);
+  if (res < 8) return 0;  // also: no persistent kernel for this workgroup size
+  return std::min<int64_t>(res, (c->plan.n_items + 7) / 8 * 8);
+}
+
 template <typename P>
 mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace, int64_t trace_row0,
                     uint32_t record_mask, uint32_t first_mask, bool or_step) {
@@ -385,7 +417,9 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.plan_dmax = c->plan.dmax;
   A.n_items = c->plan.n_items;
   A.item_grid = c->v.item_grid;
-  HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
+  const int64_t blocks1 = nsw == 1 && record_mask == 0 ? persistent_blocks<P>(c, A, lds) : 0;
+  if (blocks1 > 0) HIP_TRY(c, launch_sweep1<P>(A, c->threads1, blocks1, lds, c->stream));
+  else HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
   if (trace_e)
     HIP_TRY(c, launch_energy_reduce(c->v.gd, c->n_grids, c->plan.total_chains, c->plan.n_items, nsw,
                                     c->v.energy_part, A.energy, c->stream));
@@ -701,6 +735,10 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
     if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) c->threads = t;
   }
   c->threads1 = c->threads;
+  // One workgroup per item by default; mpr_autotune times the persistent
+  // single-sweep kernel against it (equal or slower on the workloads
+  // measured so far), mpr_set_launch_shape selects it.
+  c->persist1 = false;
   c->sites_all_chains = plan.state_elems;
   auto bail = [&](mpr_status s) {
     g_thread_err = c->err;
@@ -917,9 +955,16 @@ static mpr_status fill_sweeps(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_
 // Clears use fill kernels, never memset nodes.
 static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_t stride) {
   const mpr_ctx::GraphState key{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
-                                ctx->threads1,    n_eq,         n_samp,    stride,       ctx->p.a_sample_keep != 0};
+                                ctx->threads1,    n_eq,         n_samp,    stride,       ctx->p.a_sample_keep != 0,
+                                ctx->persist1};
   if (!ctx->graph_exec || !(key == ctx->g_key)) {
     ctx->drop_graph();
+    {  // the occupancy query of persistent single-sweep passes, outside the capture
+      int w, h;
+      size_t lds;
+      lds_extent(ctx, 1, w, h, lds);
+      (void)resident_blocks1(ctx, ctx->threads1, lds);
+    }
     if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     const hipStream_t user = ctx->stream;
     const int64_t sweep0 = ctx->sweep_index, pass0 = ctx->pass_no;
@@ -937,7 +982,8 @@ static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, 
     ctx->capturing = false;
     ctx->stream = user;
     const mpr_ctx::GraphState post{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
-                                   ctx->threads1,    n_eq,         n_samp,    stride,       key.keep_a};
+                                   ctx->threads1,    n_eq,         n_samp,    stride,       key.keep_a,
+                                   ctx->persist1};
     // nothing has run yet: the host state goes back until the graph launches
     ctx->sweep_index = sweep0;
     ctx->pass_no = pass0;
@@ -1263,6 +1309,7 @@ static std::mutex g_tune_mu;
 struct TuneChoice {
   int nsw, threads, threads1;  // sweeps per pass and workgroup size; workgroup size of single-sweep passes
   double ms, ms1;              // their time per sweep; per sweep at one sweep per pass
+  bool persist1;               // single-sweep passes on persistent workgroups
 };
 static std::map<std::string, TuneChoice> g_tune_cache;
 
@@ -1283,6 +1330,7 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
   const int64_t sweep0 = ctx->sweep_index, pass0 = ctx->pass_no;
   const bool timing0 = ctx->timing;
   const int nsw0 = ctx->nsw_run, thr0 = ctx->threads, thr10 = ctx->threads1;
+  const bool persist0 = ctx->persist1;
   ctx->timing = false;
 
   hipEvent_t e0, e1;
@@ -1290,6 +1338,7 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
   HIP_TRY(ctx, hipEventCreate(&e1));
   double best = 1e300, best1 = 1e300;
   int best_nsw = ctx->nsw_run, best_thr = ctx->threads, best_thr1 = ctx->threads1;
+  bool best_p1 = false;
   const int nsws[] = {1, 2, 3, 4, 6, 8, 12, 16};
   // Workgroups of 64 and 128 threads are tried only where every tile is
   // small (grids below 32 x 32 sites): there many more of them share a CU.
@@ -1310,41 +1359,48 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
       ctx->threads = thr;
       ctx->threads1 = thr;
       ctx->nsw_run = nsw;
-      int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
-      st = run_sweeps(ctx, nsw, false, false, nullptr, 0);  // warm-up pass
-      // Timed runs of at least ~2 ms each (a short run is lengthened after
-      // the first), the fastest kept: close candidates are otherwise
-      // decided by one-off delays.
-      float ms = 1e30f;
-      bool lengthened = false;
-      for (int rep = 0; rep < 3 && st == MPR_OK; ++rep) {
-        if (rep == 1 && ms < 2.0f) {
-          const int64_t want = (int64_t)std::ceil(n * 2.0 / std::max(ms, 0.01f));
-          n = ((std::min<int64_t>(want, 64 * n) + nsw - 1) / nsw) * nsw;
-          ms = 1e30f;  // compare runs of the new length only
-          lengthened = true;
+      // Single-sweep passes (the a-rule's) are timed on both kernels: one
+      // workgroup per item, and persistent workgroups.
+      for (int pv = 0; pv < (nsw == 1 ? 2 : 1) && st == MPR_OK; ++pv) {
+        ctx->persist1 = pv == 1;
+        int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
+        st = run_sweeps(ctx, nsw, false, false, nullptr, 0);  // warm-up pass
+        // Timed runs of at least ~2 ms each (a short run is lengthened after
+        // the first), the fastest kept: close candidates are otherwise
+        // decided by one-off delays.
+        float ms = 1e30f;
+        bool lengthened = false;
+        for (int rep = 0; rep < 3 && st == MPR_OK; ++rep) {
+          if (rep == 1 && ms < 2.0f) {
+            const int64_t want = (int64_t)std::ceil(n * 2.0 / std::max(ms, 0.01f));
+            n = ((std::min<int64_t>(want, 64 * n) + nsw - 1) / nsw) * nsw;
+            ms = 1e30f;  // compare runs of the new length only
+            lengthened = true;
+          }
+          if (rep == 2 && !lengthened) break;  // two long runs suffice
+          HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+          st = run_sweeps(ctx, n, false, false, nullptr, 0);
+          HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+          if (st != MPR_OK) break;
+          HIP_TRY(ctx, hipEventSynchronize(e1));
+          float m = 0.f;
+          HIP_TRY(ctx, hipEventElapsedTime(&m, e0, e1));
+          ms = std::min(ms, m);
         }
-        if (rep == 2 && !lengthened) break;  // two long runs suffice
-        HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
-        st = run_sweeps(ctx, n, false, false, nullptr, 0);
-        HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
         if (st != MPR_OK) break;
-        HIP_TRY(ctx, hipEventSynchronize(e1));
-        float m = 0.f;
-        HIP_TRY(ctx, hipEventElapsedTime(&m, e0, e1));
-        ms = std::min(ms, m);
+        const double per_sweep = ms / (double)n;
+        if (pv == 0 && per_sweep < best) {  // multi-sweep passes, and passes that record
+          best = per_sweep;
+          best_nsw = nsw;
+          best_thr = thr;
+        }
+        if (nsw == 1 && per_sweep < best1) {  // the a-rule runs one sweep per pass
+          best1 = per_sweep;
+          best_thr1 = thr;
+          best_p1 = pv == 1;
+        }
       }
       if (st != MPR_OK) break;
-      const double per_sweep = ms / (double)n;
-      if (per_sweep < best) {
-        best = per_sweep;
-        best_nsw = nsw;
-        best_thr = thr;
-      }
-      if (nsw == 1 && per_sweep < best1) {  // the a-rule runs one sweep per pass
-        best1 = per_sweep;
-        best_thr1 = thr;
-      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -1364,8 +1420,9 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
   ctx->nsw_run = nsw0;
   ctx->threads = thr0;
   ctx->threads1 = thr10;
+  ctx->persist1 = persist0;
   if (st != MPR_OK) return st;
-  out = {best_nsw, best_thr, best_thr1, best, best1};
+  out = {best_nsw, best_thr, best_thr1, best, best1, best_p1};
   return MPR_OK;
 }
 
@@ -1388,7 +1445,7 @@ static mpr_status tuned_shape(mpr_ctx *ctx, const double *T, int32_t trial_sweep
 }
 
 mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int32_t *nsw_out, int32_t *threads_out,
-                        int32_t *threads1_out) {
+                        int32_t *threads1_out, int32_t *persist1_out) {
   if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
   if (trial_sweeps < 1) return fail(ctx, MPR_E_ARG, "trial_sweeps must be >= 1");
   TuneChoice ch{};
@@ -1397,13 +1454,15 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   ctx->nsw_run = ch.nsw;
   ctx->threads = ch.threads;
   ctx->threads1 = ch.threads1;
+  ctx->persist1 = ch.persist1;
   if (nsw_out) *nsw_out = ch.nsw;
   if (threads_out) *threads_out = ch.threads;
   if (threads1_out) *threads1_out = ch.threads1;
+  if (persist1_out) *persist1_out = ch.persist1 ? 1 : 0;
   return MPR_OK;
 }
 
-mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1) {
+mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1, int32_t persist1) {
   if (!ctx) return fail(nullptr, MPR_E_STATE, "ctx is NULL");
   if (nsw < 1 || nsw > ctx->nsw_max)
     return fail(ctx, MPR_E_ARG, "nsw must be in 1.." + std::to_string(ctx->nsw_max));
@@ -1420,6 +1479,7 @@ mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int3
   ctx->nsw_run = nsw;
   ctx->threads = threads;
   ctx->threads1 = threads1;
+  ctx->persist1 = persist1 != 0;
   return MPR_OK;
 }
 

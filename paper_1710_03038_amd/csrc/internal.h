@@ -111,6 +111,19 @@ hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s);
 // chain's per-item partials in a fixed order -> energy[chain][s].
 hipError_t launch_energy_reduce(const GridDesc *g, int n_grids, int total_chains, int64_t n_items, int nsw,
                                 const double *part, double *energy, hipStream_t s);
+// Persistent single-sweep kernel (k_sweep1): registers a thread holds for
+// the next item, which bound the tiles it can run.
+// LDS sites a thread stages (lds_w * lds_h <= threads * p1_sites) and plan
+// entries it holds per colour (entries within the pass's reach <= threads *
+// p1_plan), by workgroup size.
+constexpr int p1_sites(int threads) { return threads >= 1024 ? 6 : (threads >= 512 ? 11 : 12); }
+constexpr int p1_plan(int threads) { return threads >= 1024 ? 3 : (threads >= 512 ? 5 : 6); }
+template <typename P>
+hipError_t launch_sweep1(const SweepArgs<P> &a, int threads, int64_t blocks, size_t lds_bytes, hipStream_t s);
+// Workgroups of k_sweep1 that are resident at once on the device (a multiple
+// of 8, one share per XCD), or 0 if the occupancy cannot be queried.
+template <typename P>
+int64_t sweep1_resident(int threads, int model, bool rep, size_t lds_bytes);
 // Largest workgroup the sweep kernel instance for `threads` can run with
 // (0 if it cannot be queried).
 template <typename P>

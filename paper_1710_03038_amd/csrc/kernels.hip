@@ -18,6 +18,7 @@
 // numbers, so results do not depend on the tiling.
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 #include "fastmath.h"
@@ -210,7 +211,6 @@ __device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int c
 // What one colour phase of the sweep kernel needs to update a site.
 template <typename P> struct UpdateCtx {
   using V2 = typename Prec<P>::V2;
-  const uint16_t *lc;  // this colour's staged plan entries
   P *pc;               // this colour's angle plane
   V2 *cc;              // this colour's (cos, sin) plane
   const V2 *cn;        // the other colour's (cos, sin) plane
@@ -259,20 +259,20 @@ __device__ __forceinline__ void site_words(const UpdateCtx<P> &U, int ly, int lx
   st[1] = w[3];
 }
 
-// Algorithm 1 with the GMRF pair interaction for the K plan entries fs[]
+// Algorithm 1 with the GMRF pair interaction for the K plan entries es[]
 // of one thread.  A site's energy is a parabola in its angle about the mean
 // m = S/n of its n in-grid neighbours (NaN in the angle plane marks none),
 // so over-relaxation reflects about m, kept inside [0, 2 pi), and
 // dH = ((p2 - p1) (n (p2 + p1) - 2 S)) / (2 pi^2).  With REP, g auxiliary
 // neighbours add g copies of the site's own angle to S and g to n.
 template <typename P, bool REP, int K>
-__device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
+__device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, const uint32_t (&es)[K],
                                                       const bool (&cnt)[K], bool use_stash, uint32_t (&stash)[K][2]) {
   int o[K];
   P phi[K], sum[K], n[K], u[K], rr[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint32_t e = U.lc[fs[k]];
+    const uint32_t e = es[k];
     const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
     const int j = lx >> 1, par = lx & 1;
     o[k] = ly * U.P2 + j;
@@ -313,12 +313,12 @@ __device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, con
   return acc;
 }
 
-// Algorithm 1 for the K plan entries fs[] of one thread, interleaved step
+// Algorithm 1 for the K plan entries es[] of one thread, interleaved step
 // by step; returns the accepted updates among those with cnt[] set.
 template <typename P, int MODEL, bool REP, int K>
-__device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&fs)[K],
+__device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&es)[K],
                                                  const bool (&cnt)[K], bool use_stash, uint32_t (&stash)[K][2]) {
-  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, REP, K>(U, fs, cnt, use_stash, stash);
+  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, REP, K>(U, es, cnt, use_stash, stash);
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
   const P q = U.q;
@@ -327,7 +327,7 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     // A plan entry e gives LDS row (e >> 8) + Ly and column (e & 255) + Lx.
-    const uint32_t e = U.lc[fs[k]];
+    const uint32_t e = es[k];
     const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
     const int j = lx >> 1, par = lx & 1;  // par = parity of the site's x
     o[k] = ly * U.P2 + j;
@@ -593,7 +593,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       P *pc = ph + c * plane;
       V2 *cc = cs + c * plane;
       const V2 *cn = cs + (c ^ 1) * plane;
-      const UpdateCtx<P> U{lc,    pc,  cc,  cn,    ph + (c ^ 1) * plane,
+      const UpdateCtx<P> U{pc,  cc,  cn,    ph + (c ^ 1) * plane,
                            Ly,    Lx,  P2,  sbase, nx,
                            sweep, cid, gid, k0,    k1,
                            q,     inv_q, alpha, beta, A.or_step != 0,
@@ -610,17 +610,17 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       auto step = [&](uint32_t f, bool use, uint32_t(&st)[2][2]) __attribute__((always_inline)) {
         const uint32_t f2 = f + NT;
         if (kIlp == 2 && __any(f2 < n)) {
-          const uint32_t fs[2] = {f, f2 < n ? f2 : f};
+          const uint32_t es[2] = {lc[f], lc[f2 < n ? f2 : f]};
           const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
           if (f2 >= n) {  // the repeated item takes the first item's words
             st[1][0] = st[0][0];
             st[1][1] = st[0][1];
           }
-          acc += update_sites<P, MODEL, REP, 2>(U, fs, cnt, use, st);
+          acc += update_sites<P, MODEL, REP, 2>(U, es, cnt, use, st);
         } else {
-          const uint32_t fs[1] = {f};
+          const uint32_t es[1] = {lc[f]};
           const bool cnt[1] = {f < n_inner};
-          acc += update_sites<P, MODEL, REP, 1>(U, fs, cnt, use, reinterpret_cast<uint32_t(&)[1][2]>(st[0]));
+          acc += update_sites<P, MODEL, REP, 1>(U, es, cnt, use, reinterpret_cast<uint32_t(&)[1][2]>(st[0]));
         }
       };
       if (threadIdx.x < n) step(threadIdx.x, from_stash, stash);
@@ -746,6 +746,380 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
     }
   }
 
+}
+
+// ------------------------------------------------- persistent single sweep
+// One sweep per pass (the a-rule's passes) with persistent workgroups:
+// each workgroup runs a fixed share of the (grid, chain, tile) items and,
+// while it sweeps one item out of LDS, has the next item's angles and
+// gap-site plan entries already loading into registers, so the memory
+// latency of staging overlaps the arithmetic of the previous item.  The
+// plan entries stay in registers (thread i updates entries i, i + NT, ...
+// of each colour), so the pass stages no list in LDS.  Same arithmetic per
+// site and the same random words as k_sweep: results are bit-identical.
+//
+// Items are cut into 8 contiguous ranges, one per XCD (a workgroup runs on
+// XCD blockIdx.x % 8): tiles that share halo rows go through the same L2.
+// A grid descriptor in scalar registers: loaded and read from the first
+// lane (every lane loads the same one).
+__device__ __forceinline__ GridDesc uniform_desc(const GridDesc *p) {
+  static_assert(sizeof(GridDesc) % 4 == 0, "GridDesc is a whole number of words");
+  GridDesc d = *p;
+  uint32_t w[sizeof(GridDesc) / 4];
+  __builtin_memcpy(w, &d, sizeof(d));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(GridDesc) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  __builtin_memcpy(&d, w, sizeof(d));
+  return d;
+}
+
+// Where item `item` lies: its grid (from the coarse index), chain and tile.
+__device__ __forceinline__ int item_grid_of(const int32_t *item_grid, const GridDesc *grids, int n_grids,
+                                            int64_t item) {
+  const int64_t ik = item / kItemStride;
+  return find_by(grids, n_grids, item, &GridDesc::item_begin, item_grid[ik], item_grid[ik + 1]);
+}
+
+// Where item `it` of grid gi lies, and the addresses its loads use.
+template <typename P> struct ItemGeo {
+  int chain, t, nx, x0, y0, ox, oy;
+  int ax, aw, ay, ah;       // in-grid part of the LDS rectangle
+  uint32_t ib;              // chain index of LDS site (0, 0), mod 2^32
+  const P *src;             // the chain's angles
+  const uint32_t *cum;      // the tile's plan counts
+  const uint16_t *pl;       // the tile's plan entries
+};
+
+template <typename P>
+__device__ __forceinline__ ItemGeo<P> item_geo(const SweepArgs<P> &A, const GridDesc &G, int64_t it, int H) {
+  ItemGeo<P> g;
+  const int64_t local = it - G.item_begin;
+  const int tiles = G.tiles_x * G.tiles_y;
+  g.chain = (int)(local / tiles);
+  g.t = (int)(local - (int64_t)g.chain * tiles);
+  g.nx = G.nx;
+  const int ny = G.ny;
+  g.x0 = (g.t % G.tiles_x) * A.tile_x;
+  g.y0 = (g.t / G.tiles_x) * A.tile_y;
+  const int ix1 = min(g.x0 + A.tile_x, g.nx), iy1 = min(g.y0 + A.tile_y, ny);
+  g.ox = max(g.x0 - H - 1, -2);
+  g.oy = max(g.y0 - H - 1, -1);
+  g.ax = max(g.x0 - H, 0) - g.ox;
+  g.aw = min(ix1 + H, g.nx) - max(g.x0 - H, 0);
+  g.ay = max(g.y0 - H, 0) - g.oy;
+  g.ah = min(iy1 + H, ny) - max(g.y0 - H, 0);
+  g.ib = (uint32_t)((int64_t)g.oy * g.nx + g.ox);
+  g.src = A.src + G.state_off + (int64_t)g.chain * g.nx * ny;
+  g.cum = A.plan_cum + (G.plan_begin + g.t) * 2 * (A.plan_dmax + 2);
+  g.pl = A.plan + G.plan_ebase + (int64_t)g.t * G.plan_cap;
+  return g;
+}
+
+template <typename P, int NT, int MODEL, bool REP>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 2)))
+    k_sweep1(const SweepArgs<P> A) {
+  constexpr bool QONE = MODEL == kMprQ1;
+  constexpr int kIlp = sizeof(P) == 4 ? 2 : 1;
+  constexpr int kS = p1_sites(NT), kE = p1_plan(NT);
+  using V2 = typename Prec<P>::V2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_d[NT / 64];
+  __shared__ double a_lds;
+  __shared__ uint32_t acc_lds;
+
+  const int W = A.lds_w, P2 = W >> 1, plane = A.lds_h * P2, n_lds = W * A.lds_h;
+  V2 *cs = reinterpret_cast<V2 *>(smem);
+  P *ph = reinterpret_cast<P *>(smem + 2 * plane * sizeof(V2));
+  const int H = 3;  // the LDS geometry of a one-sweep pass of k_sweep (2 * nsw + 1)
+  const int cstride = A.plan_dmax + 2;
+  // Reach of the two half-sweeps (rings), one more with the energy traced.
+  const int D0 = A.energy ? 2 : 1, D1 = D0 - 1;
+  // The LDS site of a thread's k-th staging slot, the same for every item.
+  const float invw = 1.0f / (float)W;
+  const int dly = NT / W, dlx = NT - (NT / W) * W;
+  int sly0, slx0;
+  split_index((int)threadIdx.x, W, invw, sly0, slx0);
+
+  // This workgroup's items: xcd range [r0, r1), items r0 + lb + k * g8.
+  const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, g8 = gridDim.x >> 3;
+  const int64_t per = (A.n_items + 7) / 8;
+  const int64_t r0 = (int64_t)xcd * per, r1 = min(r0 + per, A.n_items);
+  int64_t item = r0 + lb;
+  if (item >= r1) return;
+
+  // The loads are ordered so that a wait for one of them never waits for a
+  // later item's angles or entries (the counter of outstanding loads
+  // retires in issue order): the next item's plan counts are loaded one
+  // item ahead, its grid descriptor reused while the grid stays the same.
+  //   vn, inmask: angles of the next item (and which slots lie in the grid)
+  //   en[c][j]: plan entry threadIdx.x + j * NT of colour c of the next item
+  //   cum_n / cum_nn: plan counts of the next item / the one after
+  P vn[kS];
+  uint32_t inmask = 0;
+  uint32_t en[2][kE];
+  struct Counts { uint32_t n[2], inner[2], c1; };
+  // The same counts in scalar registers (read from the first lane): used
+  // there, they keep the sweep's loops free of waits for vector loads.
+  auto scalar = [](const Counts &k) __attribute__((always_inline)) {
+    Counts u;
+    u.n[0] = __builtin_amdgcn_readfirstlane(k.n[0]);
+    u.n[1] = __builtin_amdgcn_readfirstlane(k.n[1]);
+    u.inner[0] = __builtin_amdgcn_readfirstlane(k.inner[0]);
+    u.inner[1] = __builtin_amdgcn_readfirstlane(k.inner[1]);
+    u.c1 = __builtin_amdgcn_readfirstlane(k.c1);
+    return u;
+  };
+  auto load_counts = [&](const uint32_t *cum) __attribute__((always_inline)) {
+    Counts k;
+    k.n[0] = cum[D0 + 1];
+    k.n[1] = cum[cstride + D1 + 1];
+    k.inner[0] = cum[1];
+    k.inner[1] = cum[cstride + 1];
+    k.c1 = cum[A.plan_dmax + 1];
+    return k;
+  };
+  auto load_sites = [&](const ItemGeo<P> &g) __attribute__((always_inline)) {
+    int sly = sly0, slx = slx0;
+    inmask = 0;
+#pragma unroll
+    for (int k = 0; k < kS; ++k) {
+      vn[k] = P(0);
+      if (k * NT < n_lds && sly < A.lds_h && (uint32_t)(slx - g.ax) < (uint32_t)g.aw &&
+          (uint32_t)(sly - g.ay) < (uint32_t)g.ah) {
+        vn[k] = g.src[g.ib + (uint32_t)(sly * g.nx + slx)];
+        inmask |= 1u << k;
+      }
+      slx += dlx;
+      sly += dly;
+      if (slx >= W) {
+        slx -= W;
+        ++sly;
+      }
+    }
+  };
+  // (One register per entry: nothing uses a loaded entry before the next
+  // item, so no wait follows these loads.)
+  auto load_plan = [&](const ItemGeo<P> &g, int c, uint32_t n, uint32_t base) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < kE; ++j) {
+      const uint32_t f = threadIdx.x + (uint32_t)(j * NT);
+      if (f < n) en[c][j] = g.pl[base + f];
+    }
+  };
+  // Grid of an item: the cached one while the item lies in it.
+  auto in_grid = [&](const GridDesc &G, int64_t it) __attribute__((always_inline)) {
+    return it >= G.item_begin && it < G.item_begin + (int64_t)G.chains * G.tiles_x * G.tiles_y;
+  };
+
+  GridDesc G = uniform_desc(A.grids + item_grid_of(A.item_grid, A.grids, A.n_grids, item));  // grid of `item`
+  // Plan counts of the current and of the next item, in two sets whose
+  // roles alternate between iterations (the loop body is written twice):
+  // the set that held the current item's counts receives those of the item
+  // after next once its last reader is done, so no counts move between
+  // registers (a move would wait for the load, and with it for every load
+  // issued earlier).
+  Counts kA, kB{};
+  {
+    const ItemGeo<P> g = item_geo(A, G, item, H);
+    kA = load_counts(g.cum);
+    load_sites(g);
+    load_plan(g, 0, kA.n[0], 0u);
+    load_plan(g, 1, kA.n[1], kA.c1);
+  }
+  GridDesc Gn = G;  // grid of the next item
+  int64_t next = item + g8;
+  if (next < r1) {
+    if (!in_grid(Gn, next)) Gn = uniform_desc(A.grids + item_grid_of(A.item_grid, A.grids, A.n_grids, next));
+    kB = load_counts(item_geo(A, Gn, next, H).cum);
+  }
+  int a_chain = -1, b_chain = -1;
+  P beta = P(0);
+  if (threadIdx.x == 0) acc_lds = 0u;
+
+  // One item; returns false after the workgroup's last item.
+  auto step = [&](Counts &kc_v, Counts &kn_v) __attribute__((always_inline)) {
+    // (this item's counts were loaded two items ago, the next item's during
+    // the previous write-out: waiting for them here waits for no angle)
+    const Counts kc = scalar(kc_v), kn = scalar(kn_v);
+    const ItemGeo<P> g = item_geo(A, G, item, H);
+    const int nx = g.nx, ny = G.ny;
+    const int x0 = g.x0, y0 = g.y0, ox = g.ox, oy = g.oy, chain = g.chain, t = g.t;
+    const int ix1 = min(x0 + A.tile_x, nx), iy1 = min(y0 + A.tile_y, ny);
+    const int par0 = (ox + oy) & 1;
+    const P q = (P)G.q, inv_q = (P)G.inv_q;
+    const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
+    const int gchain = G.chain_base + chain;
+
+    // Stage this item from the registers (as k_sweep does).
+    {
+      int sly = sly0, slx = slx0;
+#pragma unroll
+      for (int k = 0; k < kS; ++k) {
+        if (k * NT < n_lds && sly < A.lds_h) {
+          const int o = ((slx + sly + par0) & 1) * plane + sly * P2 + (slx >> 1);
+          const bool in = (inmask >> k) & 1u;
+          if constexpr (MODEL == kGmrf) {
+            ph[o] = in ? vn[k] : P(__builtin_nan(""));
+          } else {
+            const P val = in ? vn[k] : -P(0);
+            if (!in || REP || o >= plane || signbit(val)) {
+              P s_ = P(0), c_ = P(0);
+              if (in) {
+                if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
+                else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+              }
+              cs[o] = V2{c_, s_};
+            }
+            ph[o] = val;
+          }
+        }
+        slx += dlx;
+        sly += dly;
+        if (slx >= W) {
+          slx -= W;
+          ++sly;
+        }
+      }
+    }
+    // The previous pass's end for this chain: once per chain, and by tile 0.
+    if (threadIdx.x == 0) {
+      if (gchain != a_chain || t == 0) {
+        a_lds = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0) : A.a_now[gchain];
+        a_chain = gchain;
+      }
+    }
+    if (t == 0 && threadIdx.x < kMaxPass) A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
+    if (gchain != b_chain) {  // one inverse temperature per chain, in scalar registers
+      const double b = A.beta[gchain];
+      uint32_t w[2];
+      __builtin_memcpy(w, &b, 8);
+      w[0] = __builtin_amdgcn_readfirstlane(w[0]);
+      w[1] = __builtin_amdgcn_readfirstlane(w[1]);
+      double bu;
+      __builtin_memcpy(&bu, w, 8);
+      beta = (P)bu;
+      b_chain = gchain;
+    }
+    __syncthreads();
+
+    // The next item: its angles load during this item's first half-sweep,
+    // its colour-0 entries during the second, its colour-1 entries and the
+    // counts of the item after it during the write-out.
+    const bool more = next < r1;
+    const int64_t next2 = next + g8;
+    ItemGeo<P> gn{};
+    if (more) {
+      gn = item_geo(A, Gn, next, H);
+      load_sites(gn);
+    }
+
+    const P alpha = (P)(6.28318530717958647692 / a_lds);
+    const uint32_t sbase = g.ib;
+    const int Ly = y0 - oy - kPlanOffset, Lx = x0 - ox - kPlanOffset;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const UpdateCtx<P> U{ph + c * plane, cs + c * plane, cs + (c ^ 1) * plane, ph + (c ^ 1) * plane,
+                           Ly, Lx, P2, sbase, nx,
+                           A.sweep0, (uint32_t)chain, (uint32_t)G.grid_id, A.key0, A.key1,
+                           q, inv_q, alpha, beta, A.or_step != 0,
+                           -ox, nx - 1 - ox, -oy, ny - 1 - oy,
+                           c == 0};
+      const uint32_t n = kc.n[c], n_inner = kc.inner[c];
+#pragma unroll
+      for (int j = 0; j < kE; j += kIlp) {
+        if ((uint32_t)(j * NT) >= n) break;
+        const uint32_t f = threadIdx.x + (uint32_t)(j * NT);
+        if (f < n) {
+          uint32_t spare[2][2];
+          const uint32_t f2 = f + NT;
+          if (kIlp == 2 && j + 1 < kE && __any(f2 < n)) {
+            const uint32_t e0 = en[c][j], e1 = en[c][j + 1 < kE ? j + 1 : j];
+            const uint32_t es[2] = {e0, f2 < n ? e1 : e0};
+            const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
+            acc += update_sites<P, MODEL, REP, 2>(U, es, cnt, false, spare);
+          } else {
+            const uint32_t es[1] = {en[c][j]};
+            const bool cnt[1] = {f < n_inner};
+            acc += update_sites<P, MODEL, REP, 1>(U, es, cnt, false, reinterpret_cast<uint32_t(&)[1][2]>(spare[0]));
+          }
+        }
+      }
+      __syncthreads();
+      if (more) load_plan(gn, c, kn.n[c], c ? kn.c1 : 0u);
+    }
+    // The counts of the item after next, into the set this item's counts
+    // held (read for the last time above).
+    GridDesc Gx = Gn;
+    if (more && next2 < r1) {
+      if (!in_grid(Gx, next2)) Gx = uniform_desc(A.grids + item_grid_of(A.item_grid, A.grids, A.n_grids, next2));
+      kc_v = load_counts(item_geo(A, Gx, next2, H).cum);
+    }
+    {
+      const uint32_t wsum = wave_sum(acc);
+      if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(&acc_lds, wsum);
+    }
+    const int iw = ix1 - x0, ih = iy1 - y0;
+    const float inv_iw = 1.0f / (float)iw;
+    if (A.energy) {
+      // Eq. (5): pairs owned by interior sites (as k_sweep), one partial per item.
+      P e = P(0);
+      for (int f = threadIdx.x; f < iw * ih; f += NT) {
+        int r, cx;
+        split_index(f, iw, inv_iw, r, cx);
+        const int gx = x0 + cx, gy = y0 + r;
+        const int lx = gx - ox, ly = gy - oy;
+        const int col = (gx + gy) & 1;
+        const P v = fabs(ph[col * plane + ly * P2 + (lx >> 1)]);
+        auto pair = [&](P d) {
+          if constexpr (MODEL == kGmrf) return d * d * Prec<P>::inv_2pi2;
+          const P sn = Prec<P>::sin_(q * d * P(0.5));
+          return P(2) * sn * sn;
+        };
+        if (gx + 1 < nx) e += pair(v - fabs(ph[(col ^ 1) * plane + ly * P2 + ((lx + 1) >> 1)]));
+        if (gy + 1 < ny) e += pair(v - fabs(ph[(col ^ 1) * plane + (ly + 1) * P2 + (lx >> 1)]));
+      }
+      const double et = block_sum<NT>((double)e, red_d);
+      if (threadIdx.x == 0) A.energy_part[item] = et;
+    }
+    // Write the interior's gap sites (as k_sweep), in a fixed number of
+    // slots (the interior is part of the staged rectangle).
+    {
+      P *dst = A.dst + cbase;
+      const int dr = NT / iw, dc = NT - (NT / iw) * iw;
+      int r, cx;
+      split_index((int)threadIdx.x, iw, inv_iw, r, cx);
+#pragma unroll
+      for (int k = 0; k < kS; ++k) {
+        if (k * NT + (int)threadIdx.x < iw * ih) {
+          const int lx = x0 - ox + cx, ly = y0 - oy + r;
+          const P v = ph[((lx + ly + par0) & 1) * plane + ly * P2 + (lx >> 1)];
+          if (!signbit(v)) dst[(uint32_t)(y0 + r) * (uint32_t)nx + (uint32_t)(x0 + cx)] = v;
+        }
+        cx += dc;
+        r += dr;
+        if (cx >= iw) {
+          cx -= iw;
+          ++r;
+        }
+      }
+    }
+    __syncthreads();  // LDS is restaged next; acc_lds is complete
+    // Accepted counts: one device atomic per run of items of one chain.
+    const int next_chain = more ? Gn.chain_base + gn.chain : -1;
+    if (threadIdx.x == 0 && (!more || next_chain != gchain)) {
+      if (acc_lds) atomicAdd(&A.counts[(int64_t)gchain * kMaxPass], acc_lds);
+      acc_lds = 0u;
+    }
+    if (!more) return false;
+    item = next;
+    next = next2;
+    G = Gn;
+    Gn = Gx;
+    return true;
+  };
+  while (step(kA, kB) && step(kB, kA)) {
+  }
 }
 
 // ------------------------------------------------------------------- plan
@@ -959,6 +1333,67 @@ hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, siz
   }
   return hipGetLastError();
 }
+
+// Persistent single-sweep workgroups of 256 and 1024 threads (the kernel's
+// register budget holds a 64 x 64 tile's staging at 1024 threads without
+// spilling; at 512 it does not).  Other sizes use one workgroup per item.
+template <typename P, int MODEL, bool REP>
+static const void *sweep1_fn(int threads) {
+  switch (threads) {
+    case 256: return reinterpret_cast<const void *>(&k_sweep1<P, 256, MODEL, REP>);
+    case 1024: return reinterpret_cast<const void *>(&k_sweep1<P, 1024, MODEL, REP>);
+    default: return nullptr;
+  }
+}
+template <typename P> static const void *sweep1_fn(int threads, int model, bool rep) {
+  if (rep) {
+    if (model == kGmrf) return sweep1_fn<P, kGmrf, true>(threads);
+    if (model == kMprQ1) return sweep1_fn<P, kMprQ1, true>(threads);
+    return sweep1_fn<P, kMprQ, true>(threads);
+  }
+  if (model == kGmrf) return sweep1_fn<P, kGmrf, false>(threads);
+  if (model == kMprQ1) return sweep1_fn<P, kMprQ1, false>(threads);
+  return sweep1_fn<P, kMprQ, false>(threads);
+}
+
+template <typename P>
+hipError_t launch_sweep1(const SweepArgs<P> &a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+  const int model = a.gmrf ? kGmrf : (a.q_is_one ? kMprQ1 : kMprQ);
+  const void *fn = sweep1_fn<P>(threads, model, a.rep != 0);
+  if (!fn || blocks < 8 || blocks % 8 != 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  void *args[] = {const_cast<SweepArgs<P> *>(&a)};
+  return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3((unsigned)threads), args, lds, s);
+}
+template hipError_t launch_sweep1<float>(const SweepArgs<float> &, int, int64_t, size_t, hipStream_t);
+template hipError_t launch_sweep1<double>(const SweepArgs<double> &, int, int64_t, size_t, hipStream_t);
+
+// Workgroups per CU: the least of what the CU's LDS, its thread slots and
+// the kernel's registers allow (the occupancy query's own figure, or the
+// LDS bound where the query assumes less LDS per CU than gfx950 has).
+template <typename P> int64_t sweep1_resident(int threads, int model, bool rep, size_t lds) {
+  const void *fn = sweep1_fn<P>(threads, model, rep);
+  if (!fn) return 0;
+  int per_cu = 0, dev = 0, cus = 0, lds_cu = 0, lds_blk = 0, thr_cu = 0, regs = 0;
+  hipFuncAttributes at{};
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&thr_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&regs, hipDeviceAttributeMaxRegistersPerMultiprocessor, dev) != hipSuccess ||
+      hipFuncGetAttributes(&at, fn) != hipSuccess)
+    return 0;
+  const size_t lds_all = lds + at.sharedSizeBytes;
+  int64_t n = std::max<int64_t>(lds_cu, lds_blk) / std::max<size_t>(lds_all, 1);
+  n = std::min<int64_t>(n, thr_cu / threads);
+  if (at.numRegs > 0 && regs > 0) n = std::min<int64_t>(n, regs / ((int64_t)at.numRegs * threads));
+  n = std::max<int64_t>(n, per_cu);
+  n = std::max<int64_t>(n, 1) * cus;
+  return n / 8 * 8;
+}
+template int64_t sweep1_resident<float>(int, int, bool, size_t);
+template int64_t sweep1_resident<double>(int, int, bool, size_t);
 
 template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};

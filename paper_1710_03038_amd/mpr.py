@@ -79,9 +79,10 @@ def lib():
         L.mpr_set_phi.argtypes = [vp, i32, i32, vp]
         L.mpr_get_chain_state.argtypes = [vp, ctypes.POINTER(i64), dp]
         L.mpr_set_chain_state.argtypes = [vp, i64, dp]
-        L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.mpr_autotune.argtypes = [vp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]
         L.mpr_reinit.argtypes = [vp]
-        L.mpr_set_launch_shape.argtypes = [vp, i32, i32, i32]
+        L.mpr_set_launch_shape.argtypes = [vp, i32, i32, i32, i32]
         L.mpr_validation_measures.argtypes = [vp, i32, vp, vp, dp]
         L.mpr_validation_measures_static.argtypes = [vp, vp, vp, i64, ctypes.c_double, vp, vp]
         L.mpr_equilibrate.argtypes = [vp, dp, i32, i32, i32, u32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -448,19 +449,22 @@ class Field:
 
     def autotune(self, T, trial_sweeps=16):
         """mpr_autotune: returns (sweeps per pass, workgroup size, workgroup
-        size of single-sweep passes) chosen."""
+        size of single-sweep passes, 1 if those run on persistent workgroups)
+        chosen."""
         T = self._T(T)
         nsw = ctypes.c_int32(0)
         thr = ctypes.c_int32(0)
         thr1 = ctypes.c_int32(0)
+        p1 = ctypes.c_int32(0)
         _check(lib().mpr_autotune(self.ctx, _dptr(T), trial_sweeps, ctypes.byref(nsw), ctypes.byref(thr),
-                                  ctypes.byref(thr1)), self.ctx)
-        return nsw.value, thr.value, thr1.value
+                                  ctypes.byref(thr1), ctypes.byref(p1)), self.ctx)
+        return nsw.value, thr.value, thr1.value, p1.value
 
-    def set_launch_shape(self, nsw, threads, threads1):
-        """mpr_set_launch_shape: sweeps per multi-sweep pass and the two
-        workgroup sizes, without timing."""
-        _check(lib().mpr_set_launch_shape(self.ctx, int(nsw), int(threads), int(threads1)), self.ctx)
+    def set_launch_shape(self, nsw, threads, threads1, persist1=1):
+        """mpr_set_launch_shape: sweeps per multi-sweep pass, the two
+        workgroup sizes and persistent single-sweep passes, without timing."""
+        _check(lib().mpr_set_launch_shape(self.ctx, int(nsw), int(threads), int(threads1), int(persist1)),
+               self.ctx)
 
     def reinit(self):
         """mpr_reinit: hot start again from the z and known tensors given at

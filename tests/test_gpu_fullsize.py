@@ -43,7 +43,7 @@ def _oracle_window(z, known, bounds, seed, chain, grid, T, a, sweep0, nsw, win, 
     return phi[0][cut], {k: v[0][cut] for k, v in margins.items()}, kw[cut]
 
 
-def _check_workload(name, chains_checked, dtype, nsw, T=None, a=2.0, sweep0=3):
+def _check_workload(name, chains_checked, dtype, nsw, T=None, a=2.0, sweep0=3, shape=None):
     import mprgen
     z, known, spec = mprgen.workload(name)
     kn = known.astype(bool)
@@ -56,6 +56,8 @@ def _check_workload(name, chains_checked, dtype, nsw, T=None, a=2.0, sweep0=3):
     if dtype == "fp64":
         params["sweeps_per_pass"] = nsw
     f = make_field([(z, known, spec["chains"])], **params)
+    if shape:
+        f.set_launch_shape(*shape)
     f.set_chain_state(sweep0, np.full(f.total_chains, a))
     f.sweep(nsw, [T])
     ny, nx = z.shape
@@ -95,8 +97,45 @@ def test_grid512x512chains_fp64_full_pass():
     _check_workload("grid512x512chains", [0, 511], "fp64", 4)
 
 
-def test_grid8192x64chains_fp32_one_sweep():
-    _check_workload("grid8192x64chains", [0, 63], "fp32", 1)
+@pytest.mark.parametrize("shape", [None, (2, 512, 512)])
+def test_grid8192x64chains_fp32_one_sweep(shape):
+    # library defaults, and the shape the benchmark's autotuner picks here
+    _check_workload("grid8192x64chains", [0, 63], "fp32", 1, shape=shape)
+
+
+def test_grid8192x64chains_fp64_one_sweep():
+    # the comparator arm of the benchmark: FP64, one sweep per pass, the
+    # library's FP64 tile (32 x 32, 256 threads), 1.7e11 bytes of workspace
+    import torch
+    torch.cuda.empty_cache()
+    _check_workload("grid8192x64chains", [0, 63], "fp64", 1)
+    torch.cuda.empty_cache()
+
+
+def test_grid64_fp64_whole_fill_equals_oracle():
+    # The 64 x 64 workload end to end at its own counts: Eq. (2), the hot
+    # start, e_s, T-hat by SEM on the shared table, 100 equilibration sweeps
+    # with the a-rule and 100 recorded sampling sweeps (Algorithm 2), FP64,
+    # one chain; z_hat and z_std against the oracle's fill site by site.
+    import mprgen
+    from paper_1710_03038_amd.etable import load_table as product_table
+    tT, te, _ = product_table()
+    z, known, spec = mprgen.workload("grid64_fp64")
+    kn = known.astype(bool)
+    f = make_field([(z, known, 1)], dtype="fp64", seed=spec["seed"])
+    e_s, _ = f.specific_energy(0)
+    phi_s, _, _ = om.transform(z, kn)
+    e_o, _, _ = om.sample_specific_energy(phi_s, kn, 0.5)
+    assert abs(e_s[0] - e_o) <= 1e-13 * abs(e_o)
+    T, _ = om.match_T(e_s, tT, te)
+    zh, zs, rep = f.fill(T, spec["n_eq"], spec["n_samp"], spec["stride"])
+    ref = om.fill(z, kn, T[0], spec["n_eq"], spec["n_samp"], spec["stride"], seed=spec["seed"], chains=1)
+    span = ref["zmax"] - ref["zmin"]
+    assert rep["records"] == ref["records"] == 100
+    np.testing.assert_array_equal(rep["a_eq"], ref["a_eq"])
+    assert np.abs(zh[0].cpu().numpy() - ref["z_hat"]).max() <= 1e-9 * span
+    assert np.abs(zs[0].cpu().numpy() - ref["z_std"]).max() <= 1e-7 * span
+    f.close()
 
 
 @pytest.mark.parametrize("name,chains", [("grid1024", [0]), ("grid512x512chains", [0, 300])])

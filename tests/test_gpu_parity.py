@@ -300,6 +300,32 @@ def test_windowed_adaptation_matches_oracle_fp64(adapt_every, nsw):
     assert np.abs(got - phi).max() < 1e-5
 
 
+@pytest.mark.parametrize("dtype,model,boundary,thr", [("fp32", "mpr", "open", 1024), ("fp32", "mpr", "open", 256),
+                                                      ("fp64", "mpr", "open", 256), ("fp32", "gmrf", "open", 1024),
+                                                      ("fp32", "mpr", "replicate", 1024),
+                                                      ("fp64", "gmrf", "replicate", 256)])
+def test_persistent_single_sweep_passes_equal_per_item_passes(dtype, model, boundary, thr):
+    # Single-sweep passes on persistent workgroups (each sweeping many
+    # items, loading the next while sweeping the current) against one
+    # workgroup per item: bit-equal states, acceptance and energy traces,
+    # with the a-rule and the energy traced, over a batch of mixed shapes.
+    grids = _grids(71)
+    T = [0.05] * len(grids)
+    outs = []
+    for persist in (0, 1):
+        f = make_field(grids, dtype=dtype, seed=19, model=model, boundary=boundary)
+        f.set_launch_shape(1, thr, thr, persist)
+        tr = f.sweep(5, T, adapt=True, trace=True, trace_energy=True).cpu().numpy()
+        outs.append((tr, [f.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])],
+                     f.chain_state()))
+        f.close()
+    (tr0, ph0, cs0), (tr1, ph1, cs1) = outs
+    assert np.array_equal(tr0, tr1)
+    for a, b in zip(ph0, ph1):
+        assert np.array_equal(a, b)
+    assert cs0[0] == cs1[0] and np.array_equal(cs0[1], cs1[1])
+
+
 def test_energy_trace_matches_state_energy():
     grids = _grids(51)
     f = make_field(grids, dtype="fp64", seed=4)
@@ -647,7 +673,7 @@ def test_autotune_leaves_state_and_results_unchanged():
     f2.sweep(3, T, adapt=True)
     before = [f2.get_phi(g, c).cpu().numpy() for g, gr in enumerate(grids) for c in range(gr[2])]
     idx, a = f2.chain_state()
-    nsw, thr, thr1 = f2.autotune(T, 8)
+    nsw, thr, thr1, _ = f2.autotune(T, 8)
     assert 1 <= nsw <= 8 and thr in (256, 512, 1024) and thr1 in (256, 512, 1024)
     idx2, a2 = f2.chain_state()
     assert idx2 == idx and np.array_equal(a2, a)
