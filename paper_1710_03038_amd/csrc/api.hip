@@ -283,22 +283,25 @@ void bind(Views &v, const Views &o, void *ws) {
   v.item_grid = rebase(o.item_grid, b);
 }
 
-// LDS extent of a pass with nsw sweeps: tile + 2*(2*nsw + 1) halo + a ring,
-// or the whole grid plus its ring when that is smaller.
-void lds_extent(const Plan &pl, int nsw, int &w, int &h, size_t &bytes) {
-  const int H = 2 * nsw + 1;
+// LDS extent of a pass with nsw sweeps: the tile with a halo of H = 2*nsw
+// sites (one more with the energy traced; columns rounded to an even
+// count), or the whole grid plus a zero ring when that is smaller.
+void lds_extent(const Plan &pl, int nsw, bool energy, int &w, int &h, size_t &bytes) {
+  const int H = 2 * nsw + (energy ? 1 : 0), Hx = (H + 1) & ~1;
   w = 0;
   h = 0;
   for (const GridDesc &d : pl.gd) {
-    w = std::max(w, std::min(pl.tile_x + 2 * H + 2, d.nx + 3));
-    h = std::max(h, std::min(pl.tile_y + 2 * H + 2, d.ny + 2));
+    w = std::max(w, std::min(pl.tile_x + 2 * Hx, d.nx + 3));
+    h = std::max(h, std::min(pl.tile_y + 2 * H, d.ny + 2));
   }
   w = (w + 1) & ~1;
   // angle + (cos, sin) of both colours, and the staged gap-site list
   bytes = (size_t)w * h * 3 * pl.elem + (size_t)w * h * 2;
 }
 
-void lds_extent(const mpr_ctx *c, int nsw, int &w, int &h, size_t &bytes) { lds_extent(c->plan, nsw, w, h, bytes); }
+void lds_extent(const mpr_ctx *c, int nsw, bool energy, int &w, int &h, size_t &bytes) {
+  lds_extent(c->plan, nsw, energy, w, h, bytes);
+}
 
 double *a_buf(mpr_ctx *c, int64_t pass) { return c->v.a + (pass & 1) * c->plan.total_chains; }
 double *win_buf(mpr_ctx *c, int64_t pass) { return c->v.window + (pass & 1) * c->plan.total_chains; }
@@ -372,7 +375,7 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   SweepArgs<P> A{};
   int w, h;
   size_t lds;
-  lds_extent(c, nsw, w, h, lds);
+  lds_extent(c, nsw, trace_e, w, h, lds);
   if (lds > c->lds_limit)
     return fail(c, MPR_E_ARG, "tile and sweeps_per_pass need " + std::to_string(lds) + " bytes of LDS, limit " +
                                   std::to_string(c->lds_limit));
@@ -753,7 +756,7 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
   {
     int w, h;
     size_t need;
-    lds_extent(c, c->nsw_max, w, h, need);
+    lds_extent(c, c->nsw_max, true, w, h, need);
     if (need > c->lds_limit)
       return bail(fail(c, MPR_E_ARG, "tile and sweeps_per_pass need " + std::to_string(need) +
                                          " bytes of LDS per workgroup, the device allows " + std::to_string(lds)));
@@ -962,7 +965,7 @@ static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, 
     {  // the occupancy query of persistent single-sweep passes, outside the capture
       int w, h;
       size_t lds;
-      lds_extent(ctx, 1, w, h, lds);
+      lds_extent(ctx, 1, false, w, h, lds);
       (void)resident_blocks1(ctx, ctx->threads1, lds);
     }
     if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -1354,7 +1357,7 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
       if (nsw > ctx->nsw_max) break;
       int w, h;
       size_t lds;
-      lds_extent(ctx, nsw, w, h, lds);
+      lds_extent(ctx, nsw, false, w, h, lds);
       if (lds > ctx->lds_limit) break;
       ctx->threads = thr;
       ctx->threads1 = thr;
@@ -1474,7 +1477,7 @@ mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int3
   }
   int w, h;
   size_t lds;
-  lds_extent(ctx, nsw, w, h, lds);
+  lds_extent(ctx, nsw, true, w, h, lds);
   if (lds > ctx->lds_limit) return fail(ctx, MPR_E_ARG, "the pass needs more LDS than the device has");
   ctx->nsw_run = nsw;
   ctx->threads = threads;
@@ -1536,7 +1539,7 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
       if (st != MPR_OK) return st;
       int w, h;
       size_t b;
-      lds_extent(pl, nsw, w, h, b);
+      lds_extent(pl, nsw, true, w, h, b);
       if (b <= (size_t)lds) {
         cands.push_back({pp, pl.bytes});
         need = std::max(need, pl.bytes);

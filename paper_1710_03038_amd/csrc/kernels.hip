@@ -419,9 +419,13 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int nx = G.nx, ny = G.ny;
   const int x0 = (t % G.tiles_x) * A.tile_x, y0 = (t / G.tiles_x) * A.tile_y;
   const int ix1 = min(x0 + A.tile_x, nx), iy1 = min(y0 + A.tile_y, ny);
-  const int H = 2 * A.nsw + 1;
-  const int ox = max(x0 - H - 1, -2);  // even: LDS x has the parity of grid x, so both colour planes pair sites lx / 2
-  const int oy = max(y0 - H - 1, -1);
+  // Halo: 2 * nsw sites, one more when the energy is traced (the reach of
+  // the pass's first half-sweep plus one).  LDS columns start at an even
+  // grid x (LDS x has the parity of grid x, so both colour planes pair
+  // sites lx / 2); a grid edge within the halo leaves zeros outside.
+  const int H = 2 * A.nsw + (A.energy ? 1 : 0), Hx = (H + 1) & ~1;
+  const int ox = max(x0 - Hx, -2);
+  const int oy = max(y0 - H, -1);
   const int lxs = max(x0 - H, 0), lxe = min(ix1 + H, nx);
   const int lys = max(y0 - H, 0), lye = min(iy1 + H, ny);
   const int W = A.lds_w, P2 = W >> 1, plane = A.lds_h * P2;
@@ -802,8 +806,8 @@ __device__ __forceinline__ ItemGeo<P> item_geo(const SweepArgs<P> &A, const Grid
   g.x0 = (g.t % G.tiles_x) * A.tile_x;
   g.y0 = (g.t / G.tiles_x) * A.tile_y;
   const int ix1 = min(g.x0 + A.tile_x, g.nx), iy1 = min(g.y0 + A.tile_y, ny);
-  g.ox = max(g.x0 - H - 1, -2);
-  g.oy = max(g.y0 - H - 1, -1);
+  g.ox = max(g.x0 - ((H + 1) & ~1), -2);
+  g.oy = max(g.y0 - H, -1);
   g.ax = max(g.x0 - H, 0) - g.ox;
   g.aw = min(ix1 + H, g.nx) - max(g.x0 - H, 0);
   g.ay = max(g.y0 - H, 0) - g.oy;
@@ -830,7 +834,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
   const int W = A.lds_w, P2 = W >> 1, plane = A.lds_h * P2, n_lds = W * A.lds_h;
   V2 *cs = reinterpret_cast<V2 *>(smem);
   P *ph = reinterpret_cast<P *>(smem + 2 * plane * sizeof(V2));
-  const int H = 3;  // the LDS geometry of a one-sweep pass of k_sweep (2 * nsw + 1)
+  const int H = A.energy ? 3 : 2;  // the halo of a one-sweep pass (as k_sweep)
   const int cstride = A.plan_dmax + 2;
   // Reach of the two half-sweeps (rings), one more with the energy traced.
   const int D0 = A.energy ? 2 : 1, D1 = D0 - 1;
