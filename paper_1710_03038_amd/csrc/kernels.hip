@@ -33,6 +33,16 @@ static dim3 block_grid(int64_t n_blocks, int threads) {
   return dim3(65536u, (unsigned)((n_blocks + 65535) / 65536));
 }
 __device__ __forceinline__ int64_t block_index() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+// Work item of this workgroup when items are dealt to the 8 XCDs in
+// contiguous ranges: workgroup b runs on XCD b % 8, which takes items
+// (b % 8) * per + b / 8 with per = ceil(n_items / 8), so the workgroups an
+// XCD runs at one time sweep neighbouring tiles and share their halo rows
+// and columns in its L2.  The launch has at least 8 * per workgroups;
+// those past the last item get n_items.
+__device__ __forceinline__ int64_t xcd_item(int64_t n_items) {
+  const int64_t b = block_index(), per = (n_items + 7) >> 3, lb = b >> 3;
+  return lb < per ? (b & 7) * per + lb : n_items;
+}
 
 
 // ------------------------------------------------------------------ Philox
@@ -405,12 +415,15 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   __shared__ uint32_t acc_lds[kMaxPass];
   __shared__ double a_lds;
 
-  const int64_t item = block_index();
-  if (item >= A.n_items) return;  // the ragged last row of a two-row launch
+  const int64_t item = xcd_item(A.n_items);
+  if (item >= A.n_items) return;  // past the last item
   // The coarse index narrows the search to the grids between two entries
   // (usually one or two in a batch of large grids).
-  const int64_t ik = item / kItemStride;
-  const int gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin, A.item_grid[ik], A.item_grid[ik + 1]);
+  int gi = 0;
+  if (A.n_grids > 1) {
+    const int64_t ik = item / kItemStride;
+    gi = find_by(A.grids, A.n_grids, item, &GridDesc::item_begin, A.item_grid[ik], A.item_grid[ik + 1]);
+  }
   const GridDesc G = A.grids[gi];  // by value: kept in registers across LDS stores
   const int64_t local = item - G.item_begin;
   const int tiles = G.tiles_x * G.tiles_y;
@@ -436,6 +449,14 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int64_t cbase = G.state_off + (int64_t)chain * nx * ny;
   const P *src = A.src + cbase;
 
+  // The tile's plan counts, loaded before the kernel's first store to
+  // global memory (so that they come through the scalar cache, uniform and
+  // without a wait on the vector loads below).
+  const int64_t pitem = G.plan_begin + t;
+  const uint32_t *cum = A.plan_cum + pitem * 2 * (A.plan_dmax + 2);
+  const int cstride = A.plan_dmax + 2;
+  const uint32_t n0_all = cum[A.plan_dmax + 1];
+  const uint32_t na = cum[2 * A.nsw + 1], nb = cum[cstride + 2 * A.nsw];
   // Stage the tile, its halo and a frozen zero ring around them, and this
   // pass's part of the tile's gap-site plan: colour-0 entries within
   // distance 2*nsw, then colour-1 entries within distance 2*nsw - 1.  Each
@@ -449,16 +470,13 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   if (threadIdx.x == 0) a_lds = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0) : A.a_now[gchain];
   if (t == 0 && threadIdx.x < kMaxPass) A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
   uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);  // past both planes
-  const int64_t pitem = G.plan_begin + t;
-  const uint32_t *cum = A.plan_cum + pitem * 2 * (A.plan_dmax + 2);
-  const int cstride = A.plan_dmax + 2;
-  const uint32_t n0_all = cum[A.plan_dmax + 1];
-  const uint32_t na = cum[2 * A.nsw + 1], nb = cum[cstride + 2 * A.nsw];
   // LDS site (ly, lx) is grid site (oy + ly, ox + lx); its colour is
   // (lx + ly + par0) & 1.
   const int par0 = (ox + oy) & 1;
   {
-    constexpr int kStage = 16, kPlanStage = 8;
+    // One batch covers a 64 x 64 tile's sites and one-sweep plan at 512
+    // threads or more.
+    constexpr int kStage = 16, kPlanStage = NT >= 512 ? 10 : 8;
     const int n_lds = W * A.lds_h;
     const float invw = 1.0f / (float)W;
     const uint16_t *pl = A.plan + G.plan_ebase + (int64_t)t * G.plan_cap;
@@ -475,13 +493,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
     const uint32_t ib = (uint32_t)((int64_t)oy * nx + ox);
     for (int base = 0, pb = 0; base < n_lds || pb < (int)n_all; base += NT * kStage, pb += NT * kPlanStage) {
       // Slots wholly past the end (a workgroup-uniform test) issue nothing.
-      uint16_t e[kPlanStage] = {};
-#pragma unroll
-      for (int k = 0; k < kPlanStage; ++k) {
-        if (pb + k * NT >= (int)n_all) break;
-        const uint32_t f = (uint32_t)(pb + k * NT) + threadIdx.x;
-        e[k] = pl[f < na ? f : (f < n_all ? n0_all + (f - na) : 0u)];
-      }
+      // The angles load first: their addresses do not wait for the counts.
       P v[kStage];
       int o[kStage];
       bool in[kStage];
@@ -505,6 +517,13 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
           slx -= W;
           ++sly;
         }
+      }
+      uint16_t e[kPlanStage] = {};
+#pragma unroll
+      for (int k = 0; k < kPlanStage; ++k) {
+        if (pb + k * NT >= (int)n_all) break;
+        const uint32_t f = (uint32_t)(pb + k * NT) + threadIdx.x;
+        e[k] = pl[f < na ? f : (f < n_all ? n0_all + (f - na) : 0u)];
       }
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
@@ -732,21 +751,35 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   // the same value in both buffers from set-up on).  Thread i writes
   // interior sites i, i + NT, ... in row-major order, its (row, column)
   // moved by (NT / iw, NT % iw) per site.
+  // Batches of kOut sites: every LDS read of a batch is issued before its
+  // first store.
   {
+    constexpr int kOut = 8;
     P *dst = A.dst + cbase;
     const int dr = NT / iw, dc = NT - (NT / iw) * iw;
     int r, cx;
     split_index((int)threadIdx.x, iw, inv_iw, r, cx);
-    for (int f = threadIdx.x; f < iw * ih; f += NT) {
-      const int lx = x0 - ox + cx, ly = y0 - oy + r;
-      const P v = ph[((lx + ly + par0) & 1) * plane + ly * P2 + (lx >> 1)];
-      if (!signbit(v)) dst[(uint32_t)(y0 + r) * (uint32_t)nx + (uint32_t)(x0 + cx)] = v;
-      cx += dc;
-      r += dr;
-      if (cx >= iw) {
-        cx -= iw;
-        ++r;
+    for (int f0 = 0; f0 < iw * ih; f0 += kOut * NT) {
+      P v[kOut];
+      uint32_t at[kOut];
+#pragma unroll
+      for (int k = 0; k < kOut; ++k) {
+        v[k] = -P(0);
+        if (f0 + k * NT + (int)threadIdx.x < iw * ih) {
+          const int lx = x0 - ox + cx, ly = y0 - oy + r;
+          v[k] = ph[((lx + ly + par0) & 1) * plane + ly * P2 + (lx >> 1)];
+        }
+        at[k] = (uint32_t)(y0 + r) * (uint32_t)nx + (uint32_t)(x0 + cx);
+        cx += dc;
+        r += dr;
+        if (cx >= iw) {
+          cx -= iw;
+          ++r;
+        }
       }
+#pragma unroll
+      for (int k = 0; k < kOut; ++k)
+        if (!signbit(v[k])) dst[at[k]] = v[k];
     }
   }
 
@@ -1292,7 +1325,7 @@ hipError_t launch_energy_reduce(const GridDesc *g, int n_grids, int total_chains
 
 template <typename P, int MODEL, bool REP, bool STASH, bool RREG>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  const dim3 grid = block_grid(n_items, threads);
+  const dim3 grid = block_grid((n_items + 7) / 8 * 8, threads);  // xcd_item's workgroups
   switch (threads) {
     case 64: hipLaunchKernelGGL((k_sweep<P, 64, MODEL, REP, STASH, RREG>), grid, dim3(64), lds, s, a); break;
     case 128: hipLaunchKernelGGL((k_sweep<P, 128, MODEL, REP, STASH, RREG>), grid, dim3(128), lds, s, a); break;
