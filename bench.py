@@ -42,22 +42,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spin-updates/sec + realisations/sec, batched FP32 vs plain FP64, equal MAE"
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz lane-
-# instructions per second.  A SIMD issues a plain wave64 FP32 or INT32
-# instruction (v_mad_u64_u32 included) every 2 cycles and a transcendental
-# (v_sin, v_exp, v_sqrt, v_rcp) every 8, measured on gfx950 with throughput
-# probes; the published 157.3 TFLOP/s FP32 is this peak times 2 flops per FMA.
-VALU_PEAK_TINST = 256 * 4 * 32 * 2.4e9 / 1e12
-# Issue slots (2-cycle units) of one FP32 gap-site update in the compiled
-# sweep kernel for q = 1/2 when the update draws its own random words: the
-# two-update iteration of k_sweep<float> has 347 VALU instructions for two
-# updates, of which 2 x 20 v_mad_u64_u32 for Philox and 2 x 5
-# transcendentals at 4 slots each: (337 + 40) / 2 = 188.5 (the one-update
-# iteration: 165 + 5 * 4 = 185).  One Philox4x32-10 call is 58 of them
-# (20 v_mad_u64_u32 and 38 v_xor_b32); an update whose words come from the
-# previous sweep's call (odd sweeps of a multi-sweep pass) skips it.
-VALU_INST_PER_UPDATE = 188
-VALU_INST_PHILOX = 58
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs at 2.4 GHz, one wave64
+# instruction issued per SIMD at a time: 2.458e12 SIMD issue-cycles/s.
+# Issue cycles per wave64 instruction on gfx950, measured with throughput
+# probes (independent chains, 16 waves per SIMD): FP32 add/mul/fma/min/max,
+# compares and selects, v_add_u32 and v_mov 2; other 32-bit integer and bit
+# operations (xor, shifts, lshl_add, add3, mul_lo, cvt) and v_mad_u64_u32 4;
+# transcendentals (v_sin, v_exp, v_sqrt, v_rcp) 8.  The published 157.3
+# TFLOP/s FP32 is 1024 x 2.4 GHz x 64 lanes x 2 flops / 2 cycles.
+VALU_PEAK_TCYC = 256 * 4 * 2.4e9 / 1e12
+# Issue cycles of one FP32 gap-site update (q < 1) in the compiled sweep
+# kernel, per lane: the two-update step of k_sweep<float, 512> has 346 VALU
+# instructions (179 FP32/compare/select, 9 fast integer, 148 other integer,
+# 10 transcendental) = 1048 cycles for 2 x 64 updates, 8.19 per update.  Its
+# Philox4x32-10 calls are 40 v_mad_u64_u32 and 77 v_xor_b32 = 468 cycles,
+# 3.66 per update; an update whose words come from the previous sweep's
+# call (odd sweeps of a multi-sweep pass) skips them.
+CYC_PER_UPDATE = 1048 / 128
+CYC_PHILOX = 468 / 128
 
 
 def stash_fraction(n_eq, n_samp, nsw):
@@ -735,8 +737,8 @@ def main():
     ksec = kms * 1e-3
     useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
     nsw_run = tuned[0] or (prm32.sweeps_per_pass or 8)
-    inst = VALU_INST_PER_UPDATE - VALU_INST_PHILOX * stash_fraction(W["n_eq"], W["n_samp"], nsw_run)
-    achieved = useful_updates * inst / ksec / 1e12 if kms > 0 else None
+    cyc = CYC_PER_UPDATE - CYC_PHILOX * stash_fraction(W["n_eq"], W["n_samp"], nsw_run)
+    achieved = useful_updates * cyc / ksec / 1e12 if kms > 0 else None
     avg_us = kms * 1e3 / kl if kl else None
     alg_bytes = kss / kl * b_site if kl else None  # algorithmic one-pass bytes per launch
     hbm_gbs = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
@@ -772,16 +774,16 @@ def main():
         "mae_fp32_sigma": sig32,
         "fp64_plain": fp64,
         "roofline": {"bound": "alu", "kernel": "k_sweep<float> (every sweep launch of the fill)",
-                     "achieved": achieved, "peak": VALU_PEAK_TINST,
-                     "unit": "T VALU issue slots/s (lane-instructions, transcendentals x4)",
-                     "frac": (achieved / VALU_PEAK_TINST) if achieved else None,
+                     "achieved": achieved, "peak": VALU_PEAK_TCYC,
+                     "unit": "T SIMD issue-cycles/s (useful updates x their VALU issue cycles)",
+                     "frac": (achieved / VALU_PEAK_TCYC) if achieved else None,
                      "traffic": traffic,
-                     "alu_frac": (achieved / VALU_PEAK_TINST) if achieved else None,
+                     "alu_frac": (achieved / VALU_PEAK_TCYC) if achieved else None,
                      "hbm_achieved_GBps": hbm_gbs, "hbm_peak_GBps": HBM_PEAK_GBS,
                      "hbm_frac": hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
                      "hbm_measured_GBps": traffic / (avg_us * 1e-6) / 1e9 if traffic and avg_us else None,
                      "hbm_algorithmic_bytes_per_launch": alg_bytes, "bytes_per_site_sweep": b_site,
-                     "inst_per_update": inst, "avg_launch_us": avg_us, "launches": kl,
+                     "issue_cycles_per_update": cyc, "avg_launch_us": avg_us, "launches": kl,
                      "site_sweeps_per_launch": kss / kl if kl else None},
         "paper_timing": PAPER_TIMING,
     }

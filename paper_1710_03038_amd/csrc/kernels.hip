@@ -1787,7 +1787,10 @@ hipError_t launch_measures(const double *z, const double *zh, const uint8_t *kno
 // -------------------------------------------------------------- finalize
 // Per site of each grid: pool the chains' recorded states (mean and
 // variance about each chain's first record), then map back with the
-// inverse of Eq. (2).  Samples: z and 0.
+// inverse of Eq. (2).  Samples: z and 0.  One pass over the chains: each
+// chain's mean m_c and variance v_c go into sums of (m_c - K) and
+// v_c + (m_c - K)^2, K the first chain's mean, so that the pooled variance
+// (1/C) sum_c (v_c + (m_c - K)^2) - (mean - K)^2 subtracts no large terms.
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
     k_finalize(const GridDesc *grids, int n_grids, const double *const *zp, const P *state, const P *ref, const P *s1,
@@ -1799,7 +1802,7 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t n = (int64_t)G.nx * G.ny;
   const int64_t base = (b - G.sb_begin) * kChunk;
   const double *z = zp[gi];
-  const double M = (double)records, C = (double)G.chains;
+  const double inv_m = 1.0 / (double)records, C = (double)G.chains;
   for (int64_t i = base + threadIdx.x; i < min(base + kChunk, n); i += kThreads) {
     const int64_t o = G.site_off + i;
     if (signbit(state[G.state_off + i])) {
@@ -1807,21 +1810,20 @@ __global__ void __launch_bounds__(kThreads)
       if (zstd) zstd[o] = 0.0;
       continue;
     }
-    double mean = 0.0;
+    double K = 0.0, sd = 0.0, sq = 0.0;
     for (int c = 0; c < G.chains; ++c) {
       const int64_t k = G.state_off + (int64_t)c * n + i;
-      mean += (double)ref[k] + (double)s1[k] / M;
-    }
-    mean /= C;
-    double var = 0.0;
-    for (int c = 0; c < G.chains; ++c) {
-      const int64_t k = G.state_off + (int64_t)c * n + i;
-      const double m1 = (double)s1[k] / M;
+      const double m1 = (double)s1[k] * inv_m;
       const double mc = (double)ref[k] + m1;
-      const double vc = fmax((double)s2[k] / M - m1 * m1, 0.0);
-      var += vc + (mc - mean) * (mc - mean);
+      const double vc = fmax((double)s2[k] * inv_m - m1 * m1, 0.0);
+      if (c == 0) K = mc;
+      const double d = mc - K;
+      sd += d;
+      sq += vc + d * d;
     }
-    var /= C;
+    const double dm = sd / C;
+    const double mean = K + dm;
+    const double var = fmax(sq / C - dm * dm, 0.0);
     const double span = G.zmax - G.zmin;
     zhat[o] = G.zmin + span * (mean / 6.28318530717958647692);
     if (zstd) zstd[o] = span / 6.28318530717958647692 * sqrt(var);
