@@ -91,12 +91,13 @@ def bytes_per_site_sweep(elem, p):
     return elem * (1.0 + p) + 0.125
 
 
-def profiled_traffic(workload, shape, tile):
+def profiled_traffic(workload, shape, tile, single_only=False):
     """HBM bytes per sweep launch measured by rocprofv3 (FETCH_SIZE and
     WRITE_SIZE, scaled by a plain copy) for this workload, or None when
     there is no profile for it, the kernel sources changed since it was
     taken, or this run's launch shape or tile differs from the profiled
-    one."""
+    one.  With single_only (every pass of the fill is one sweep), only the
+    single-sweep part of the shape (threads, persistent) has to match."""
     import hashlib
     import re
     if workload not in PROFILES:
@@ -115,7 +116,9 @@ def profiled_traffic(workload, shape, tile):
     if m.group(3) is not None:
         prof_shape = tuple(int(m.group(i)) for i in (3, 4, 5, 6))
         prof_tile = (int(m.group(7)), int(m.group(8)))
-        if tuple(int(v or 0) for v in shape) != prof_shape or tuple(tile)[:2] not in (prof_tile, (0, 0)):
+        run_shape = tuple(int(v or 0) for v in shape)
+        same = run_shape[2:] == prof_shape[2:] if single_only else run_shape == prof_shape
+        if not same or tuple(tile)[:2] not in (prof_tile, (0, 0)):
             return None
     return float(m.group(1))
 
@@ -742,7 +745,7 @@ def main():
     avg_us = kms * 1e3 / kl if kl else None
     alg_bytes = kss / kl * b_site if kl else None  # algorithmic one-pass bytes per launch
     hbm_gbs = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
-    traffic = profiled_traffic(args.workload, tuple(tuned)[:4], tile_tuned or tuple(args.tile)) \
+    traffic = profiled_traffic(args.workload, tuple(tuned)[:4], tile_tuned or tuple(args.tile), W["n_samp"] <= 1) \
         if args.boundary == "open" and "MPR_SWEEP_THREADS" not in os.environ else None
     cfg = dict(W["config"])
     cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"],
