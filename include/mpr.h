@@ -102,7 +102,7 @@ typedef struct {
   int32_t a_sample_keep;  /* 0: a = 1 while sampling, as in Algorithm 2 step 5.2; 1: keep the adapted a */
   int32_t dtype;          /* mpr_dtype of the sweeps' arithmetic and the stored angles */
   int32_t sweeps_per_pass;/* sweeps fused per HBM pass, 1..16; 0 = library choice */
-  int32_t tile_x, tile_y; /* interior tile of one workgroup (even, 8..192); 0 = library choice */
+  int32_t tile_x, tile_y; /* interior tile of one workgroup (even, 8..188); 0 = library choice */
   uint64_t seed;          /* Philox4x32-10 key: (seed mod 2^32, seed >> 32); counter (site y*nx + x,
                              sweep >> 1, chain, grid), words (w0, w1) in even sweeps, (w2, w3) in
                              odd ones; the hot start uses 0xFFFFFFFF for sweep >> 1 and w0 */

@@ -148,7 +148,7 @@ mpr_status check_params(const mpr_params *p) {
     return fail(nullptr, MPR_E_ARG, "sweeps_per_pass must lie in [0, 16]");
   for (int t : {p->tile_x, p->tile_y})
     if (t != 0 && (t < 8 || t > kMaxTile || (t & 1)))
-      return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 192]");
+      return fail(nullptr, MPR_E_ARG, "tile sizes must be 0 or even in [8, 188]");
   if (p->model != MPR_MODEL_MPR && p->model != MPR_MODEL_GMRF)
     return fail(nullptr, MPR_E_ARG, "model must be MPR_MODEL_MPR or MPR_MODEL_GMRF");
   if (p->boundary != MPR_BC_OPEN && p->boundary != MPR_BC_REPLICATE)
@@ -295,8 +295,9 @@ void lds_extent(const Plan &pl, int nsw, bool energy, int &w, int &h, size_t &by
     h = std::max(h, std::min(pl.tile_y + 2 * H, d.ny + 2));
   }
   w = (w + 1) & ~1;
-  // angle + (cos, sin) of both colours, and the staged gap-site list
-  bytes = (size_t)w * h * 3 * pl.elem + (size_t)w * h * 2;
+  // angle + (cos, sin) of both colours, and the staged plan pairs (per LDS
+  // row and colour at most w / 4 + 2 of them, 2 bytes each)
+  bytes = (size_t)w * h * 3 * pl.elem + (size_t)h * (w + 8);
 }
 
 void lds_extent(const mpr_ctx *c, int nsw, bool energy, int &w, int &h, size_t &bytes) {
@@ -362,7 +363,9 @@ template <typename P> int64_t persistent_blocks(mpr_ctx *c, const SweepArgs<P> &
   const int thr = c->threads1;
   if ((int64_t)A.lds_w * A.lds_h > (int64_t)thr * p1_sites(thr)) return 0;
   const int D0 = A.energy ? 2 : 1;  // reach of the colour-0 half-sweep, in rings
-  const int64_t reach = ((int64_t)(A.tile_x + 2 * D0) * (A.tile_y + 2 * D0) + 1) / 2;
+  // plan pairs of colour 0 within that reach, at most: per row, those whose
+  // first site lies in [x0 - D0 - 2, ix1 + D0), one in every 4 columns
+  const int64_t reach = (int64_t)(A.tile_y + 2 * D0) * ((A.tile_x + 2 * D0) / 4 + 2);
   if (reach > (int64_t)thr * p1_plan(thr)) return 0;
   const int64_t res = resident_blocks1(c, thr, lds);
   if (res < 8) return 0;  // also: no persistent kernel for this workgroup size

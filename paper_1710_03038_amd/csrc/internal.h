@@ -79,11 +79,14 @@ struct SweepArgs {
   double *energy_part;             // this pass: [kMaxPass][n_items] energy of each item's interior pairs
   uint32_t *counts_clear;          // buffer of the pass after next, cleared by tile 0
   P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
-  // Gap-site plan (k_plan): per tile, the gap sites within ring distance
-  // plan_dmax of the interior, colour 0 then colour 1, each sorted by ring
-  // (ring = Manhattan distance from the interior rectangle); entry =
-  // ((y - y0 + 32) << 8) | (x - x0 + 32).  plan_cum[tile][c][r] = number of
-  // colour-c entries with ring < r, r = 0 .. plan_dmax + 1.
+  // Gap-site plan (k_plan): per tile, the pairs of same-colour sites
+  // (x, x + 2) in a row, x mod 4 in {0, 1}, that hold a gap site within
+  // ring distance plan_dmax of the interior, colour 0 then colour 1, each
+  // sorted by ring (a pair's ring: the least Manhattan distance from the
+  // interior rectangle of its gap sites within plan_dmax); entry =
+  // ((y - y0 + kPlanOffset) << 8) | (x - x0 + kPlanOffset) of the pair's
+  // first site.  plan_cum[tile][c][r] = number of colour-c pairs with
+  // ring < r, r = 0 .. plan_dmax + 1.
   const uint16_t *plan;
   const uint32_t *plan_cum;
   int32_t plan_dmax;
@@ -96,11 +99,12 @@ struct SweepArgs {
 // Items per entry of SweepArgs::item_grid.
 constexpr int kItemStride = 256;
 
-// Entries of the gap-site plan are packed into 16 bits with an offset of 32
-// around the tile origin; this bounds plan_dmax <= 32 and
-// tile + plan_dmax <= 224.
-constexpr int kPlanOffset = 32;
-constexpr int kMaxTile = 192;
+// Entries of the gap-site plan are packed into 16 bits with an offset of 34
+// around the tile origin (a pair's first site lies up to plan_dmax + 2
+// columns left of the tile); with plan_dmax <= 32 this bounds the tile to
+// 188 sites (188 - 1 + 32 + 34 <= 255).
+constexpr int kPlanOffset = 34;
+constexpr int kMaxTile = 188;
 
 // Launchers (kernels.hip).  All return the hipError_t of the launch.
 template <typename P>
@@ -114,10 +118,10 @@ hipError_t launch_energy_reduce(const GridDesc *g, int n_grids, int total_chains
 // Persistent single-sweep kernel (k_sweep1): registers a thread holds for
 // the next item, which bound the tiles it can run.
 // LDS sites a thread stages (lds_w * lds_h <= threads * p1_sites) and plan
-// entries it holds per colour (entries within the pass's reach <= threads *
+// pairs it holds per colour (pairs within the pass's reach <= threads *
 // p1_plan), by workgroup size.
 constexpr int p1_sites(int threads) { return threads >= 1024 ? 6 : (threads >= 512 ? 11 : 12); }
-constexpr int p1_plan(int threads) { return threads >= 1024 ? 3 : (threads >= 512 ? 5 : 6); }
+constexpr int p1_plan(int threads) { return threads >= 1024 ? 2 : (threads >= 512 ? 3 : 6); }
 template <typename P>
 hipError_t launch_sweep1(const SweepArgs<P> &a, int threads, int64_t blocks, size_t lds_bytes, hipStream_t s);
 // Workgroups of k_sweep1 that are resident at once on the device (a multiple

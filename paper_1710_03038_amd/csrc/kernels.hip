@@ -10,12 +10,14 @@
 //
 // Layout: angles are stored per (grid, chain) in natural row-major order;
 // the sign bit marks a frozen sample site (|v| is its angle).  A sweep
-// workgroup stages its tile plus a halo of 2*nsw + 1 sites in LDS, split by
+// workgroup stages its tile plus a halo of 2*nsw (+1) sites in LDS, split by
 // colour so that the sites of one colour and the neighbours they read are
 // contiguous, runs nsw sweeps there, and writes the tile interior to the
 // other buffer of a ping-pong pair.  Sites of the halo are updated
 // redundantly by neighbouring tiles with identical arithmetic and random
-// numbers, so results do not depend on the tiling.
+// numbers, so results do not depend on the tiling.  One Philox4x32-10 call
+// per sweep serves a pair of same-colour sites (x, x + 2) of a row,
+// x mod 4 in {0, 1}: counter (first site, sweep, chain, grid).
 #include "internal.h"
 
 #include <algorithm>
@@ -237,6 +239,10 @@ template <typename P> struct UpdateCtx {
   // Store the updated sites' (cos, sin): false in the pass's last
   // half-sweep, after which nothing reads them.
   bool store_cs;
+  // The interior in LDS columns ix0 .. ix1 and rows iy0 .. iy1, and the
+  // reach D of this half-sweep: a site takes part if its distance from the
+  // interior is at most D.
+  int ix0, ix1, iy0, iy1, D;
 };
 
 // Replicate auxiliary nodes (Sec. 2.5): the number of a site's neighbours
@@ -247,149 +253,120 @@ __device__ __forceinline__ int aux_count(const UpdateCtx<P> &U, int ly, int lx) 
   return (lx == U.ex0 ? 1 : 0) + (lx == U.ex1 ? 1 : 0) + (ly == U.ey0 ? 1 : 0) + (ly == U.ey1 ? 1 : 0);
 }
 
-// Random words (u, r) of a site for this sweep.  One Philox call keyed by
-// (site, sweep >> 1, chain, grid) serves two sweeps: words (w0, w1) in the
-// even one, (w2, w3) in the odd one.  On an even sweep the odd sweep's
-// words go to the thread's stash; with use_stash (an odd sweep whose even
-// predecessor ran in this pass, for the same item) they come from it.
-template <typename P>
-__device__ __forceinline__ void site_words(const UpdateCtx<P> &U, int ly, int lx, bool use_stash, uint32_t (&st)[2],
-                                           uint32_t &wu, uint32_t &wr) {
-  if (use_stash) {
-    wu = st[0];
-    wr = st[1];
-    return;
-  }
-  uint32_t w[4];
-  philox4x32_10(U.sbase + (uint32_t)(ly * U.gnx + lx), U.sweep >> 1, U.cid, U.gid, U.k0, U.k1, w);
-  const bool odd = (U.sweep & 1u) != 0;
-  wu = odd ? w[2] : w[0];
-  wr = odd ? w[3] : w[1];
-  st[0] = w[2];
-  st[1] = w[3];
-}
-
-// Algorithm 1 with the GMRF pair interaction for the K plan entries es[]
-// of one thread.  A site's energy is a parabola in its angle about the mean
-// m = S/n of its n in-grid neighbours (NaN in the angle plane marks none),
-// so over-relaxation reflects about m, kept inside [0, 2 pi), and
+// Algorithm 1 for one plan entry: a pair of sites of this colour in one
+// row, the first at LDS (ly, lx) and the second at (ly, lx + 2), whose
+// random words come from one Philox call keyed by (first site, sweep,
+// chain, grid): (w0, w1) are the first site's (u, r), (w2, w3) the
+// second's.  A site takes part if it lies in the grid, within the
+// half-sweep's reach and is a gap site; one that does not reads a harmless
+// slot and writes nothing.  The two updates are interleaved step by step.
+// Returns the accepted updates of interior sites.
+//
+// MPR pair interaction (Eq. 3): h = sum_j (cos q phi_j, sin q phi_j).
+// GMRF (Sec. 4.4): a site's energy is a parabola in its angle about the
+// mean m = S/n of its n in-grid neighbours (NaN in the angle plane marks
+// none), so over-relaxation reflects about m, kept inside [0, 2 pi), and
 // dH = ((p2 - p1) (n (p2 + p1) - 2 S)) / (2 pi^2).  With REP, g auxiliary
-// neighbours add g copies of the site's own angle to S and g to n.
-template <typename P, bool REP, int K>
-__device__ __forceinline__ uint32_t update_sites_gmrf(const UpdateCtx<P> &U, const uint32_t (&es)[K],
-                                                      const bool (&cnt)[K], bool use_stash, uint32_t (&stash)[K][2]) {
-  int o[K];
-  P phi[K], sum[K], n[K], u[K], rr[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint32_t e = es[k];
-    const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
-    const int j = lx >> 1, par = lx & 1;
-    o[k] = ly * U.P2 + j;
-    phi[k] = U.pc[o[k]];
-    const P nb[4] = {U.pn[o[k] - 1 + par], U.pn[o[k] + par], U.pn[o[k] - U.P2], U.pn[o[k] + U.P2]};
-    sum[k] = P(0);
-    n[k] = P(0);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const bool in = !__builtin_isnan(nb[m]);
-      sum[k] += in ? fabs(nb[m]) : P(0);
-      n[k] += in ? P(1) : P(0);
-    }
-    if constexpr (REP) {
-      const P g = (P)aux_count(U, ly, lx);
-      sum[k] = fma(g, phi[k], sum[k]);
-      n[k] += g;
-    }
-    uint32_t wu, wr;
-    site_words(U, ly, lx, use_stash, stash[k], wu, wr);
-    u[k] = unit<P>(wu);
-    rr[k] = unit<P>(wr);
-  }
-  uint32_t acc = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    P p1 = phi[k];
-    if (U.or_step && n[k] > P(0)) {
-      const P star = P(2) * sum[k] / n[k] - phi[k];
-      if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
-    }
-    const P p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
-    const P dH = (p2 - p1) * (n[k] * (p2 + p1) - P(2) * sum[k]) * Prec<P>::inv_2pi2;
-    const bool ok = (dH <= P(0)) || (rr[k] < Prec<P>::exp_(-U.beta * dH));
-    U.pc[o[k]] = ok ? p2 : p1;
-    acc += (ok && cnt[k]) ? 1u : 0u;
-  }
-  return acc;
-}
-
-// Algorithm 1 for the K plan entries es[] of one thread, interleaved step
-// by step; returns the accepted updates among those with cnt[] set.
-template <typename P, int MODEL, bool REP, int K>
-__device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const uint32_t (&es)[K],
-                                                 const bool (&cnt)[K], bool use_stash, uint32_t (&stash)[K][2]) {
-  if constexpr (MODEL == kGmrf) return update_sites_gmrf<P, REP, K>(U, es, cnt, use_stash, stash);
-  constexpr bool QONE = MODEL == kMprQ1;
+// neighbours (Sec. 2.5) add g copies of the site's own value.
+template <typename P, int MODEL, bool REP>
+__device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t e) {
+  constexpr bool QONE = MODEL == kMprQ1, GMRF = MODEL == kGmrf;
   using V2 = typename Prec<P>::V2;
   const P q = U.q;
-  int o[K];
-  P phi[K], hx[K], hy[K], u[K], rr[K];
+  const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
+  const int par = lx & 1;  // the parity of both sites' x
+  const int ry = max(max(U.iy0 - ly, ly - U.iy1), 0);
+  uint32_t w[4];
+  philox4x32_10(U.sbase + (uint32_t)(ly * U.gnx + lx), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
+  int o[2];
+  bool act[2], inner[2];
+  P phi[2], hx[2], hy[2], u[2], rr[2];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    // A plan entry e gives LDS row (e >> 8) + Ly and column (e & 255) + Lx.
-    const uint32_t e = es[k];
-    const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
-    const int j = lx >> 1, par = lx & 1;  // par = parity of the site's x
-    o[k] = ly * U.P2 + j;
+  for (int k = 0; k < 2; ++k) {
+    const int x = lx + 2 * k;
+    const int ring = max(max(U.ix0 - x, x - U.ix1), 0) + ry;
+    const bool geo = ring <= U.D && x <= U.ex1;
+    inner[k] = ring == 0;
+    // (LDS row 1, pair 1: every neighbour of it lies in the LDS)
+    o[k] = geo ? ly * U.P2 + (x >> 1) : U.P2 + 1;
     phi[k] = U.pc[o[k]];
-    const V2 nl = U.cn[o[k] - 1 + par], nr = U.cn[o[k] + par];
-    const V2 nu = U.cn[o[k] - U.P2], nd = U.cn[o[k] + U.P2];
-    hx[k] = nl.x + nr.x + nu.x + nd.x;
-    hy[k] = nl.y + nr.y + nu.y + nd.y;
-    if constexpr (REP) {
-      // off-grid neighbours read (0, 0); each auxiliary one adds the site's own (cos, sin)
-      const P g = (P)aux_count(U, ly, lx);
-      const V2 own = U.cc[o[k]];
-      hx[k] = fma(g, own.x, hx[k]);
-      hy[k] = fma(g, own.y, hy[k]);
+    act[k] = geo && !signbit(phi[k]);
+    if constexpr (GMRF) {
+      const P nb[4] = {U.pn[o[k] - 1 + par], U.pn[o[k] + par], U.pn[o[k] - U.P2], U.pn[o[k] + U.P2]};
+      P sum = P(0), n = P(0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bool in = !__builtin_isnan(nb[m]);
+        sum += in ? fabs(nb[m]) : P(0);
+        n += in ? P(1) : P(0);
+      }
+      if constexpr (REP) {
+        const P g = (P)aux_count(U, ly, x);
+        sum = fma(g, phi[k], sum);
+        n += g;
+      }
+      hx[k] = sum;  // S and n of the GMRF update
+      hy[k] = n;
+    } else {
+      const V2 nl = U.cn[o[k] - 1 + par], nr = U.cn[o[k] + par];
+      const V2 nu = U.cn[o[k] - U.P2], nd = U.cn[o[k] + U.P2];
+      hx[k] = nl.x + nr.x + nu.x + nd.x;
+      hy[k] = nl.y + nr.y + nu.y + nd.y;
+      if constexpr (REP) {
+        // off-grid neighbours read (0, 0); each auxiliary one adds the site's own (cos, sin)
+        const P g = (P)aux_count(U, ly, x);
+        const V2 own = U.cc[o[k]];
+        hx[k] = fma(g, own.x, hx[k]);
+        hy[k] = fma(g, own.y, hy[k]);
+      }
     }
-    uint32_t wu, wr;
-    site_words(U, ly, lx, use_stash, stash[k], wu, wr);
-    u[k] = unit<P>(wu);
-    rr[k] = unit<P>(wr);
+    u[k] = unit<P>(w[2 * k]);
+    rr[k] = unit<P>(w[2 * k + 1]);
   }
   uint32_t acc = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
-    const P h2 = hx[k] * hx[k] + hy[k] * hy[k];
-    const bool live = h2 > Prec<P>::tiny_h2;
-    const P psi = live ? Prec<P>::atan2_(hy[k], hx[k]) : P(0);
-    P p1 = phi[k];
-    if (live && U.or_step) {
-      const P star = (P(2) * psi - q * phi[k]) * U.inv_q;
-      // (+ 0 turns a reflection to -0 into +0: a set sign bit marks a sample site)
-      if (QONE) p1 = wrap_any(star);
-      else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star + P(0);
-    }
-    // Steps 2-3: restricted Metropolis proposal.
-    const P p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
-    // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
-    //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
-    P dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_dh_(q * (p2 + p1) * P(0.5) - psi) *
+  for (int k = 0; k < 2; ++k) {
+    P p1 = phi[k], p2, dH;
+    if constexpr (GMRF) {
+      const P sum = hx[k], n = hy[k];
+      if (U.or_step && n > P(0)) {
+        const P star = P(2) * sum / n - phi[k];
+        if (star >= P(0) && star < Prec<P>::two_pi) p1 = star;
+      }
+      p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
+      dH = (p2 - p1) * (n * (p2 + p1) - P(2) * sum) * Prec<P>::inv_2pi2;
+    } else {
+      // Algorithm 1, step 1: over-relaxation, Eq. (6) with the field of q*phi.
+      const P h2 = hx[k] * hx[k] + hy[k] * hy[k];
+      const bool live = h2 > Prec<P>::tiny_h2;
+      const P psi = live ? Prec<P>::atan2_(hy[k], hx[k]) : P(0);
+      if (live && U.or_step) {
+        const P star = (P(2) * psi - q * phi[k]) * U.inv_q;
+        // (+ 0 turns a reflection to -0 into +0: a set sign bit marks a sample site)
+        if (QONE) p1 = wrap_any(star);
+        else if (star >= P(0) && star < Prec<P>::two_pi) p1 = star + P(0);
+      }
+      // Steps 2-3: restricted Metropolis proposal.
+      p2 = wrap_step(p1 + U.alpha * (u[k] - P(0.5)));
+      // Step 4: dH = -sum_j [cos q(p2 - phi_j) - cos q(p1 - phi_j)]
+      //            = 2 |h| sin(q (p2 + p1)/2 - psi) sin(q (p2 - p1)/2).
+      dH = P(2) * Prec<P>::sqrt_(h2) * Prec<P>::sin_dh_(q * (p2 + p1) * P(0.5) - psi) *
            Prec<P>::sin_dh_(q * (p2 - p1) * P(0.5));
-    dH = live ? dH : P(0);
+      dH = live ? dH : P(0);
+    }
     // Steps 5-6: accept iff dH <= 0 or r < exp(-dH / T).
     const bool ok = (dH <= P(0)) || (rr[k] < Prec<P>::exp_(-U.beta * dH));
     const P nv = ok ? p2 : p1;
-    U.pc[o[k]] = nv;
-    if (U.store_cs) {
-      P s_, c_;
-      if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
-      else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
-      U.cc[o[k]] = V2{c_, s_};
+    if (act[k]) {
+      U.pc[o[k]] = nv;
+      if (!GMRF && U.store_cs) {
+        P s_, c_;
+        if (QONE) Prec<P>::sincos_(q * nv, &s_, &c_);
+        else Prec<P>::sincos_0pi_(q * nv, &s_, &c_);
+        U.cc[o[k]] = V2{c_, s_};
+      }
     }
-    acc += (ok && cnt[k]) ? 1u : 0u;
+    acc += (act[k] && ok && inner[k]) ? 1u : 0u;
   }
   return acc;
 }
@@ -406,7 +383,7 @@ __device__ __forceinline__ uint32_t update_sites(const UpdateCtx<P> &U, const ui
 // a thread's first interior sites stay in registers for the whole pass:
 // loaded before the first record and stored after the last, instead of a
 // read-modify-write in HBM per record.  The sums are the same, term by term.
-template <typename P, int NT, int MODEL, bool REP, bool STASH, bool RREG>
+template <typename P, int NT, int MODEL, bool REP, bool RREG>
 __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
@@ -476,7 +453,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   {
     // One batch covers a 64 x 64 tile's sites and one-sweep plan at 512
     // threads or more.
-    constexpr int kStage = 16, kPlanStage = NT >= 512 ? 10 : 8;
+    constexpr int kStage = 16, kPlanStage = NT >= 512 ? 5 : 8;
     const int n_lds = W * A.lds_h;
     const float invw = 1.0f / (float)W;
     const uint16_t *pl = A.plan + G.plan_ebase + (int64_t)t * G.plan_cap;
@@ -567,11 +544,6 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   // sbase + ly * nx + lx (mod 2^32).
   const int Ly = y0 - oy - kPlanOffset, Lx = x0 - ox - kPlanOffset;
   const uint32_t sbase = (uint32_t)((int64_t)oy * nx + ox);
-  // Odd-sweep random words of each thread's first two plan items per
-  // colour (the same items in every sweep of the pass).  Without STASH
-  // every sweep draws its own: the kernel then holds 8 registers fewer,
-  // which lets two workgroups share a CU where the LDS would allow it.
-  uint32_t stash0[2][2] = {}, stash1[2][2] = {};
   // Register-held fill sums (RREG): sites f = threadIdx.x + j * NT, j < kRegSites.
   constexpr int kRegSites = RREG ? (NT >= 512 ? 4096 / NT : 8) : 1;
   P r_ref[kRegSites], r_s1[kRegSites], r_s2[kRegSites];
@@ -604,60 +576,22 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
 
   for (int s = 0; s < A.nsw; ++s) {
     const uint32_t sweep = A.sweep0 + (uint32_t)s;
-    const bool from_stash = STASH && (sweep & 1u) != 0 && s > 0;
     uint32_t acc = 0;
-    // One colour phase (half-sweep); called once per colour with that
-    // colour's stash, so that every register array is indexed statically.
-    auto phase = [&](const int c, uint32_t(&stash)[2][2]) __attribute__((always_inline)) {
+    // One colour phase (half-sweep): thread i updates the plan pairs
+    // i, i + NT, ... within this half-sweep's reach.
+    for (int c = 0; c < 2; ++c) {
       const int D = 2 * A.nsw - (2 * s + c) - (A.energy ? 0 : 1);
-      const uint32_t n = cum[c * cstride + D + 1];      // entries within ring D
-      const uint32_t n_inner = cum[c * cstride + 1];    // ring 0: the interior
+      const uint32_t n = cum[c * cstride + D + 1];  // pairs within ring D
       const uint16_t *lc = list + (c ? na : 0);
-      P *pc = ph + c * plane;
-      V2 *cc = cs + c * plane;
-      const V2 *cn = cs + (c ^ 1) * plane;
-      const UpdateCtx<P> U{pc,  cc,  cn,    ph + (c ^ 1) * plane,
+      const UpdateCtx<P> U{ph + c * plane,  cs + c * plane,  cs + (c ^ 1) * plane, ph + (c ^ 1) * plane,
                            Ly,    Lx,  P2,  sbase, nx,
                            sweep, cid, gid, k0,    k1,
                            q,     inv_q, alpha, beta, A.or_step != 0,
                            -ox,   nx - 1 - ox, -oy, ny - 1 - oy,
-                           !(c == 1 && s == A.nsw - 1)};
-      // In FP32, two independent updates per thread and iteration (items f
-      // and f + NT) give the scheduler two dependency chains to interleave;
-      // a lane without a second item repeats its first, with the first's
-      // random words, whose identical write is harmless, and counts it once.
-      // FP64 keeps one per iteration (its registers would cost occupancy).
-      // The first iteration's items keep their odd-sweep words in `stash`;
-      // later ones draw their own.
-      constexpr uint32_t kIlp = sizeof(P) == 4 ? 2 : 1;
-      auto step = [&](uint32_t f, bool use, uint32_t(&st)[2][2]) __attribute__((always_inline)) {
-        const uint32_t f2 = f + NT;
-        if (kIlp == 2 && __any(f2 < n)) {
-          const uint32_t es[2] = {lc[f], lc[f2 < n ? f2 : f]};
-          const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
-          if (f2 >= n) {  // the repeated item takes the first item's words
-            st[1][0] = st[0][0];
-            st[1][1] = st[0][1];
-          }
-          acc += update_sites<P, MODEL, REP, 2>(U, es, cnt, use, st);
-        } else {
-          const uint32_t es[1] = {lc[f]};
-          const bool cnt[1] = {f < n_inner};
-          acc += update_sites<P, MODEL, REP, 1>(U, es, cnt, use, reinterpret_cast<uint32_t(&)[1][2]>(st[0]));
-        }
-      };
-      if (threadIdx.x < n) step(threadIdx.x, from_stash, stash);
-      for (uint32_t f = threadIdx.x + kIlp * NT; f < n; f += kIlp * NT) {
-        uint32_t spare[2][2];
-        step(f, false, spare);
-      }
+                           !(c == 1 && s == A.nsw - 1),
+                           x0 - ox, ix1 - 1 - ox, y0 - oy, iy1 - 1 - oy, D};
+      for (uint32_t f = threadIdx.x; f < n; f += NT) acc += update_pair<P, MODEL, REP>(U, lc[f]);
       __syncthreads();
-    };
-    if constexpr (STASH) {
-      phase(0, stash0);
-      phase(1, stash1);
-    } else {
-      for (int c = 0; c < 2; ++c) phase(c, stash0);  // no stash to index: one copy of the code
     }
 
     {
@@ -856,7 +790,6 @@ template <typename P, int NT, int MODEL, bool REP>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 2)))
     k_sweep1(const SweepArgs<P> A) {
   constexpr bool QONE = MODEL == kMprQ1;
-  constexpr int kIlp = sizeof(P) == 4 ? 2 : 1;
   constexpr int kS = p1_sites(NT), kE = p1_plan(NT);
   using V2 = typename Prec<P>::V2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -894,15 +827,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
   P vn[kS];
   uint32_t inmask = 0;
   uint32_t en[2][kE];
-  struct Counts { uint32_t n[2], inner[2], c1; };
+  struct Counts { uint32_t n[2], c1; };
   // The same counts in scalar registers (read from the first lane): used
   // there, they keep the sweep's loops free of waits for vector loads.
   auto scalar = [](const Counts &k) __attribute__((always_inline)) {
     Counts u;
     u.n[0] = __builtin_amdgcn_readfirstlane(k.n[0]);
     u.n[1] = __builtin_amdgcn_readfirstlane(k.n[1]);
-    u.inner[0] = __builtin_amdgcn_readfirstlane(k.inner[0]);
-    u.inner[1] = __builtin_amdgcn_readfirstlane(k.inner[1]);
     u.c1 = __builtin_amdgcn_readfirstlane(k.c1);
     return u;
   };
@@ -910,8 +841,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
     Counts k;
     k.n[0] = cum[D0 + 1];
     k.n[1] = cum[cstride + D1 + 1];
-    k.inner[0] = cum[1];
-    k.inner[1] = cum[cstride + 1];
     k.c1 = cum[A.plan_dmax + 1];
     return k;
   };
@@ -1061,26 +990,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
                            A.sweep0, (uint32_t)chain, (uint32_t)G.grid_id, A.key0, A.key1,
                            q, inv_q, alpha, beta, A.or_step != 0,
                            -ox, nx - 1 - ox, -oy, ny - 1 - oy,
-                           c == 0};
-      const uint32_t n = kc.n[c], n_inner = kc.inner[c];
+                           c == 0,
+                           x0 - ox, ix1 - 1 - ox, y0 - oy, iy1 - 1 - oy, c == 0 ? D0 : D1};
+      const uint32_t n = kc.n[c];
 #pragma unroll
-      for (int j = 0; j < kE; j += kIlp) {
+      for (int j = 0; j < kE; ++j) {
         if ((uint32_t)(j * NT) >= n) break;
-        const uint32_t f = threadIdx.x + (uint32_t)(j * NT);
-        if (f < n) {
-          uint32_t spare[2][2];
-          const uint32_t f2 = f + NT;
-          if (kIlp == 2 && j + 1 < kE && __any(f2 < n)) {
-            const uint32_t e0 = en[c][j], e1 = en[c][j + 1 < kE ? j + 1 : j];
-            const uint32_t es[2] = {e0, f2 < n ? e1 : e0};
-            const bool cnt[2] = {f < n_inner, f2 < n && f2 < n_inner};
-            acc += update_sites<P, MODEL, REP, 2>(U, es, cnt, false, spare);
-          } else {
-            const uint32_t es[1] = {en[c][j]};
-            const bool cnt[1] = {f < n_inner};
-            acc += update_sites<P, MODEL, REP, 1>(U, es, cnt, false, reinterpret_cast<uint32_t(&)[1][2]>(spare[0]));
-          }
-        }
+        if (threadIdx.x + (uint32_t)(j * NT) < n) acc += update_pair<P, MODEL, REP>(U, en[c][j]);
       }
       __syncthreads();
       if (more) load_plan(gn, c, kn.n[c], c ? kn.c1 : 0u);
@@ -1160,11 +1076,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
 }
 
 // ------------------------------------------------------------------- plan
-// One workgroup per (grid, tile): list the tile's gap sites within
-// Manhattan distance dmax of its interior, colour 0 first, each colour
-// sorted by distance and, within one distance, in row-major order (a
-// counting sort that keeps the scan order), so that neighbouring lanes of
-// the sweep update neighbouring sites.  The plan is the same on every run.
+// One workgroup per (grid, tile): list the pairs of same-colour sites
+// (x, x + 2) of a row, x mod 4 in {0, 1}, that hold a gap site within
+// Manhattan distance dmax of the tile's interior, colour 0 first, each
+// colour sorted by the pair's distance (the least over its gap sites within
+// dmax) and, within one distance, in the row-major order of the pair's
+// first such site (a counting sort that keeps the scan order), so that
+// neighbouring lanes of the sweep update neighbouring sites.  The plan is
+// the same on every run.
 template <typename P>
 __global__ void __launch_bounds__(kThreads)
     k_plan(const GridDesc *grids, int n_grids, int64_t n_tiles, const P *state, int tile_x, int tile_y, int dmax,
@@ -1188,16 +1107,29 @@ __global__ void __launch_bounds__(kThreads)
   const float inv = 1.0f / (float)rw;
   const int nb = 2 * (dmax + 2);
   const P *st = state + G.state_off;  // chain 0: the sample sites are those of every chain
-  // Bucket of scanned site f: colour * (dmax + 2) + ring, or -1 (a sample
-  // site or a corner of the scanned square beyond distance dmax).
+  // A site of the scanned rectangle that the plan covers: a gap site
+  // within distance dmax (its distance in ring).
+  auto covered = [&](int gx, int gy, int &ring) {
+    if (gx < rx0 || gx >= rx1) return false;
+    if (signbit(st[(int64_t)gy * nx + gx])) return false;
+    ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
+    return ring <= dmax;
+  };
+  // Bucket of scanned site f: colour * (dmax + 2) + the pair's ring if f is
+  // the first covered site of its pair, else -1.
   auto bucket = [&](int f, uint16_t &entry) {
     int r, cx;
     split_index(f, rw, inv, r, cx);
     const int gx = rx0 + cx, gy = ry0 + r;
-    if (signbit(st[(int64_t)gy * nx + gx])) return -1;
-    const int ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
-    if (ring > dmax) return -1;
-    entry = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (gx - x0 + kPlanOffset));
+    int ring, other;
+    if (!covered(gx, gy, ring)) return -1;
+    const int b = gx & ~2;  // the pair's first site
+    if (gx != b) {
+      if (covered(b, gy, other)) return -1;  // listed from the first site
+    } else if (covered(b + 2, gy, other)) {
+      ring = min(ring, other);
+    }
+    entry = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (b - x0 + kPlanOffset));
     return ((gx + gy) & 1) * (dmax + 2) + ring;
   };
   for (int i = threadIdx.x; i < kBuckets; i += kThreads) {
@@ -1323,28 +1255,25 @@ hipError_t launch_energy_reduce(const GridDesc *g, int n_grids, int total_chains
   return hipGetLastError();
 }
 
-template <typename P, int MODEL, bool REP, bool STASH, bool RREG>
+template <typename P, int MODEL, bool REP, bool RREG>
 static void launch_sweep_q(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   const dim3 grid = block_grid((n_items + 7) / 8 * 8, threads);  // xcd_item's workgroups
   switch (threads) {
-    case 64: hipLaunchKernelGGL((k_sweep<P, 64, MODEL, REP, STASH, RREG>), grid, dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((k_sweep<P, 128, MODEL, REP, STASH, RREG>), grid, dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, STASH, RREG>), grid, dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, STASH, RREG>), grid, dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP, STASH, RREG>), grid, dim3(1024), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((k_sweep<P, 64, MODEL, REP, RREG>), grid, dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sweep<P, 128, MODEL, REP, RREG>), grid, dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sweep<P, 256, MODEL, REP, RREG>), grid, dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep<P, 512, MODEL, REP, RREG>), grid, dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<P, 1024, MODEL, REP, RREG>), grid, dim3(1024), lds, s, a); break;
   }
 }
 
-template <typename P, bool REP, bool STASH, bool RREG = false>
+template <typename P, bool REP, bool RREG = false>
 static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
-  if (a.gmrf) launch_sweep_q<P, kGmrf, REP, STASH, RREG>(a, threads, n_items, lds, s);
-  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP, STASH, RREG>(a, threads, n_items, lds, s);
-  else launch_sweep_q<P, kMprQ, REP, STASH, RREG>(a, threads, n_items, lds, s);
+  if (a.gmrf) launch_sweep_q<P, kGmrf, REP, RREG>(a, threads, n_items, lds, s);
+  else if (a.q_is_one) launch_sweep_q<P, kMprQ1, REP, RREG>(a, threads, n_items, lds, s);
+  else launch_sweep_q<P, kMprQ, REP, RREG>(a, threads, n_items, lds, s);
 }
 
-// Passes of 3 or more sweeps keep random words between the sweeps of a pair
-// (their LDS already limits a CU to one workgroup); shorter passes use the
-// leaner kernel.  The replicate boundary, a rarely used option, always does.
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
@@ -1352,21 +1281,11 @@ hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, siz
   // FP32 passes recording two or more sweeps keep their fill sums in registers.
   bool rreg = false;
   if constexpr (sizeof(P) == 4) rreg = !a.rep && __builtin_popcount(a.record_mask) >= 2;
-  if (a.rep) launch_sweep_m<P, true, true>(a, threads, n_items, lds, s);
-  else if (a.nsw >= 3) {
-    if constexpr (sizeof(P) == 4)
-      if (rreg) {
-        launch_sweep_m<P, false, true, true>(a, threads, n_items, lds, s);
-        return hipGetLastError();
-      }
-    launch_sweep_m<P, false, true>(a, threads, n_items, lds, s);
+  if (a.rep) launch_sweep_m<P, true>(a, threads, n_items, lds, s);
+  else if (rreg) {
+    if constexpr (sizeof(P) == 4) launch_sweep_m<P, false, true>(a, threads, n_items, lds, s);
   } else {
-    if constexpr (sizeof(P) == 4)
-      if (rreg) {
-        launch_sweep_m<P, false, false, true>(a, threads, n_items, lds, s);
-        return hipGetLastError();
-      }
-    launch_sweep_m<P, false, false>(a, threads, n_items, lds, s);
+    launch_sweep_m<P, false>(a, threads, n_items, lds, s);
   }
   return hipGetLastError();
 }
@@ -1436,11 +1355,11 @@ template <typename P> int sweep_max_threads(int threads) {
   hipFuncAttributes at{};
   hipError_t e = hipErrorInvalidValue;
   switch (threads) {
-    case 64: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 64, kMprQ, false, true, false>)); break;
-    case 128: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 128, kMprQ, false, true, false>)); break;
-    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false, true, false>)); break;
-    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false, true, false>)); break;
-    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false, true, false>)); break;
+    case 64: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 64, kMprQ, false, false>)); break;
+    case 128: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 128, kMprQ, false, false>)); break;
+    case 256: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 256, kMprQ, false, false>)); break;
+    case 512: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 512, kMprQ, false, false>)); break;
+    case 1024: e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_sweep<P, 1024, kMprQ, false, false>)); break;
     default: break;
   }
   return e == hipSuccess ? at.maxThreadsPerBlock : 0;
@@ -1580,7 +1499,7 @@ __global__ void __launch_bounds__(kThreads)
     if (kn[i]) {
       v = -(P)((z[i] - zmin) / span * 6.28318530717958647692);
     } else {
-      // the site's counter with word 0xFFFFFFFF (sweep >> 1 never reaches it); word w0
+      // the site's counter with word 0xFFFFFFFF (the sweep word never reaches it); word w0
       uint32_t w[4];
       philox4x32_10((uint32_t)i, 0xFFFFFFFFu, (uint32_t)chain, (uint32_t)G.grid_id, k0, k1, w);
       // Float angles are rounded to the nearest float; keep gaps below 2*pi.

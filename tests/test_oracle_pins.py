@@ -395,3 +395,25 @@ def test_match_T_nodes_monotone_and_clamped():
     assert np.all(np.diff(That) > 0)
     That, st = mpr.match_T([e[0] - 0.01, e[-1] + 0.01], T, e)
     assert list(That) == [T[0], T[-1]] and list(st) == [1, 1]
+
+
+def test_site_words_distinct_across_sites_and_sweeps():
+    # Every (site, sweep) draws its own (u, r): a pair's two sites, two
+    # sweeps of one site and two chains never share a word pair (48 random
+    # bits, so a chance collision among these 9600 draws is negligible),
+    # and the u of a pair's two sites and of one site in consecutive sweeps
+    # are uncorrelated.
+    ny, nx = 40, 40
+    draws = []
+    for sweep in (6, 7, 8):
+        u, r = mpr.site_uniforms(11, ny, nx, sweep, [0, 1], 3)
+        draws.append((u, r))
+    keys = np.concatenate([(u * 2.0 ** 24).astype(np.int64).ravel() * 2 ** 24 + (r * 2.0 ** 24).astype(np.int64).ravel()
+                           for u, r in draws])
+    assert len(np.unique(keys)) == keys.size
+    u0 = draws[0][0][0]
+    first = u0[:, 0::4].ravel()
+    second = u0[:, 2::4].ravel()
+    assert abs(np.corrcoef(first, second)[0, 1]) < 0.1
+    assert abs(np.corrcoef(draws[0][0].ravel(), draws[1][0].ravel())[0, 1]) < 0.1
+    assert abs(u0.mean() - 0.5) < 0.03
