@@ -52,31 +52,15 @@ HBM_PEAK_GBS = 8000.0
 # TFLOP/s FP32 is 1024 x 2.4 GHz x 64 lanes x 2 flops / 2 cycles.
 VALU_PEAK_TCYC = 256 * 4 * 2.4e9 / 1e12
 # Issue cycles of one FP32 gap-site update (q < 1) in the compiled sweep
-# kernel, per lane: the two-update step of k_sweep<float, 512> has 346 VALU
-# instructions (179 FP32/compare/select, 9 fast integer, 148 other integer,
-# 10 transcendental) = 1048 cycles for 2 x 64 updates, 8.19 per update.  Its
-# Philox4x32-10 calls are 40 v_mad_u64_u32 and 77 v_xor_b32 = 468 cycles,
-# 3.66 per update; an update whose words come from the previous sweep's
-# call (odd sweeps of a multi-sweep pass) skips them.
-CYC_PER_UPDATE = 1048 / 128
-CYC_PHILOX = 468 / 128
+# kernel, per lane: one step of k_sweep<float, 512> updates a pair of sites
+# of one colour; the loop body (loop control included) is 296 VALU
+# instructions for colour 0 (174 FP32/compare/select, 22 fast integer, 90
+# other integer, 10 transcendental) = 832 cycles, and 312 = 878 cycles for
+# colour 1, for 2 x 64 updates: 6.68 cycles per update, of which the pair's
+# shared Philox4x32-10 call (20 v_mad_u64_u32, 40 v_xor_b32) is 1.88.
+CYC_PER_UPDATE = (832 + 878) / 2 / 128
 
 
-def stash_fraction(n_eq, n_samp, nsw):
-    """Share of a fill's site updates whose random words come from the
-    previous sweep's Philox call: the equilibration runs one sweep per pass
-    (the a-rule needs every sweep's acceptance), the sampling runs passes of
-    nsw sweeps from sweep n_eq, and the odd sweeps after a pass's first
-    sweep reuse the words.  (Items past a thread's first two per colour
-    draw their own; below 2 * 1024 per colour for the 64 x 64 tiles of the
-    default workload, so none there.)"""
-    served, s0, left = 0, n_eq, n_samp
-    while left > 0:
-        k = min(nsw, left)
-        served += sum(1 for s in range(1, k) if (s0 + s) % 2 == 1)
-        s0 += k
-        left -= k
-    return served / (n_eq + n_samp)
 KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd/csrc/fastmath.h",
                   "paper_1710_03038_amd/csrc/internal.h")
 # rocprofv3 summaries whose FETCH_SIZE / WRITE_SIZE give the measured HBM
@@ -739,8 +723,7 @@ def main():
     b_site = bytes_per_site_sweep(4, p)
     ksec = kms * 1e-3
     useful_updates = kss * p  # gap-site updates of the timed sweep launches (halo work excluded)
-    nsw_run = tuned[0] or (prm32.sweeps_per_pass or 8)
-    cyc = CYC_PER_UPDATE - CYC_PHILOX * stash_fraction(W["n_eq"], W["n_samp"], nsw_run)
+    cyc = CYC_PER_UPDATE
     achieved = useful_updates * cyc / ksec / 1e12 if kms > 0 else None
     avg_us = kms * 1e3 / kl if kl else None
     alg_bytes = kss / kl * b_site if kl else None  # algorithmic one-pass bytes per launch

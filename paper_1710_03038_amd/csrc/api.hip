@@ -1492,7 +1492,7 @@ mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int3
 // Tile candidates of mpr_autotune_tile, the library default first so that
 // a tie keeps it.  Tiles are even and row-major wide where they are not
 // square: a workgroup stages whole tile rows.
-static const int kTileCand32[][2] = {{64, 64}, {64, 48}, {32, 32}, {64, 32}, {128, 32}, {128, 64}, {96, 96}};
+static const int kTileCand32[][2] = {{64, 64}, {64, 56}, {64, 48}, {32, 32}, {64, 32}, {128, 32}, {128, 64}, {96, 96}};
 static const int kTileCand64[][2] = {{32, 32}, {16, 16}, {32, 16}, {64, 32}, {64, 64}};
 
 static constexpr double kTileMargin = 0.95;  // a tile must cost 5 % less than the default to replace it

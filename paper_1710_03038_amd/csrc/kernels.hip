@@ -281,8 +281,10 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
   int o[2];
   bool act[2], inner[2];
   P phi[2], hx[2], hy[2], u[2], rr[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  // A site's reads (gather) and its update and writes (finish).  FP32
+  // interleaves the two sites' steps; FP64 finishes the first site before
+  // the second one's reads, which halves the live FP64 temporaries.
+  auto gather = [&](const int k) __attribute__((always_inline)) {
     const int x = lx + 2 * k;
     const int ring = max(max(U.ix0 - x, x - U.ix1), 0) + ry;
     const bool geo = ring <= U.D && x <= U.ex1;
@@ -322,10 +324,9 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
     }
     u[k] = unit<P>(w[2 * k]);
     rr[k] = unit<P>(w[2 * k + 1]);
-  }
+  };
   uint32_t acc = 0;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  auto finish = [&](const int k) __attribute__((always_inline)) {
     P p1 = phi[k], p2, dH;
     if constexpr (GMRF) {
       const P sum = hx[k], n = hy[k];
@@ -367,6 +368,17 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
       }
     }
     acc += (act[k] && ok && inner[k]) ? 1u : 0u;
+  };
+  if constexpr (sizeof(P) == 4) {
+    gather(0);
+    gather(1);
+    finish(0);
+    finish(1);
+  } else {
+    gather(0);
+    finish(0);
+    gather(1);
+    finish(1);
   }
   return acc;
 }
