@@ -358,18 +358,24 @@ int64_t resident_blocks1(mpr_ctx *c, int thr, size_t lds) {
   return it->second;
 }
 
-template <typename P> int64_t persistent_blocks(mpr_ctx *c, const SweepArgs<P> &A, size_t lds) {
-  if (!c->persist1) return 0;
-  const int thr = c->threads1;
-  if ((int64_t)A.lds_w * A.lds_h > (int64_t)thr * p1_sites(thr)) return 0;
-  const int D0 = A.energy ? 2 : 1;  // reach of the colour-0 half-sweep, in rings
+// Workgroups of k_sweep1 for a one-sweep pass of `thr` threads over this
+// LDS extent, or 0 where a thread's registers cannot hold an item (or no
+// persistent kernel exists for that size).
+int64_t persistent_fit(mpr_ctx *c, int thr, int lds_w, int lds_h, bool energy, size_t lds) {
+  if ((int64_t)lds_w * lds_h > (int64_t)thr * p1_sites(thr)) return 0;
+  const int D0 = energy ? 2 : 1;  // reach of the colour-0 half-sweep, in rings
   // plan pairs of colour 0 within that reach, at most: per row, those whose
   // first site lies in [x0 - D0 - 2, ix1 + D0), one in every 4 columns
-  const int64_t reach = (int64_t)(A.tile_y + 2 * D0) * ((A.tile_x + 2 * D0) / 4 + 2);
+  const int64_t reach = (int64_t)(c->plan.tile_y + 2 * D0) * ((c->plan.tile_x + 2 * D0) / 4 + 2);
   if (reach > (int64_t)thr * p1_plan(thr)) return 0;
   const int64_t res = resident_blocks1(c, thr, lds);
   if (res < 8) return 0;  // also: no persistent kernel for this workgroup size
   return std::min<int64_t>(res, (c->plan.n_items + 7) / 8 * 8);
+}
+
+template <typename P> int64_t persistent_blocks(mpr_ctx *c, const SweepArgs<P> &A, size_t lds) {
+  if (!c->persist1) return 0;
+  return persistent_fit(c, c->threads1, A.lds_w, A.lds_h, A.energy != nullptr, lds);
 }
 
 template <typename P>
@@ -1366,8 +1372,9 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
       ctx->threads1 = thr;
       ctx->nsw_run = nsw;
       // Single-sweep passes (the a-rule's) are timed on both kernels: one
-      // workgroup per item, and persistent workgroups.
-      for (int pv = 0; pv < (nsw == 1 ? 2 : 1) && st == MPR_OK; ++pv) {
+      // workgroup per item, and persistent workgroups where they run.
+      const bool p1_runs = nsw == 1 && persistent_fit(ctx, thr, w, h, false, lds) > 0;
+      for (int pv = 0; pv < (p1_runs ? 2 : 1) && st == MPR_OK; ++pv) {
         ctx->persist1 = pv == 1;
         int64_t n = ((trial_sweeps + nsw - 1) / nsw) * nsw;
         st = run_sweeps(ctx, nsw, false, false, nullptr, 0);  // warm-up pass
