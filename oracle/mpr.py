@@ -68,11 +68,11 @@ over-relaxation reflects phi about the mean of its neighbours, kept only
 inside [0, 2 pi), and everything else is unchanged.
 
 Random stream (a definition of this project): key = (seed mod 2^32,
-seed >> 32).  The sites of one colour in a row come in pairs (x, x + 2)
-with x mod 4 in {0, 1}; one call with counter (pair, sweep, chain, grid),
-pair = y * nx + (x with bit 1 cleared), serves both sites of a pair in one
-sweep: words (w0 -> u, w1 -> r) to the pair's first site, (w2 -> u,
-w3 -> r) to its second.  The hot start uses counter (site, 0xFFFFFFFF,
+seed >> 32).  The sites of one colour in a column come in pairs
+(y, y + 2) with y mod 4 in {0, 1}; one call with counter (pair, sweep,
+chain, grid), pair = (y with bit 1 cleared) * nx + x, serves both sites of
+a pair in one sweep: words (w0 -> u, w1 -> r) to the pair's first site,
+(w2 -> u, w3 -> r) to its second.  The hot start uses counter (site, 0xFFFFFFFF,
 chain, grid) with site = y * nx + x (the sweep word never reaches
 0xFFFFFFFF) and the u word w0.
 """
@@ -124,9 +124,9 @@ def site_uniforms(seed, ny, nx, sweep, chains, grid, origin=(0, 0), gnx=None):
         site = ((y * gnx + x) % (1 << 32)).astype(np.uint64)
         w0, w1, _, _ = philox4x32(site, HOT_START_SWEEP, chains, grid, k0, k1)
         return unit_float(w0), unit_float(w1)
-    # x & ~2: the pair's first site (two's complement, also left of the grid)
-    pair = ((y * gnx + (x & ~2)) % (1 << 32)).astype(np.uint64)
-    second = ((x >> 1) & 1).astype(bool)
+    # y & ~2: the pair's first site (two's complement, also above the grid)
+    pair = (((y & ~2) * gnx + x) % (1 << 32)).astype(np.uint64)
+    second = np.broadcast_to(((y >> 1) & 1).astype(bool), pair.shape)
     w0, w1, w2, w3 = philox4x32(pair, sweep, chains, grid, k0, k1)
     return unit_float(np.where(second, w2, w0)), unit_float(np.where(second, w3, w1))
 
@@ -382,8 +382,8 @@ def hybrid_sweep_literal(phi, known, beta, alpha, q, seed, sweep, chain, grid, o
             for x in range(nx):
                 if (x + y) % 2 != colour or known[y][x]:
                     continue
-                w = philox4x32(y * nx + (x & ~2), sweep, chain, grid, k0, k1)
-                wu, wr = (w[2], w[3]) if (x >> 1) & 1 else (w[0], w[1])
+                w = philox4x32((y & ~2) * nx + x, sweep, chain, grid, k0, k1)
+                wu, wr = (w[2], w[3]) if (y >> 1) & 1 else (w[0], w[1])
                 u = float(unit_float(wu))
                 r = float(unit_float(wr))
                 cur = phi[y][x]

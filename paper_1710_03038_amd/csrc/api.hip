@@ -295,9 +295,10 @@ void lds_extent(const Plan &pl, int nsw, bool energy, int &w, int &h, size_t &by
     h = std::max(h, std::min(pl.tile_y + 2 * H, d.ny + 2));
   }
   w = (w + 1) & ~1;
-  // angle + (cos, sin) of both colours, and the staged plan pairs (per LDS
-  // row and colour at most w / 4 + 2 of them, 2 bytes each)
-  bytes = (size_t)w * h * 3 * pl.elem + (size_t)h * (w + 8);
+  // angle + (cos, sin) of both colours, and the staged plan pairs: their
+  // first sites lie in rows [oy - 2, oy + h), two rows in every four, so at
+  // most w (h + 4) / 2 pairs of 2 bytes
+  bytes = (size_t)w * h * 3 * pl.elem + (size_t)w * (h + 4);
 }
 
 void lds_extent(const mpr_ctx *c, int nsw, bool energy, int &w, int &h, size_t &bytes) {
@@ -364,9 +365,10 @@ int64_t resident_blocks1(mpr_ctx *c, int thr, size_t lds) {
 int64_t persistent_fit(mpr_ctx *c, int thr, int lds_w, int lds_h, bool energy, size_t lds) {
   if ((int64_t)lds_w * lds_h > (int64_t)thr * p1_sites(thr)) return 0;
   const int D0 = energy ? 2 : 1;  // reach of the colour-0 half-sweep, in rings
-  // plan pairs of colour 0 within that reach, at most: per row, those whose
-  // first site lies in [x0 - D0 - 2, ix1 + D0), one in every 4 columns
-  const int64_t reach = (int64_t)(c->plan.tile_y + 2 * D0) * ((c->plan.tile_x + 2 * D0) / 4 + 2);
+  // plan pairs of colour 0 within that reach, at most: their first sites
+  // lie in rows [y0 - D0 - 2, iy1 + D0), two rows in every four, with one
+  // site of the colour in every 2 columns of [x0 - D0, ix1 + D0)
+  const int64_t reach = (int64_t)((c->plan.tile_y + 2 * D0) / 2 + 2) * ((c->plan.tile_x + 2 * D0) / 2 + 1);
   if (reach > (int64_t)thr * p1_plan(thr)) return 0;
   const int64_t res = resident_blocks1(c, thr, lds);
   if (res < 8) return 0;  // also: no persistent kernel for this workgroup size

@@ -80,7 +80,7 @@ struct SweepArgs {
   uint32_t *counts_clear;          // buffer of the pass after next, cleared by tile 0
   P *acc_ref, *acc_s1, *acc_s2;    // fill accumulators (state layout)
   // Gap-site plan (k_plan): per tile, the pairs of same-colour sites
-  // (x, x + 2) in a row, x mod 4 in {0, 1}, that hold a gap site within
+  // (y, y + 2) in a column, y mod 4 in {0, 1}, that hold a gap site within
   // ring distance plan_dmax of the interior, colour 0 then colour 1, each
   // sorted by ring (a pair's ring: the least Manhattan distance from the
   // interior rectangle of its gap sites within plan_dmax); entry =
@@ -101,8 +101,8 @@ constexpr int kItemStride = 256;
 
 // Entries of the gap-site plan are packed into 16 bits with an offset of 34
 // around the tile origin (a pair's first site lies up to plan_dmax + 2
-// columns left of the tile); with plan_dmax <= 32 this bounds the tile to
-// 188 sites (188 - 1 + 32 + 34 <= 255).
+// rows above the tile); with plan_dmax <= 32 this bounds the tile to 188
+// sites (188 - 1 + 32 + 34 <= 255).
 constexpr int kPlanOffset = 34;
 constexpr int kMaxTile = 188;
 

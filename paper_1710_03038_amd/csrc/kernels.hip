@@ -16,8 +16,8 @@
 // other buffer of a ping-pong pair.  Sites of the halo are updated
 // redundantly by neighbouring tiles with identical arithmetic and random
 // numbers, so results do not depend on the tiling.  One Philox4x32-10 call
-// per sweep serves a pair of same-colour sites (x, x + 2) of a row,
-// x mod 4 in {0, 1}: counter (first site, sweep, chain, grid).
+// per sweep serves a pair of same-colour sites (y, y + 2) of a column,
+// y mod 4 in {0, 1}: counter (first site, sweep, chain, grid).
 #include "internal.h"
 
 #include <algorithm>
@@ -254,7 +254,7 @@ __device__ __forceinline__ int aux_count(const UpdateCtx<P> &U, int ly, int lx) 
 }
 
 // Algorithm 1 for one plan entry: a pair of sites of this colour in one
-// row, the first at LDS (ly, lx) and the second at (ly, lx + 2), whose
+// column, the first at LDS (ly, lx) and the second at (ly + 2, lx), whose
 // random words come from one Philox call keyed by (first site, sweep,
 // chain, grid): (w0, w1) are the first site's (u, r), (w2, w3) the
 // second's.  A site takes part if it lies in the grid, within the
@@ -275,7 +275,7 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
   const P q = U.q;
   const int ly = (int)(e >> 8) + U.Ly, lx = (int)(e & 255u) + U.Lx;
   const int par = lx & 1;  // the parity of both sites' x
-  const int ry = max(max(U.iy0 - ly, ly - U.iy1), 0);
+  const int rx = max(max(U.ix0 - lx, lx - U.ix1), 0);
   uint32_t w[4];
   philox4x32_10(U.sbase + (uint32_t)(ly * U.gnx + lx), U.sweep, U.cid, U.gid, U.k0, U.k1, w);
   int o[2];
@@ -284,13 +284,15 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
   // A site's reads (gather) and its update and writes (finish).  FP32
   // interleaves the two sites' steps; FP64 finishes the first site before
   // the second one's reads, which halves the live FP64 temporaries.
+  // Neighbouring lanes hold neighbouring pairs of a row: their reads are
+  // consecutive in both colour planes.
   auto gather = [&](const int k) __attribute__((always_inline)) {
-    const int x = lx + 2 * k;
-    const int ring = max(max(U.ix0 - x, x - U.ix1), 0) + ry;
-    const bool geo = ring <= U.D && x <= U.ex1;
+    const int y = ly + 2 * k;
+    const int ring = rx + max(max(U.iy0 - y, y - U.iy1), 0);
+    const bool geo = ring <= U.D && y <= U.ey1;
     inner[k] = ring == 0;
     // (LDS row 1, pair 1: every neighbour of it lies in the LDS)
-    o[k] = geo ? ly * U.P2 + (x >> 1) : U.P2 + 1;
+    o[k] = geo ? y * U.P2 + (lx >> 1) : U.P2 + 1;
     phi[k] = U.pc[o[k]];
     act[k] = geo && !signbit(phi[k]);
     if constexpr (GMRF) {
@@ -303,7 +305,7 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
         n += in ? P(1) : P(0);
       }
       if constexpr (REP) {
-        const P g = (P)aux_count(U, ly, x);
+        const P g = (P)aux_count(U, y, lx);
         sum = fma(g, phi[k], sum);
         n += g;
       }
@@ -316,7 +318,7 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
       hy[k] = nl.y + nr.y + nu.y + nd.y;
       if constexpr (REP) {
         // off-grid neighbours read (0, 0); each auxiliary one adds the site's own (cos, sin)
-        const P g = (P)aux_count(U, ly, x);
+        const P g = (P)aux_count(U, y, lx);
         const V2 own = U.cc[o[k]];
         hx[k] = fma(g, own.x, hx[k]);
         hy[k] = fma(g, own.y, hy[k]);
@@ -1089,7 +1091,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
 
 // ------------------------------------------------------------------- plan
 // One workgroup per (grid, tile): list the pairs of same-colour sites
-// (x, x + 2) of a row, x mod 4 in {0, 1}, that hold a gap site within
+// (y, y + 2) of a column, y mod 4 in {0, 1}, that hold a gap site within
 // Manhattan distance dmax of the tile's interior, colour 0 first, each
 // colour sorted by the pair's distance (the least over its gap sites within
 // dmax) and, within one distance, in the row-major order of the pair's
@@ -1122,7 +1124,7 @@ __global__ void __launch_bounds__(kThreads)
   // A site of the scanned rectangle that the plan covers: a gap site
   // within distance dmax (its distance in ring).
   auto covered = [&](int gx, int gy, int &ring) {
-    if (gx < rx0 || gx >= rx1) return false;
+    if (gx < rx0 || gx >= rx1 || gy < ry0 || gy >= ry1) return false;
     if (signbit(st[(int64_t)gy * nx + gx])) return false;
     ring = max(max(x0 - gx, gx - (ix1 - 1)), 0) + max(max(y0 - gy, gy - (iy1 - 1)), 0);
     return ring <= dmax;
@@ -1135,13 +1137,13 @@ __global__ void __launch_bounds__(kThreads)
     const int gx = rx0 + cx, gy = ry0 + r;
     int ring, other;
     if (!covered(gx, gy, ring)) return -1;
-    const int b = gx & ~2;  // the pair's first site
-    if (gx != b) {
-      if (covered(b, gy, other)) return -1;  // listed from the first site
-    } else if (covered(b + 2, gy, other)) {
+    const int b = gy & ~2;  // the row of the pair's first site
+    if (gy != b) {
+      if (covered(gx, b, other)) return -1;  // listed from the first site
+    } else if (covered(gx, b + 2, other)) {
       ring = min(ring, other);
     }
-    entry = (uint16_t)(((gy - y0 + kPlanOffset) << 8) | (b - x0 + kPlanOffset));
+    entry = (uint16_t)(((b - y0 + kPlanOffset) << 8) | (gx - x0 + kPlanOffset));
     return ((gx + gy) & 1) * (dmax + 2) + ring;
   };
   for (int i = threadIdx.x; i < kBuckets; i += kThreads) {

@@ -412,8 +412,8 @@ def test_site_words_distinct_across_sites_and_sweeps():
                            for u, r in draws])
     assert len(np.unique(keys)) == keys.size
     u0 = draws[0][0][0]
-    first = u0[:, 0::4].ravel()
-    second = u0[:, 2::4].ravel()
+    first = u0[0::4, :].ravel()
+    second = u0[2::4, :].ravel()
     assert abs(np.corrcoef(first, second)[0, 1]) < 0.1
     assert abs(np.corrcoef(draws[0][0].ravel(), draws[1][0].ravel())[0, 1]) < 0.1
     assert abs(u0.mean() - 0.5) < 0.03
