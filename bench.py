@@ -768,6 +768,10 @@ def main():
                      "hbm_achieved_GBps": hbm_gbs, "hbm_peak_GBps": HBM_PEAK_GBS,
                      "hbm_frac": hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
                      "hbm_measured_GBps": traffic / (avg_us * 1e-6) / 1e9 if traffic and avg_us else None,
+                     "hbm_measured_frac": traffic / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS if traffic and avg_us else None,
+                     "hbm_note": "hbm_frac: one-pass algorithmic bytes per launch over its time (effective bandwidth); "
+                                 "hbm_measured_*: profiled FETCH_SIZE + WRITE_SIZE bytes per launch over the same time",
+
                      "hbm_algorithmic_bytes_per_launch": alg_bytes, "bytes_per_site_sweep": b_site,
                      "issue_cycles_per_update": cyc, "avg_launch_us": avg_us, "launches": kl,
                      "site_sweeps_per_launch": kss / kl if kl else None},

@@ -756,11 +756,10 @@ def test_extreme_shapes(shape, dtype, nsw):
 
 @pytest.mark.parametrize("dtype,nsw", [("fp32", 8), ("fp64", 4)])
 def test_fused_pass_equals_single_sweeps_dense_gaps(dtype, nsw):
-    # 95 % gaps: a colour of a 64 x 64 tile has more plan entries than two
-    # per thread, so within one pass some items reuse the previous sweep's
-    # random words and the rest draw their own; the result must equal
-    # single-sweep passes (which draw every word) bit for bit, from an even
-    # and from an odd first sweep
+    # 95 % gaps: a colour of a 64 x 64 tile has several plan pairs per
+    # thread and pairs straddle the shrinking reach of a fused pass; the
+    # result must equal single-sweep passes bit for bit, from an even and
+    # from an odd first sweep
     rng = np.random.default_rng(17)
     z = rng.normal(50.0, 10.0, (200, 190))
     known = (rng.random(z.shape) < 0.05).astype(np.uint8)
