@@ -465,47 +465,68 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   // (lx + ly + par0) & 1.
   const int par0 = (ox + oy) & 1;
   {
-    // One batch covers a 64 x 64 tile's sites and one-sweep plan at 512
-    // threads or more.
-    constexpr int kStage = 16, kPlanStage = NT >= 512 ? 5 : 8;
-    const int n_lds = W * A.lds_h;
-    const float invw = 1.0f / (float)W;
+    // Sites are staged two at a time: LDS sites (ly, 2j) and (ly, 2j + 1),
+    // one of each colour, both at index ly * P2 + j of their colour's
+    // planes.  The colour-1 site's (cos, sin) is always needed, so every
+    // lane computes one; the colour-0 site's only for a sample, an off-grid
+    // site or at the replicate boundary (see below), which most waves skip
+    // as a whole.  One batch covers a 64 x 64 tile's sites and one-sweep
+    // plan at 512 threads or more.
+    constexpr int kStage = 8, kPlanStage = NT >= 512 ? 5 : 8;
+    using Pair = typename Prec<P>::V2;  // two consecutive angles
+    const int n_slots = P2 * A.lds_h;
+    const float invp = 1.0f / (float)P2;
     const uint16_t *pl = A.plan + G.plan_ebase + (int64_t)t * G.plan_cap;
     const uint32_t n_all = na + nb;
-    // Thread i stages LDS sites i, i + NT, ... in row-major order: its
-    // (ly, lx) moves by (NT / W, NT % W) per site, with a carry.  The
-    // in-grid part of the LDS rectangle is [ax, ax + aw) x [ay, ay + ah);
-    // the chain's angle of LDS site (ly, lx) is src[ib + ly * nx + lx],
-    // an index below 2^32 for every in-grid site.
-    const int dly = NT / W, dlx = NT - (NT / W) * W;
-    int sly, slx;
-    split_index((int)threadIdx.x, W, invw, sly, slx);
+    // Thread i stages slots i, i + NT, ... in row-major order: its (ly, j)
+    // moves by (NT / P2, NT % P2) per slot, with a carry.  The in-grid part
+    // of the LDS rectangle is [ax, ax + aw) x [ay, ay + ah); the chain's
+    // angle of LDS site (ly, lx) is src[ib + ly * nx + lx], an index below
+    // 2^32 for every in-grid site.  When nx and the chain's first index are
+    // even, both angles of a slot come in one 2-element load (ox is even).
+    const int dly = NT / P2, dlj = NT - (NT / P2) * P2;
+    int sly, sj;
+    split_index((int)threadIdx.x, P2, invp, sly, sj);
     const int ax = lxs - ox, aw = lxe - lxs, ay = lys - oy, ah = lye - lys;
     const uint32_t ib = (uint32_t)((int64_t)oy * nx + ox);
-    for (int base = 0, pb = 0; base < n_lds || pb < (int)n_all; base += NT * kStage, pb += NT * kPlanStage) {
+    const bool wide = ((nx | (int)(cbase & 1)) & 1) == 0;
+    for (int base = 0, pb = 0; base < n_slots || pb < (int)n_all; base += NT * kStage, pb += NT * kPlanStage) {
       // Slots wholly past the end (a workgroup-uniform test) issue nothing.
       // The angles load first: their addresses do not wait for the counts.
-      P v[kStage];
-      int o[kStage];
-      bool in[kStage];
+      P va[kStage], vb[kStage];
+      int jj[kStage], ca[kStage];
+      bool ina[kStage], inb[kStage];
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
-        o[k] = -1;  // every slot, also those past the loop's break below
-        in[k] = false;
-        v[k] = P(0);
+        jj[k] = -1;  // every slot, also those past the loop's break below
+        ca[k] = 0;
+        ina[k] = inb[k] = false;
+        va[k] = vb[k] = P(0);
       }
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
-        if (base + k * NT >= n_lds) break;
+        if (base + k * NT >= n_slots) break;
         if (sly < A.lds_h) {
-          o[k] = ((slx + sly + par0) & 1) * plane + sly * P2 + (slx >> 1);
-          in[k] = (uint32_t)(slx - ax) < (uint32_t)aw && (uint32_t)(sly - ay) < (uint32_t)ah;
-          if (in[k]) v[k] = src[ib + (uint32_t)(sly * nx + slx)];
+          const int slx = 2 * sj;
+          jj[k] = sly * P2 + sj;
+          ca[k] = (sly + par0) & 1;  // colour of the slot's first site
+          const bool iny = (uint32_t)(sly - ay) < (uint32_t)ah;
+          ina[k] = iny && (uint32_t)(slx - ax) < (uint32_t)aw;
+          inb[k] = iny && (uint32_t)(slx + 1 - ax) < (uint32_t)aw;
+          const uint32_t i0 = ib + (uint32_t)(sly * nx + slx);
+          if (wide && ina[k] && inb[k]) {
+            const Pair two = *reinterpret_cast<const Pair *>(src + i0);
+            va[k] = two.x;
+            vb[k] = two.y;
+          } else {
+            if (ina[k]) va[k] = src[i0];
+            if (inb[k]) vb[k] = src[i0 + 1];
+          }
         }
-        slx += dlx;
+        sj += dlj;
         sly += dly;
-        if (slx >= W) {
-          slx -= W;
+        if (sj >= P2) {
+          sj -= P2;
           ++sly;
         }
       }
@@ -518,26 +539,37 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       }
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
-        if (o[k] < 0) continue;
+        if (jj[k] < 0) continue;
+        // the slot's colour-0 and colour-1 sites
+        const bool in0 = ca[k] ? inb[k] : ina[k], in1 = ca[k] ? ina[k] : inb[k];
+        const P v0 = ca[k] ? vb[k] : va[k], v1 = ca[k] ? va[k] : vb[k];
+        const int j = jj[k];
         if constexpr (MODEL == kGmrf) {
           // angles only; NaN marks a site outside the grid or the halo
-          ph[o[k]] = in[k] ? v[k] : P(__builtin_nan(""));
+          ph[j] = in0 ? v0 : P(__builtin_nan(""));
+          ph[plane + j] = in1 ? v1 : P(__builtin_nan(""));
         } else {
+          const P a0 = in0 ? v0 : -P(0), a1 = in1 ? v1 : -P(0);
+          {
+            P s_, c_;
+            if (QONE) Prec<P>::sincos_(q * fabs(a1), &s_, &c_);
+            else Prec<P>::sincos_0pi_(q * fabs(a1), &s_, &c_);
+            cs[plane + j] = in1 ? V2{c_, s_} : V2{P(0), P(0)};
+          }
           // (cos, sin) of colour-0 gap sites is never read before the
           // pass's first half-sweep recomputes it (every colour-0 gap site
           // a colour-1 update reads lies in that half-sweep's reach), except
           // for a site's own value at the replicate boundary.
-          const P val = in[k] ? v[k] : -P(0);
-          const bool need = !in[k] || REP || o[k] >= plane || signbit(val);
-          if (need) {
+          if (!in0 || REP || signbit(a0)) {
             P s_ = P(0), c_ = P(0);
-            if (in[k]) {
-              if (QONE) Prec<P>::sincos_(q * fabs(val), &s_, &c_);
-              else Prec<P>::sincos_0pi_(q * fabs(val), &s_, &c_);
+            if (in0) {
+              if (QONE) Prec<P>::sincos_(q * fabs(a0), &s_, &c_);
+              else Prec<P>::sincos_0pi_(q * fabs(a0), &s_, &c_);
             }
-            cs[o[k]] = V2{c_, s_};
+            cs[j] = V2{c_, s_};
           }
-          ph[o[k]] = val;
+          ph[j] = a0;
+          ph[plane + j] = a1;
         }
       }
 #pragma unroll
