@@ -390,9 +390,11 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
 // nearest-neighbour dependencies.  Half-sweep hs of the pass updates the
 // colour-(hs & 1) gap sites within distance D = 2*nsw - 1 - hs: each reads
 // neighbours within D + 1, exact after half-sweep hs - 1 (the staged halo of
-// 2*nsw + 1 sites covers hs = 0), so the interior is exact after the last
-// half-sweep.  When the energy of interior pairs is traced, every D is one
-// larger, so that the interior plus one ring is exact after each sweep.
+// 2*nsw sites covers hs = 0), so the interior is exact after the last
+// half-sweep.  When the energy of interior pairs is traced, every D and the
+// halo are one larger, so that the interior plus one ring is exact after
+// each sweep.  The gap sites come from the tile's plan as pairs (one Philox
+// call each): thread i updates pairs i, i + NT, ... of a half-sweep.
 // With RREG (an FP32 pass that records two or more sweeps), the fill sums of
 // a thread's first interior sites stay in registers for the whole pass:
 // loaded before the first record and stored after the last, instead of a
@@ -448,12 +450,13 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   const int cstride = A.plan_dmax + 2;
   const uint32_t n0_all = cum[A.plan_dmax + 1];
   const uint32_t na = cum[2 * A.nsw + 1], nb = cum[cstride + 2 * A.nsw];
-  // Stage the tile, its halo and a frozen zero ring around them, and this
-  // pass's part of the tile's gap-site plan: colour-0 entries within
-  // distance 2*nsw, then colour-1 entries within distance 2*nsw - 1.  Each
-  // thread issues the loads of up to kStage sites and kPlanStage plan
-  // entries before it waits for any, so the staging costs one memory
-  // latency per batch (one batch for the library's default shapes).
+  // Stage the tile, its halo (with a frozen zero row or column where a grid
+  // edge lies within it), and this pass's part of the tile's plan:
+  // colour-0 pairs within distance 2*nsw, then colour-1 pairs within
+  // distance 2*nsw - 1.  Each thread issues the loads of up to kStage site
+  // slots and kPlanStage plan pairs before it waits for any, so the staging
+  // costs one memory latency per batch (one batch for the library's
+  // default shapes).
   if (threadIdx.x < kMaxPass) acc_lds[threadIdx.x] = 0u;
   const int gchain = G.chain_base + chain;
   // Close the previous pass (every tile derives the same a; tile 0 records):
