@@ -103,9 +103,11 @@ typedef struct {
   int32_t dtype;          /* mpr_dtype of the sweeps' arithmetic and the stored angles */
   int32_t sweeps_per_pass;/* sweeps fused per HBM pass, 1..16; 0 = library choice */
   int32_t tile_x, tile_y; /* interior tile of one workgroup (even, 8..188); 0 = library choice */
-  uint64_t seed;          /* Philox4x32-10 key: (seed mod 2^32, seed >> 32); counter (site y*nx + x,
-                             sweep >> 1, chain, grid), words (w0, w1) in even sweeps, (w2, w3) in
-                             odd ones; the hot start uses 0xFFFFFFFF for sweep >> 1 and w0 */
+  uint64_t seed;          /* Philox4x32-10 key: (seed mod 2^32, seed >> 32).  Same-colour sites
+                             (x, y) and (x, y + 2) with y mod 4 in {0, 1} share one call per sweep:
+                             counter (y*nx + x, sweep, chain, grid), words (w0, w1) -> (u, r) of the
+                             first site, (w2, w3) of the second; the hot start uses counter
+                             (y*nx + x, 0xFFFFFFFF, chain, grid) and w0 */
   int32_t model;          /* pair interaction: MPR_MODEL_MPR (Eq. 3) or MPR_MODEL_GMRF (Sec. 4.4) */
   int32_t boundary;       /* mpr_boundary: MPR_BC_OPEN (default) or MPR_BC_REPLICATE */
 } mpr_params;
