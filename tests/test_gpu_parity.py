@@ -73,8 +73,9 @@ def test_specific_energies(dtype):
 CASES = [(0.3, 1.0), (0.02, 5.0), (1e-3, 40.0), (math.inf, 1.0), (0.0, 3.0)]
 
 
-def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, model="mpr", boundary="open"):
-    grids = _grids(21)
+def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, model="mpr", boundary="open",
+                    grids=None):
+    grids = _grids(21) if grids is None else grids
     om_model = om.GMRF if model == "gmrf" else om.MPR
     f = make_field(grids, dtype=dtype, seed=seed, tile_x=tile[0], tile_y=tile[1], sweeps_per_pass=nsw, model=model,
                    boundary=boundary)
@@ -138,6 +139,29 @@ def test_teacher_forced_sweep_fp32(tile, nsw):
             n_bad = int(((np.abs(got - ref) > 1e-3) & ~known.astype(bool)).sum())
         total_bad += n_bad
         total_gap += int((~known.astype(bool)).sum())
+    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_teacher_forced_sweep_odd_chain_offsets(dtype):
+    # Grids of even width whose chains start at odd element offsets in the
+    # state buffer (after a 3 x 5 one-chain grid): the staging takes its
+    # two-site loads one site at a time there, and must agree with the
+    # oracle as everywhere else
+    shapes = [((3, 5), 1), ((40, 36), 2), ((33, 64), 1), ((64, 64), 1)]
+    grids = []
+    for k, ((ny, nx), chains) in enumerate(shapes):
+        z, known = random_grid(ny, nx, 0.4, 300 + 10 * k, smooth=True)
+        grids.append((z, known, chains))
+    total_gap = total_bad = 0
+    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced(dtype, (32, 32), 1, grids=grids):
+        if dtype == "fp64":
+            assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
+        else:
+            n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+            assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
+            total_bad += n_bad
+            total_gap += int((~known.astype(bool)).sum())
     assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
 
 
