@@ -59,21 +59,59 @@ def beta_of(T):
     return 0.0 if T == math.inf else (math.inf if T == 0 else 1.0 / T)
 
 
-def explained_mismatches(phi_gpu, phi_ref, margins, known, tol, thr=1e-4):
-    """Sites with |gpu - ref| > tol, split into those explained by a
-    rounding-sensitive decision (near a threshold, or a colour-1 site next to
-    a mismatched colour-0 site) and the unexplained rest."""
-    diff = np.abs(phi_gpu - phi_ref)
-    bad = (diff > tol) & ~known.astype(bool)
-    ny, nx = bad.shape
-    yy, xx = np.mgrid[0:ny, 0:nx]
-    near = (margins["accept"] < thr) | (margins["or_edge"] < thr) | (margins["wrap"] < thr)
-    expl = bad & near
-    c0bad = bad & (((xx + yy) % 2) == 0)
-    nb = np.zeros_like(bad)
-    nb[:, 1:] |= c0bad[:, :-1]
-    nb[:, :-1] |= c0bad[:, 1:]
-    nb[1:, :] |= c0bad[:-1, :]
-    nb[:-1, :] |= c0bad[1:, :]
-    expl |= bad & (((xx + yy) % 2) == 1) & nb
-    return int(bad.sum()), int(expl.sum()), np.argwhere(bad & ~expl)
+def chain_margins(margins, c):
+    """Chain c's decision margins, from the oracle's (chains, ny, nx) arrays."""
+    return {k: v[c] for k, v in margins.items()}
+
+
+def explainable(sweep_margins, origin=(0, 0), thr=1e-4):
+    """Sites that a rounding-sensitive decision may set apart after a pass.
+
+    sweep_margins: one chain's 2-D decision margins (the oracle's
+    hybrid_sweep margins) of each sweep of the pass, in order; origin: grid
+    coordinates of the frame's (0, 0), which fix the sites' colours.  A
+    decision within thr of its threshold (accept, over-relaxation range
+    edge, wrap) in half-sweep h = 2 s + colour may come out the other way
+    in FP32; it changes its own site, and through the pass's later
+    half-sweeps sites up to 2 nsw - 1 - h steps away (Manhattan distance).
+    With one sweep: the site itself, and for a colour-0 site its colour-1
+    neighbours."""
+    nsw = len(sweep_margins)
+    shape = sweep_margins[0]["accept"].shape
+    assert len(shape) == 2, "pass one chain's margins"
+    yy, xx = np.mgrid[0:shape[0], 0:shape[1]]
+    colour = (yy + xx + origin[0] + origin[1]) % 2
+    expl = np.zeros(shape, dtype=bool)
+    for s, m in enumerate(sweep_margins):
+        near = (m["accept"] < thr) | (m["or_edge"] < thr) | (m["wrap"] < thr)
+        for c in (0, 1):
+            reach = near & (colour == c)
+            for _ in range(2 * nsw - 1 - (2 * s + c)):
+                grow = reach.copy()
+                grow[1:, :] |= reach[:-1, :]
+                grow[:-1, :] |= reach[1:, :]
+                grow[:, 1:] |= reach[:, :-1]
+                grow[:, :-1] |= reach[:, 1:]
+                reach = grow
+            expl |= reach
+    return expl
+
+
+def mismatches(phi_gpu, phi_ref, expl, known, tol):
+    """Gap sites with |gpu - ref| > tol: (count, count explained by the
+    explainable() mask expl, indices of the unexplained ones)."""
+    bad = (np.abs(phi_gpu - phi_ref) > tol) & ~np.asarray(known).astype(bool)
+    assert expl.shape == bad.shape
+    return int(bad.sum()), int((bad & expl).sum()), np.argwhere(bad & ~expl)
+
+
+def fp32_cap(n_gap):
+    """Most gap sites an FP32 comparison may find beyond 1e-3 rad of the
+    oracle: 0.01 % (at least 99.99 % within), or one site in small cases;
+    each of them must also be explained (see mismatches)."""
+    return max(1.0, 1e-4 * n_gap)
+
+
+def explained_mismatches(phi_gpu, phi_ref, margins, known, tol, thr=1e-4, origin=(0, 0)):
+    """mismatches() after one sweep, from that sweep's 2-D margins."""
+    return mismatches(phi_gpu, phi_ref, explainable([margins], origin, thr), known, tol)

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import mpr as om
-from tests.gpu_util import TWO_PI, as_fp32_state, beta_of, explained_mismatches, make_field
+from tests.gpu_util import TWO_PI, as_fp32_state, beta_of, chain_margins, explainable, fp32_cap, make_field, mismatches
 
 pytestmark = pytest.mark.gpu
 
@@ -35,12 +35,17 @@ def _oracle_window(z, known, bounds, seed, chain, grid, T, a, sweep0, nsw, win, 
     phi = om.hot_start(ws, kw, seed, [chain], grid, origin=(ey0, ex0), gnx=nx)
     if dtype == "fp32":
         phi = as_fp32_state(phi[0], kw)[None]
-    margins = {}
+    sweep_margins = []
     for s in range(nsw):
+        margins = {}
         phi, _ = om.hybrid_sweep(phi, kw, [beta_of(T)], [TWO_PI / a], 0.5, seed, sweep0 + s, [chain], grid,
                                  margins=margins, origin=(ey0, ex0), gnx=nx)
+        sweep_margins.append(chain_margins(margins, 0))
     cut = (slice(y0 - ey0, y1 - ey0), slice(x0 - ex0, x1 - ex0))
-    return phi[0][cut], {k: v[0][cut] for k, v in margins.items()}, kw[cut]
+    # sites a near-threshold decision of the pass may set apart, found on the
+    # extended window (a decision in its margin reaches into the cut)
+    expl = explainable(sweep_margins, origin=(ey0, ex0))
+    return phi[0][cut], expl[cut], kw[cut]
 
 
 def _check_workload(name, chains_checked, dtype, nsw, T=None, a=2.0, sweep0=3, shape=None):
@@ -65,18 +70,18 @@ def _check_workload(name, chains_checked, dtype, nsw, T=None, a=2.0, sweep0=3, s
     for c in chains_checked:
         got_full = f.get_phi(0, c).cpu().numpy()
         for win in _windows(ny, nx):
-            ref, margins, kw = _oracle_window(z, known, bounds, spec["seed"], c, 0, T, a, sweep0, nsw, win, dtype)
+            ref, expl, kw = _oracle_window(z, known, bounds, spec["seed"], c, 0, T, a, sweep0, nsw, win, dtype)
             got = got_full[win[0]:win[1], win[2]:win[3]]
             if dtype == "fp64":
                 d = float(np.abs(got - ref).max())
                 assert d <= 1e-5, (name, c, win, d)
             else:
-                n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, kw, 1e-3)
+                n_bad, n_expl, unexpl = mismatches(got, ref, expl, kw, 1e-3)
                 assert len(unexpl) == 0, (name, c, win, unexpl[:4])
                 total_bad += n_bad
                 total_gap += int((~kw).sum())
     if dtype == "fp32":
-        assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+        assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
     f.close()
 
 
@@ -214,11 +219,11 @@ def test_uneven2000_fp32_one_sweep():
         got_full = f.get_phi(g, 0).cpu().numpy()
         wins = _windows(ny, nx) if min(ny, nx) > 64 else [(0, ny, 0, nx)]
         for win in wins:
-            ref, margins, kw = _oracle_window(z, known, bounds, seed, 0, g, T[g], a, sweep0, 1, win, "fp32")
+            ref, expl, kw = _oracle_window(z, known, bounds, seed, 0, g, T[g], a, sweep0, 1, win, "fp32")
             got = got_full[win[0]:win[1], win[2]:win[3]]
-            n_bad, _, unexpl = explained_mismatches(got, ref, margins, kw, 1e-3)
+            n_bad, _, unexpl = mismatches(got, ref, expl, kw, 1e-3)
             assert len(unexpl) == 0, (g, win, unexpl[:4])
             total_bad += n_bad
             total_gap += int((~kw).sum())
-    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+    assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
     f.close()

@@ -13,7 +13,8 @@ import numpy as np
 import pytest
 
 from oracle import mpr as om
-from tests.gpu_util import TWO_PI, as_fp32_state, beta_of, explained_mismatches, make_field, oracle_init
+from tests.gpu_util import (TWO_PI, as_fp32_state, beta_of, chain_margins, explainable, fp32_cap, make_field,
+                            mismatches, oracle_init)
 from tests.test_gpu_fullsize import _oracle_window
 
 pytestmark = pytest.mark.gpu
@@ -38,13 +39,13 @@ def test_sweep_of_2p32_work_items_16384_grid():
             (ny - w, ny, nx // 2, nx // 2 + w)]
     bad = gaps = 0
     for win in wins:
-        ref, margins, kw = _oracle_window(z, known, bounds, seed, 0, 0, T, a, sweep0, 1, win, "fp32")
+        ref, expl, kw = _oracle_window(z, known, bounds, seed, 0, 0, T, a, sweep0, 1, win, "fp32")
         got = got_full[win[0]:win[1], win[2]:win[3]]
-        n_bad, _, unexpl = explained_mismatches(got, ref, margins, kw, 1e-3)
+        n_bad, _, unexpl = mismatches(got, ref, expl, kw, 1e-3)
         assert len(unexpl) == 0, (win, unexpl[:4])
         bad += n_bad
         gaps += int((~kw).sum())
-    assert bad <= max(3, 1e-3 * gaps), (bad, gaps)
+    assert bad <= fp32_cap(gaps), (bad, gaps)
 
 
 def test_many_chains_past_2p32_work_items():
@@ -70,7 +71,7 @@ def test_many_chains_past_2p32_work_items():
         ref, _ = om.hybrid_sweep(phi0[c][None], kn, [beta_of(T)], [TWO_PI / a], 0.5, seed, sweep0, [c], 0,
                                  margins=margins)
         got = f.get_phi(0, c).cpu().numpy()
-        _, _, unexpl = explained_mismatches(got, as_fp32_state(ref[0], known), {k: v[0] for k, v in margins.items()},
-                                            kn, 1e-3)
+        _, _, unexpl = mismatches(got, as_fp32_state(ref[0], known), explainable([chain_margins(margins, 0)]), kn,
+                                  1e-3)
         assert len(unexpl) == 0, (c, unexpl)
     f.close()

@@ -3,7 +3,8 @@
 Per-sweep parity is teacher-forced: the oracle's state is loaded into the
 library, one pass is run on both sides with the same Philox stream, and the
 angles are compared site by site (FP64: 1e-5 rad at every site; FP32:
-1e-3 rad except flips explained by a decision within 1e-4 of its threshold).
+1e-3 rad except sites within reach of an oracle decision that lay within
+1e-4 of its threshold, in the same pass: see gpu_util.explainable).
 """
 import math
 
@@ -12,8 +13,8 @@ import pytest
 
 from oracle import exact
 from oracle import mpr as om
-from tests.gpu_util import (TWO_PI, as_fp32_state, beta_of, explained_mismatches, make_field, oracle_init,
-                            random_grid)
+from tests.gpu_util import (TWO_PI, as_fp32_state, beta_of, chain_margins, explainable, fp32_cap, make_field,
+                            mismatches, oracle_init, random_grid)
 
 pytestmark = pytest.mark.gpu
 
@@ -99,16 +100,20 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, mod
         for g, (z, known, chains) in enumerate(grids):
             beta = beta_of(T)
             phi = states[g]
-            margins = {}
+            sweep_margins = []
             accs = []
             for s in range(nsw):
+                margins = {}
                 phi, acc = om.hybrid_sweep(phi, known.astype(bool), [beta] * chains, [TWO_PI / a] * chains, 0.5,
                                            seed, sweep_index + s, np.arange(chains), g, margins=margins,
                                            or_step=or_step, model=om_model, boundary=boundary)
+                sweep_margins.append(margins)
                 accs.append(acc)
             for c in range(chains):
                 got = f.get_phi(g, c).cpu().numpy()
-                results.append((T, a, g, c, got, phi[c], margins, known,
+                # this chain's decision margins of each sweep of the pass
+                expl = explainable([chain_margins(m, c) for m in sweep_margins])
+                results.append((T, a, g, c, got, phi[c], expl, known,
                                 [tr[s, k, 0] for s in range(nsw)], [x[c] for x in accs]))
                 k += 1
     return results
@@ -116,7 +121,7 @@ def _teacher_forced(dtype, tile, nsw, seed=77, sweep_index=11, or_step=True, mod
 
 @pytest.mark.parametrize("tile,nsw", [((32, 32), 1), ((16, 24), 3), ((40, 24), 2)])
 def test_teacher_forced_sweep_fp64(tile, nsw):
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp64", tile, nsw):
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced("fp64", tile, nsw):
         d = np.abs(got - ref).max()
         assert d <= 1e-5, (T, a, g, c, d)
         n_gap = int((~known.astype(bool)).sum())
@@ -127,19 +132,15 @@ def test_teacher_forced_sweep_fp64(tile, nsw):
             assert all(x == 1.0 for x in A)
 
 
-@pytest.mark.parametrize("tile,nsw", [((64, 64), 1), ((16, 16), 2)])
+@pytest.mark.parametrize("tile,nsw", [((64, 64), 1), ((16, 16), 2), ((32, 32), 4)])
 def test_teacher_forced_sweep_fp32(tile, nsw):
     total_gap = total_bad = 0
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp32", tile, nsw):
-        if nsw == 1:
-            n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
-            assert len(unexpl) == 0, (T, a, g, c, unexpl[:5], got[tuple(unexpl[0])], ref[tuple(unexpl[0])])
-        else:
-            # after several sweeps flips propagate; compare only the share of close sites
-            n_bad = int(((np.abs(got - ref) > 1e-3) & ~known.astype(bool)).sum())
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced("fp32", tile, nsw):
+        n_bad, n_expl, unexpl = mismatches(got, ref, expl, known, 1e-3)
+        assert len(unexpl) == 0, (T, a, g, c, unexpl[:5], got[tuple(unexpl[0])], ref[tuple(unexpl[0])])
         total_bad += n_bad
         total_gap += int((~known.astype(bool)).sum())
-    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+    assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
@@ -154,15 +155,15 @@ def test_teacher_forced_sweep_odd_chain_offsets(dtype):
         z, known = random_grid(ny, nx, 0.4, 300 + 10 * k, smooth=True)
         grids.append((z, known, chains))
     total_gap = total_bad = 0
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced(dtype, (32, 32), 1, grids=grids):
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced(dtype, (32, 32), 1, grids=grids):
         if dtype == "fp64":
             assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
         else:
-            n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+            n_bad, n_expl, unexpl = mismatches(got, ref, expl, known, 1e-3)
             assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
             total_bad += n_bad
             total_gap += int((~known.astype(bool)).sum())
-    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+    assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
 
 
 @pytest.mark.parametrize("threads", ["64", "128"])
@@ -170,15 +171,15 @@ def test_teacher_forced_sweep_small_workgroups(threads, monkeypatch):
     # one- and two-wave workgroups (offered by the autotuner for batches of
     # small grids): every staging, plan and update loop runs in many strides
     monkeypatch.setenv("MPR_SWEEP_THREADS", threads)
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp64", (32, 24), 2):
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced("fp64", (32, 24), 2):
         assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
     total_gap = total_bad = 0
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced("fp32", (16, 16), 1):
-        n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced("fp32", (16, 16), 1):
+        n_bad, n_expl, unexpl = mismatches(got, ref, expl, known, 1e-3)
         assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
         total_bad += n_bad
         total_gap += int((~known.astype(bool)).sum())
-    assert total_bad <= max(3, 1e-3 * total_gap), (total_bad, total_gap)
+    assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
@@ -186,13 +187,15 @@ def test_teacher_forced_sweep_without_over_relaxation(dtype):
     # Metropolis alone (MPR_NO_OR), the update the paper compares with the
     # hybrid: same tolerances as the hybrid sweep.
     total_gap = total_bad = 0
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced(dtype, (32, 24), 2, or_step=False):
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced(dtype, (32, 24), 2, or_step=False):
         if dtype == "fp64":
             assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
         else:
-            total_bad += int(((np.abs(got - ref) > 1e-3) & ~known.astype(bool)).sum())
+            n_bad, n_expl, unexpl = mismatches(got, ref, expl, known, 1e-3)
+            assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
+            total_bad += n_bad
             total_gap += int((~known.astype(bool)).sum())
-    assert total_bad <= max(3, 1e-3 * max(total_gap, 1)), (total_bad, total_gap)
+    assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
 
 
 @pytest.mark.parametrize("model", ["mpr", "gmrf"])
@@ -203,8 +206,8 @@ def test_teacher_forced_sweep_replicate_boundary(dtype, model):
     # interior of edge tiles
     total_gap = total_bad = 0
     nsw = 2 if dtype == "fp64" else 1
-    for T, a, g, c, got, ref, margins, known, A, acc in _teacher_forced(dtype, (32, 24), nsw, model=model,
-                                                                        boundary="replicate"):
+    for T, a, g, c, got, ref, expl, known, A, acc in _teacher_forced(dtype, (32, 24), nsw, model=model,
+                                                                     boundary="replicate"):
         if dtype == "fp64":
             assert np.abs(got - ref).max() <= 1e-5, (T, a, g, c)
             n_gap = int((~known.astype(bool)).sum())
@@ -212,11 +215,11 @@ def test_teacher_forced_sweep_replicate_boundary(dtype, model):
                 if n_gap:
                     assert A[s] * n_gap == pytest.approx(acc[s], abs=1e-6), (T, a, g, c, s)
         else:
-            n_bad, n_expl, unexpl = explained_mismatches(got, ref, margins, known, 1e-3)
+            n_bad, n_expl, unexpl = mismatches(got, ref, expl, known, 1e-3)
             assert len(unexpl) == 0, (T, a, g, c, unexpl[:5])
             total_bad += n_bad
             total_gap += int((~known.astype(bool)).sum())
-    assert total_bad <= max(3, 1e-3 * max(total_gap, 1)), (total_bad, total_gap)
+    assert total_bad <= fp32_cap(total_gap), (total_bad, total_gap)
 
 
 def test_replicate_boundary_changes_only_edge_updates():
@@ -765,16 +768,18 @@ def test_extreme_shapes(shape, dtype, nsw):
     f.set_chain_state(4, np.full(1, a))
     f.sweep(nsw, np.array([T]))
     got = f.get_phi(0, 0).cpu().numpy()
-    ref, margins = phi[None], {}
+    ref, sweep_margins = phi[None], []
     for s in range(nsw):
+        margins = {}
         ref, _ = om.hybrid_sweep(ref, known.astype(bool), [beta_of(T)], [TWO_PI / a], 0.5, seed, 4 + s, [0], 0,
                                  margins=margins)
+        sweep_margins.append(chain_margins(margins, 0))
     if dtype == "fp64":
         assert np.abs(got - ref[0]).max() <= 1e-5
     else:
-        n_bad, _, unexpl = explained_mismatches(got, ref[0], margins, known, 1e-3)
+        n_bad, _, unexpl = mismatches(got, ref[0], explainable(sweep_margins), known, 1e-3)
         assert len(unexpl) == 0, unexpl[:5]
-        assert n_bad <= max(3, 1e-3 * int((known == 0).sum()))
+        assert n_bad <= fp32_cap(int((known == 0).sum()))
     f.close()
 
 
