@@ -65,13 +65,12 @@ KERNEL_SOURCES = ("paper_1710_03038_amd/csrc/kernels.hip", "paper_1710_03038_amd
                   "paper_1710_03038_amd/csrc/internal.h")
 # rocprofv3 summaries whose FETCH_SIZE / WRITE_SIZE give the measured HBM
 # traffic of the sweep launches, per workload.
-PROFILES = {"grid8192x64chains": "profiles/k_sweep_fp32_grid8192x64chains.md",
-            "grid1024": "profiles/k_sweep_fp32_grid1024.md"}
+PROFILES = {"grid8192x64chains": "profiles/k_sweep_fp32_grid8192x64chains.md"}
 
 
 def bytes_per_site_sweep(elem, p):
-    """Algorithmic HBM bytes of one site in one single-pass sweep: read the
-    angle, write it back at gap sites, one mask bit."""
+    """Algorithmic HBM bytes of one site in one pass (any number of sweeps
+    in LDS): read the angle, write it back at gap sites, one mask bit."""
     return elem * (1.0 + p) + 0.125
 
 
@@ -81,7 +80,9 @@ def profiled_traffic(workload, shape, tile, single_only=False):
     there is no profile for it, the kernel sources changed since it was
     taken, or this run's launch shape or tile differs from the profiled
     one.  With single_only (every pass of the fill is one sweep), only the
-    single-sweep part of the shape (threads, persistent) has to match."""
+    single-sweep part of the shape (threads, persistent) has to match;
+    speculative two-sweep a-rule passes run at the multi-sweep workgroup
+    size, so then the whole shape has to."""
     import hashlib
     import re
     if workload not in PROFILES:
@@ -726,9 +727,11 @@ def main():
     cyc = CYC_PER_UPDATE
     achieved = useful_updates * cyc / ksec / 1e12 if kms > 0 else None
     avg_us = kms * 1e3 / kl if kl else None
-    alg_bytes = kss / kl * b_site if kl else None  # algorithmic one-pass bytes per launch
+    # algorithmic one-pass bytes per launch: each launch passes over every site once
+    sites_all = sum(int(z.size) * c for (z, _), c in zip(W["grids"], W["chains"]))
+    alg_bytes = sites_all * b_site if kl else None
     hbm_gbs = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
-    traffic = profiled_traffic(args.workload, tuple(tuned)[:4], tile_tuned or tuple(args.tile), W["n_samp"] <= 1) \
+    traffic = profiled_traffic(args.workload, tuple(tuned)[:4], tile_tuned or tuple(args.tile), False) \
         if args.boundary == "open" and "MPR_SWEEP_THREADS" not in os.environ else None
     cfg = dict(W["config"])
     cfg.update({"workload": args.workload, "boundary": args.boundary, "gap_fraction": p, "n_eq": W["n_eq"],

@@ -39,6 +39,7 @@ struct Views {
   uint16_t *plan = nullptr;
   uint32_t *plan_cum = nullptr;
   int32_t *item_grid = nullptr;  // coarse item -> grid index (SweepArgs::item_grid)
+  uint32_t *spec = nullptr;      // speculative a-rule passes: predictions [chains], then the redo list (count, chains)
 };
 
 struct Plan {
@@ -70,6 +71,11 @@ struct mpr_ctx {
   int threads = 256;           // workgroup size of the sweep kernel
   int threads1 = 256;          // ... for single-sweep passes (the a-rule's); tuned apart
   bool persist1 = false;       // single-sweep passes on persistent workgroups (k_sweep1) where they fit
+  // a-rule sweeps (adapt_every == 1) two per pass, the second with a
+  // predicted a and a per-chain redo where the prediction fails (FP32)
+  bool spec2 = false;
+  int threads2 = 256;          // workgroup size of the speculative two-sweep passes
+  bool spec_ok = false;        // FP32, a plan of two or more sweeps per pass, and MPR_SPECULATE not 0
   std::map<std::pair<int, size_t>, int64_t> resident1;  // (threads, LDS bytes) -> k_sweep1 workgroups
   size_t lds_limit = 65536;
   std::vector<double> beta_h;  // staging for per-chain inverse temperatures
@@ -88,13 +94,14 @@ struct mpr_ctx {
   bool capturing = false;
   struct GraphState {
     int64_t sweep_index, pass_no;
-    int cur, nsw_run, threads, threads1;
+    int cur, nsw_run, threads, threads1, threads2;
     int32_t n_eq, n_samp, stride;
-    bool keep_a, persist1;
+    bool keep_a, persist1, spec2;
     bool operator==(const GraphState &o) const {
       return sweep_index == o.sweep_index && pass_no == o.pass_no && cur == o.cur && nsw_run == o.nsw_run &&
-             threads == o.threads && threads1 == o.threads1 && n_eq == o.n_eq && n_samp == o.n_samp &&
-             stride == o.stride && keep_a == o.keep_a && persist1 == o.persist1;
+             threads == o.threads && threads1 == o.threads1 && threads2 == o.threads2 && n_eq == o.n_eq &&
+             n_samp == o.n_samp &&
+             stride == o.stride && keep_a == o.keep_a && persist1 == o.persist1 && spec2 == o.spec2;
     }
   };
   GraphState g_key{}, g_post{};
@@ -253,6 +260,7 @@ mpr_status make_plan(const mpr_grid *grids, int n, const mpr_params *p, bool nee
   v.plan = (uint16_t *)take(2 * (size_t)pl.plan_entries);
   v.plan_cum = (uint32_t *)take(4 * (size_t)pl.n_tiles * 2 * (pl.dmax + 2));
   v.item_grid = (int32_t *)take(4 * pl.item_grid.size());
+  v.spec = (uint32_t *)take(4 * (2 * C + 1));
   pl.bytes = off;
   return MPR_OK;
 }
@@ -281,6 +289,7 @@ void bind(Views &v, const Views &o, void *ws) {
   v.plan = rebase(o.plan, b);
   v.plan_cum = rebase(o.plan_cum, b);
   v.item_grid = rebase(o.item_grid, b);
+  v.spec = rebase(o.spec, b);
 }
 
 // LDS extent of a pass with nsw sweeps: the tile with a halo of H = 2*nsw
@@ -382,7 +391,7 @@ template <typename P> int64_t persistent_blocks(mpr_ctx *c, const SweepArgs<P> &
 
 template <typename P>
 mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace, int64_t trace_row0,
-                    uint32_t record_mask, uint32_t first_mask, bool or_step) {
+                    uint32_t record_mask, uint32_t first_mask, bool or_step, bool spec = false) {
   SweepArgs<P> A{};
   int w, h;
   size_t lds;
@@ -411,6 +420,9 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.adapt_every = c->p.adapt_every;
   A.a_targ = c->p.a_targ;
   A.k_a = c->p.k_a;
+  A.spec = spec ? 1 : 0;
+  A.pred = spec ? c->v.spec : nullptr;
+  A.redo = nullptr;
   A.src = (const P *)c->v.st[c->cur];
   A.dst = (P *)c->v.st[c->cur ^ 1];
   A.beta = c->v.beta;
@@ -433,7 +445,23 @@ mpr_status run_pass(mpr_ctx *c, int nsw, bool adapt, bool trace_e, double *trace
   A.item_grid = c->v.item_grid;
   const int64_t blocks1 = nsw == 1 && record_mask == 0 ? persistent_blocks<P>(c, A, lds) : 0;
   if (blocks1 > 0) HIP_TRY(c, launch_sweep1<P>(A, c->threads1, blocks1, lds, c->stream));
-  else HIP_TRY(c, launch_sweep<P>(A, nsw == 1 ? c->threads1 : c->threads, c->plan.n_items, lds, c->stream));
+  else HIP_TRY(c, launch_sweep<P>(A, spec ? c->threads2 : (nsw == 1 ? c->threads1 : c->threads), c->plan.n_items,
+                                  lds, c->stream));
+  if (spec) {
+    // Check sweep 0's outcome per chain, and rerun the chains it did not
+    // predict (the others' workgroups of the redo launch exit at once).
+    if constexpr (sizeof(P) == 4) {
+      const int C = c->plan.total_chains;
+      HIP_TRY(c, launch_spec_check(c->v.gd, c->n_grids, C, A.counts, A.win_now, c->p.adapt_every, c->p.a_targ,
+                                   c->v.spec, c->v.spec + C, c->stream));
+      A.redo = c->v.spec + C;
+      // a few workgroups per CU share the listed chains' items
+      const int blocks = (int)std::min<int64_t>(c->plan.n_items, 1024);
+      HIP_TRY(c, launch_sweep_redo(A, c->threads2, blocks, lds, c->stream));
+    } else {
+      return fail(c, MPR_E_STATE, "speculative passes run in FP32 only");
+    }
+  }
   if (trace_e)
     HIP_TRY(c, launch_energy_reduce(c->v.gd, c->n_grids, c->plan.total_chains, c->plan.n_items, nsw,
                                     c->v.energy_part, A.energy, c->stream));
@@ -486,9 +514,22 @@ mpr_status close_pending(mpr_ctx *c) {
   return c->p.dtype == MPR_FP64 ? close_pending<double>(c) : close_pending<float>(c);
 }
 
+// Cost of a speculative pass beyond its two sweeps: the per-chain check and
+// a redo launch whose workgroups exit at once, about 4 us each (ms).
+constexpr double kSpecOverheadMs = 0.008;
+// The a-rule's outcome flips back and forth over the first sweeps after a
+// hot start while the proposal width settles (on the 8192^2 workload the
+// chains' mean acceptance runs 0.47, 0.31, 0.24, 0.31, 0.28, ... about the
+// target 0.3), so most early predictions would fail: speculation starts at
+// this sweep index.
+constexpr int64_t kSpecFromSweep = 8;
+
 // n sweeps in passes of at most nsw_max; with the a-rule no pass crosses the
-// end of an adapt_every window, so a is constant within every pass.
-// rec_stride > 0 records every rec_stride-th sweep of this run.
+// end of an adapt_every window, so a is constant within every pass, except
+// in speculative two-sweep passes (adapt_every == 1, spec2), whose second
+// sweep runs with a predicted a and is redone per chain where the
+// prediction fails (run_pass).  rec_stride > 0 records every rec_stride-th
+// sweep of this run.
 mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *trace, int rec_stride,
                       bool or_step = true) {
   if (c->sweep_index + n >= 0xFFFFFFFFLL) return fail(c, MPR_E_STATE, "sweep counter would reach 2^32 - 1");
@@ -513,9 +554,16 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
   int64_t done = 0;
   while (done < n) {
     int64_t len = std::min<int64_t>(c->nsw_run, n - done);
+    bool spec = false;
     if (adapt) {
       const int64_t ae = c->p.adapt_every;
       len = std::min<int64_t>(len, ae - (c->sweep_index % ae));
+      // a-rule sweeps two per pass, the second speculative (see run_pass)
+      if (ae == 1 && c->spec2 && !trace_e && rec_stride == 0 && n - done >= 2 && c->nsw_max >= 2 &&
+          c->p.dtype == MPR_FP32 && c->sweep_index >= kSpecFromSweep) {
+        len = 2;
+        spec = true;
+      }
     }
     uint32_t rec = 0, first = 0;
     if (rec_stride > 0)
@@ -526,9 +574,9 @@ mpr_status run_sweeps(mpr_ctx *c, int64_t n, bool adapt, bool trace_e, double *t
           if (j + 1 == rec_stride) first |= 1u << s;
         }
       }
-    const mpr_status st = c->p.dtype == MPR_FP64
-                              ? run_pass<double>(c, (int)len, adapt, trace_e, trace, done, rec, first, or_step)
-                              : run_pass<float>(c, (int)len, adapt, trace_e, trace, done, rec, first, or_step);
+    const mpr_status st =
+        c->p.dtype == MPR_FP64 ? run_pass<double>(c, (int)len, adapt, trace_e, trace, done, rec, first, or_step)
+                               : run_pass<float>(c, (int)len, adapt, trace_e, trace, done, rec, first, or_step, spec);
     if (st != MPR_OK) return st;
     done += len;
   }
@@ -749,10 +797,18 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
     if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) c->threads = t;
   }
   c->threads1 = c->threads;
+  c->threads2 = c->threads;
   // One workgroup per item by default; mpr_autotune times the persistent
   // single-sweep kernel against it (equal or slower on the workloads
   // measured so far), mpr_set_launch_shape selects it.
   c->persist1 = false;
+  {
+    const char *env = std::getenv("MPR_SPECULATE");
+    c->spec_ok = p->dtype == MPR_FP32 && plan.nsw_max >= 2 && !(env && std::atoi(env) == 0);
+  }
+  // Speculative a-rule passes by default where the plan allows two sweeps
+  // per pass; mpr_autotune keeps them only where they are faster.
+  c->spec2 = c->spec_ok;
   c->sites_all_chains = plan.state_elems;
   auto bail = [&](mpr_status s) {
     g_thread_err = c->err;
@@ -969,8 +1025,8 @@ static mpr_status fill_sweeps(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_
 // Clears use fill kernels, never memset nodes.
 static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, int32_t stride) {
   const mpr_ctx::GraphState key{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
-                                ctx->threads1,    n_eq,         n_samp,    stride,       ctx->p.a_sample_keep != 0,
-                                ctx->persist1};
+                                ctx->threads1,    ctx->threads2, n_eq,         n_samp,    stride,       ctx->p.a_sample_keep != 0,
+                                ctx->persist1,    ctx->spec2};
   if (!ctx->graph_exec || !(key == ctx->g_key)) {
     ctx->drop_graph();
     {  // the occupancy query of persistent single-sweep passes, outside the capture
@@ -996,8 +1052,8 @@ static mpr_status fill_sweeps_graph(mpr_ctx *ctx, int32_t n_eq, int32_t n_samp, 
     ctx->capturing = false;
     ctx->stream = user;
     const mpr_ctx::GraphState post{ctx->sweep_index, ctx->pass_no, ctx->cur, ctx->nsw_run, ctx->threads,
-                                   ctx->threads1,    n_eq,         n_samp,    stride,       key.keep_a,
-                                   ctx->persist1};
+                                   ctx->threads1,    ctx->threads2, n_eq,         n_samp,    stride,       key.keep_a,
+                                   ctx->persist1,    ctx->spec2};
     // nothing has run yet: the host state goes back until the graph launches
     ctx->sweep_index = sweep0;
     ctx->pass_no = pass0;
@@ -1324,6 +1380,9 @@ struct TuneChoice {
   int nsw, threads, threads1;  // sweeps per pass and workgroup size; workgroup size of single-sweep passes
   double ms, ms1;              // their time per sweep; per sweep at one sweep per pass
   bool persist1;               // single-sweep passes on persistent workgroups
+  bool spec2;                  // a-rule sweeps in speculative two-sweep passes
+  int threads2;                // their workgroup size
+  double ms_arule;             // time per a-rule sweep (adapt_every == 1) with that choice
 };
 static std::map<std::string, TuneChoice> g_tune_cache;
 
@@ -1351,6 +1410,7 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
   HIP_TRY(ctx, hipEventCreate(&e0));
   HIP_TRY(ctx, hipEventCreate(&e1));
   double best = 1e300, best1 = 1e300;
+  std::map<int, double> two;  // per sweep in two-sweep passes, by workgroup size
   int best_nsw = ctx->nsw_run, best_thr = ctx->threads, best_thr1 = ctx->threads1;
   bool best_p1 = false;
   const int nsws[] = {1, 2, 3, 4, 6, 8, 12, 16};
@@ -1404,6 +1464,7 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
         }
         if (st != MPR_OK) break;
         const double per_sweep = ms / (double)n;
+        if (pv == 0 && nsw == 2) two[thr] = per_sweep;
         if (pv == 0 && per_sweep < best) {  // multi-sweep passes, and passes that record
           best = per_sweep;
           best_nsw = nsw;
@@ -1437,7 +1498,17 @@ static mpr_status time_launch_shapes(mpr_ctx *ctx, const double *T, int32_t tria
   ctx->threads1 = thr10;
   ctx->persist1 = persist0;
   if (st != MPR_OK) return st;
-  out = {best_nsw, best_thr, best_thr1, best, best1, best_p1};
+  // Speculative a-rule passes: two sweeps at their own best workgroup size,
+  // kept where that beats one sweep per pass, check and redo launch included.
+  int thr2 = best_thr;
+  double ms_spec = 1e300;
+  for (const auto &kv : two)
+    if (kv.second + kSpecOverheadMs / 2 < ms_spec) {
+      ms_spec = kv.second + kSpecOverheadMs / 2;
+      thr2 = kv.first;
+    }
+  const bool spec2 = ctx->spec_ok && ms_spec < best1;
+  out = {best_nsw, best_thr, best_thr1, best, best1, best_p1, spec2, thr2, spec2 ? ms_spec : best1};
   return MPR_OK;
 }
 
@@ -1470,6 +1541,8 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
   ctx->threads = ch.threads;
   ctx->threads1 = ch.threads1;
   ctx->persist1 = ch.persist1;
+  ctx->spec2 = ch.spec2 && ctx->spec_ok;
+  ctx->threads2 = ch.threads2;
   if (nsw_out) *nsw_out = ch.nsw;
   if (threads_out) *threads_out = ch.threads;
   if (threads1_out) *threads1_out = ch.threads1;
@@ -1495,6 +1568,8 @@ mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int3
   ctx->threads = threads;
   ctx->threads1 = threads1;
   ctx->persist1 = persist1 != 0;
+  ctx->spec2 = ctx->spec_ok && nsw >= 2;  // a shape of multi-sweep passes also speculates
+  ctx->threads2 = threads;
   return MPR_OK;
 }
 
@@ -1616,7 +1691,7 @@ mpr_status mpr_autotune_tile(const mpr_grid *grids, int32_t n_grids, const mpr_p
         return st;
       }
       mpr_destroy(c);
-      const double cost = n_eq * (p->adapt_every == 1 ? ch.ms1 : ch.ms) + n_samp * ch.ms;
+      const double cost = n_eq * (p->adapt_every == 1 ? ch.ms_arule : ch.ms) + n_samp * ch.ms;
       if (i == 0) default_cost = cost;
       if (cost < best_cost) {
         best_cost = cost;

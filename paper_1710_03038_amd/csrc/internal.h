@@ -68,6 +68,15 @@ struct SweepArgs {
   uint32_t record_mask, first_mask;
   int32_t adapt, adapt_every;      // a-rule (Algorithm 2, step 4.2)
   double a_targ, k_a;
+  // Speculative two-sweep a-rule pass (adapt_every == 1): sweep 1 runs with
+  // the a that the last known outcome predicts; tile 0 of each chain stores
+  // that prediction (1: acceptance below a_targ) in pred[chain] and item 0
+  // clears pred[chains], the count of the redo list that follows.  The redo
+  // launch reruns the chains listed in redo[1 .. redo[0]] with the other
+  // outcome (redo = pred + chains).
+  int32_t spec;
+  uint32_t *pred;
+  const uint32_t *redo;
   const P *src;
   P *dst;
   const double *beta;              // per chain
@@ -109,6 +118,14 @@ constexpr int kMaxTile = 188;
 // Launchers (kernels.hip).  All return the hipError_t of the launch.
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds_bytes, hipStream_t s);
+// The redo launch of a speculative pass (FP32): same arguments, redo set;
+// `blocks` workgroups share the listed chains' items.
+hipError_t launch_sweep_redo(const SweepArgs<float> &a, int threads, int blocks, size_t lds_bytes, hipStream_t s);
+// After a speculative pass: per chain, compare sweep 0's a-rule outcome with
+// the prediction; where they differ clear the chain's counts of the pass and
+// list the chain in redo[1 ..], counted in redo[0].
+hipError_t launch_spec_check(const GridDesc *g, int n_grids, int total_chains, uint32_t *counts, const double *win_in,
+                             int adapt_every, double a_targ, const uint32_t *pred, uint32_t *redo, hipStream_t s);
 template <typename P>
 hipError_t launch_pass_end(const SweepArgs<P> &a, hipStream_t s);
 // Per chain and sweep of a pass with the energy traced: the sum of the

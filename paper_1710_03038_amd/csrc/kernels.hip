@@ -189,7 +189,7 @@ __device__ __forceinline__ void split_index(int f, int npr, float inv, int &r, i
 // computes the same a from the same read-only inputs; only the caller with
 // write = true stores a, the window, the trace and the acceptance sums.
 template <typename P>
-__device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int ch, bool write) {
+__device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int ch, bool write, int *below = nullptr) {
   const PassEnd &E = A.pe;
   double a = E.a_in[ch], win = E.win_in[ch];
   double accs = 0.0;
@@ -206,7 +206,9 @@ __device__ double apply_pass_end(const SweepArgs<P> &A, const GridDesc &G, int c
       win += acc;
       const uint32_t i = E.sweep0 + (uint32_t)s;
       if ((i + 1) % (uint32_t)A.adapt_every == 0) {
-        if (win / (double)A.adapt_every < A.a_targ) a = 1.0 + (double)(i + 1) / A.k_a;
+        const bool low = win / (double)A.adapt_every < A.a_targ;
+        if (low) a = 1.0 + (double)(i + 1) / A.k_a;
+        if (below) *below = low ? 1 : 0;
         win = 0.0;
       }
     }
@@ -399,16 +401,17 @@ __device__ __forceinline__ uint32_t update_pair(const UpdateCtx<P> &U, uint32_t 
 // a thread's first interior sites stay in registers for the whole pass:
 // loaded before the first record and stored after the last, instead of a
 // read-modify-write in HBM per record.  The sums are the same, term by term.
-template <typename P, int NT, int MODEL, bool REP, bool RREG>
-__global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
+// With REDO (the redo of a speculative pass's mispredicted chains), the
+// previous pass's end is not applied a second time.
+template <typename P, int NT, int MODEL, bool REP, bool RREG, bool REDO>
+__device__ __forceinline__ void sweep_item(const SweepArgs<P> &A, const int64_t item) {
   constexpr bool QONE = MODEL == kMprQ1;
   using V2 = typename Prec<P>::V2;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_d[NT / 64];
   __shared__ uint32_t acc_lds[kMaxPass];
-  __shared__ double a_lds;
+  __shared__ double a_lds, a1_lds;
 
-  const int64_t item = xcd_item(A.n_items);
   if (item >= A.n_items) return;  // past the last item
   // The coarse index narrows the search to the grids between two entries
   // (usually one or two in a batch of large grids).
@@ -459,10 +462,25 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   // default shapes).
   if (threadIdx.x < kMaxPass) acc_lds[threadIdx.x] = 0u;
   const int gchain = G.chain_base + chain;
-  // Close the previous pass (every tile derives the same a; tile 0 records):
-  // one thread, while the staging loads are in flight.
-  if (threadIdx.x == 0) a_lds = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0) : A.a_now[gchain];
-  if (t == 0 && threadIdx.x < kMaxPass) A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
+  // Close the previous pass (every tile derives the same a; tile 0 records,
+  // except in a redo, where the first launch has recorded it): one thread,
+  // while the staging loads are in flight.  A speculative pass predicts the
+  // a-rule outcome of its sweep 0 to be that of the last known sweep
+  // (acceptance below a_targ when none is known); its redo takes the other.
+  if (threadIdx.x == 0) {
+    int below = 1;
+    const double a0 = A.pe.valid ? apply_pass_end(A, G, gchain, t == 0 && !REDO, &below) : A.a_now[gchain];
+    a_lds = a0;
+    if (A.spec) {
+      const int pb = REDO ? 1 - below : below;
+      a1_lds = pb ? 1.0 + (double)(A.sweep0 + 1) / A.k_a : a0;
+      if (!REDO && t == 0) A.pred[gchain] = (uint32_t)pb;
+      // (the redo list's count follows the predictions; k_spec_check counts
+      // from zero after this launch)
+      if (!REDO && item == 0) A.pred[A.total_chains] = 0u;
+    }
+  }
+  if (!REDO && t == 0 && threadIdx.x < kMaxPass) A.counts_clear[(int64_t)gchain * kMaxPass + threadIdx.x] = 0u;
   uint16_t *list = reinterpret_cast<uint16_t *>(ph + 2 * plane);  // past both planes
   // LDS site (ly, lx) is grid site (oy + ly, ox + lx); its colour is
   // (lx + ly + par0) & 1.
@@ -585,6 +603,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
   __syncthreads();
   const double a_d = a_lds;
   const P beta = (P)A.beta[gchain], alpha = (P)(6.28318530717958647692 / a_d);
+  const P alpha1 = A.spec ? (P)(6.28318530717958647692 / a1_lds) : alpha;  // sweep 1's
   const uint32_t k0 = A.key0, k1 = A.key1, cid = (uint32_t)chain, gid = (uint32_t)G.grid_id;
   const int iw = ix1 - x0, ih = iy1 - y0;
   const float inv_iw = 1.0f / (float)iw;
@@ -635,7 +654,7 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
       const UpdateCtx<P> U{ph + c * plane,  cs + c * plane,  cs + (c ^ 1) * plane, ph + (c ^ 1) * plane,
                            Ly,    Lx,  P2,  sbase, nx,
                            sweep, cid, gid, k0,    k1,
-                           q,     inv_q, alpha, beta, A.or_step != 0,
+                           q,     inv_q, s == 1 ? alpha1 : alpha, beta, A.or_step != 0,
                            -ox,   nx - 1 - ox, -oy, ny - 1 - oy,
                            !(c == 1 && s == A.nsw - 1),
                            x0 - ox, ix1 - 1 - ox, y0 - oy, iy1 - 1 - oy, D};
@@ -765,7 +784,34 @@ __global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
         if (!signbit(v[k])) dst[at[k]] = v[k];
     }
   }
+}
 
+template <typename P, int NT, int MODEL, bool REP, bool RREG>
+__global__ void __launch_bounds__(NT) k_sweep(const SweepArgs<P> A) {
+  sweep_item<P, NT, MODEL, REP, RREG, false>(A, xcd_item(A.n_items));
+}
+
+// The redo of a speculative pass: the workgroups share the items of the
+// chains listed by k_spec_check (none, mostly, and then they exit at once).
+template <typename P, int NT, int MODEL, bool REP>
+__global__ void __launch_bounds__(NT) k_sweep_redo(const SweepArgs<P> A) {
+  const uint32_t n_list = A.redo[0];
+  for (uint32_t k = 0; k < n_list; ++k) {
+    const int ch = (int)A.redo[1 + k];
+    int lo = 0, hi = A.n_grids - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (A.grids[mid].chain_base <= ch) lo = mid;
+      else hi = mid - 1;
+    }
+    const GridDesc &G = A.grids[lo];
+    const int64_t tiles = (int64_t)G.tiles_x * G.tiles_y;
+    const int64_t i0 = G.item_begin + (int64_t)(ch - G.chain_base) * tiles;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+      sweep_item<P, NT, MODEL, REP, false, true>(A, i0 + t);
+      __syncthreads();  // the next item restages the LDS
+    }
+  }
 }
 
 // ------------------------------------------------- persistent single sweep
@@ -1323,6 +1369,23 @@ static void launch_sweep_m(const SweepArgs<P> &a, int threads, int64_t n_items, 
   else launch_sweep_q<P, kMprQ, REP, RREG>(a, threads, n_items, lds, s);
 }
 
+template <int MODEL, bool REP>
+static void launch_redo_q(const SweepArgs<float> &a, int threads, int blocks, size_t lds, hipStream_t s) {
+  switch (threads) {
+    case 64: hipLaunchKernelGGL((k_sweep_redo<float, 64, MODEL, REP>), dim3(blocks), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sweep_redo<float, 128, MODEL, REP>), dim3(blocks), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sweep_redo<float, 256, MODEL, REP>), dim3(blocks), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep_redo<float, 512, MODEL, REP>), dim3(blocks), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep_redo<float, 1024, MODEL, REP>), dim3(blocks), dim3(1024), lds, s, a); break;
+  }
+}
+template <bool REP>
+static void launch_redo_m(const SweepArgs<float> &a, int threads, int blocks, size_t lds, hipStream_t s) {
+  if (a.gmrf) launch_redo_q<kGmrf, REP>(a, threads, blocks, lds, s);
+  else if (a.q_is_one) launch_redo_q<kMprQ1, REP>(a, threads, blocks, lds, s);
+  else launch_redo_q<kMprQ, REP>(a, threads, blocks, lds, s);
+}
+
 template <typename P>
 hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, size_t lds, hipStream_t s) {
   if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
@@ -1336,6 +1399,49 @@ hipError_t launch_sweep(const SweepArgs<P> &a, int threads, int64_t n_items, siz
   } else {
     launch_sweep_m<P, false>(a, threads, n_items, lds, s);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_redo(const SweepArgs<float> &a, int threads, int blocks, size_t lds, hipStream_t s) {
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+    return hipErrorInvalidValue;
+  if (!a.spec || !a.redo || a.record_mask || blocks < 1) return hipErrorInvalidValue;
+  if (a.rep) launch_redo_m<true>(a, threads, blocks, lds, s);
+  else launch_redo_m<false>(a, threads, blocks, lds, s);
+  return hipGetLastError();
+}
+
+// One thread per chain, after a speculative pass: sweep 0's a-rule outcome
+// (Algorithm 2, step 4.2, with the window the pass started with) against
+// the prediction the pass ran sweep 1 with.
+__global__ void __launch_bounds__(kThreads)
+    k_spec_check(const GridDesc *grids, int n_grids, int total_chains, uint32_t *counts, const double *win_in,
+                 int adapt_every, double a_targ, const uint32_t *pred, uint32_t *redo) {
+  // redo[0]: number of listed chains (cleared by the pass), redo[1 ..]: the chains
+  const int64_t ch = block_index() * kThreads + threadIdx.x;
+  if (ch >= total_chains) return;
+  int lo = 0, hi = n_grids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (grids[mid].chain_base <= ch) lo = mid;
+    else hi = mid - 1;
+  }
+  const GridDesc &G = grids[lo];
+  uint32_t *k = counts + ch * kMaxPass;
+  const double acc = G.n_gap > 0 ? (double)k[0] / (double)G.n_gap : 1.0;
+  const double win = win_in[ch] + acc;
+  const int low = win / (double)adapt_every < a_targ ? 1 : 0;
+  if (low != (int)pred[ch]) {
+    k[0] = 0u;
+    k[1] = 0u;
+    redo[1 + atomicAdd(&redo[0], 1u)] = (uint32_t)ch;
+  }
+}
+
+hipError_t launch_spec_check(const GridDesc *g, int n_grids, int total_chains, uint32_t *counts, const double *win_in,
+                             int adapt_every, double a_targ, const uint32_t *pred, uint32_t *redo, hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_check, block_grid((total_chains + kThreads - 1) / kThreads, kThreads), dim3(kThreads), 0,
+                     s, g, n_grids, total_chains, counts, win_in, adapt_every, a_targ, pred, redo);
   return hipGetLastError();
 }
 
