@@ -156,6 +156,12 @@ mpr_status mpr_init_field(mpr_ctx **ctx, const mpr_grid *grids, int32_t n_grids,
  *   MPR_NO_OR leaves out over-relaxation.
  * trace: device [n_sweeps][total chains][2] doubles or NULL; receives the
  *   acceptance ratio A and (with MPR_TRACE_E, else NaN) e of each sweep.
+ * With MPR_ADAPT, adapt_every = 1 and an FP32 context whose launch shape
+ * allows it (below), a-rule sweeps from global sweep 8 on may run two per
+ * pass: the second with the a that each chain's last outcome predicts, the
+ * pass rerun for the chains whose first-sweep outcome differs.  Results are
+ * bitwise those of one sweep per pass.  MPR_SPECULATE=0 in the environment
+ * when the context is created turns this off.
  * Asynchronous.  Errors: MPR_E_ARG, MPR_E_STATE, MPR_E_HIP.
  */
 mpr_status mpr_sweep(mpr_ctx *ctx, int32_t n_sweeps, const double *T, uint32_t flags, double *trace);
@@ -369,6 +375,9 @@ mpr_status mpr_set_chain_state(mpr_ctx *ctx, int64_t sweep_index, const double *
  * persist1_out (nullable) 1 if those passes run on persistent workgroups
  * (each looping over many items and loading the next item while it sweeps
  * the current one), 0 if on one workgroup per item; both kernels are timed.
+ * The two-sweep a-rule passes of mpr_sweep are kept (FP32) where their
+ * timed two-sweep pass, with 8 us for the check and redo launches, beats a
+ * one-sweep pass, at their own fastest workgroup size.
  * Uses the fill accumulators as scratch: do not call during a fill.
  * Synchronises the stream.
  */
@@ -383,8 +392,9 @@ mpr_status mpr_autotune(mpr_ctx *ctx, const double *T, int32_t trial_sweeps, int
  * workgroups (persist1 != 0; used where a thread's registers hold an
  * item's staged sites and plan entries, else one workgroup per item).  For
  * callers that know their shape (repeated runs, profiling, where timing
- * the candidates would sway the choice).  The shape does not change
- * results.  MPR_E_ARG if a value is out of range or the pass's LDS exceeds
+ * the candidates would sway the choice).  nsw >= 2 also runs a-rule sweeps
+ * two per pass where mpr_sweep allows it, at the multi-sweep workgroup size.
+ * The shape does not change results.  MPR_E_ARG if a value is out of range or the pass's LDS exceeds
  * the device's; the context is then unchanged.  No device work.
  */
 mpr_status mpr_set_launch_shape(mpr_ctx *ctx, int32_t nsw, int32_t threads, int32_t threads1, int32_t persist1);
